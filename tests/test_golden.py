@@ -1,0 +1,48 @@
+"""Fixtures under tests/golden/ (CPU only)."""
+
+import json
+import os
+
+import numpy as np
+
+from oracle import oracle
+from tests import pins
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_worked():
+    segs, lists = [], []
+    for line in open(os.path.join(GOLDEN, "worked_segments.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        head, tail = line.split(":")
+        segs.append([int(v) for v in head.split()])
+        lists.append([tuple(int(c) for c in p.split(",")) for p in tail.split()])
+    return np.array(segs, dtype=np.int32), lists
+
+
+def test_worked_segments_by_exact_search():
+    """Each stored list equals the Fraction nearest-centre construction."""
+    segs, lists = load_worked()
+    for s, lst in zip(segs, lists):
+        assert pins.fraction_list(s) == lst
+
+
+def test_worked_segments_match_oracle():
+    segs, lists = load_worked()
+    got = oracle.voxel_list(segs)
+    flat = [p for lst in lists for p in lst]
+    assert [tuple(int(c) for c in v) for v in got] == flat
+
+
+def test_paper_table4_throughput_column():
+    """Table 4's MVox/s row is 1e9 voxels over the printed time, to the
+    printed precision, except the GTX 1050 entry (77.2 printed, 76.9 derived)."""
+    t = json.load(open(os.path.join(GOLDEN, "paper_tables.json")))["table4_1024_arbitrary_1gvox"]
+    derived = [1e9 / (ms * 1e-3) / 1e6 for ms in t["time_ms"]]
+    for i, (d, p) in enumerate(zip(derived, t["mvox_per_s"])):
+        if i == 2:
+            assert abs(d - p) > 0.1
+        else:
+            assert abs(d - p) <= 0.11
