@@ -1,0 +1,193 @@
+/*
+ * vox.h - C ABI of the MI355X (gfx950) parametric segment voxelizer.
+ *
+ * The operation (arXiv 2009.09500, Section 3): a segment with start point S
+ * and end point E is decomposed into the voxels that contain the points
+ *     G_k = S + W k,  W = (E - S) / N,  k = 0, 1, ..., N      (eq. (2)-(3))
+ * emitted in order as the array V^(k) (algorithm of Fig. 3).  This library
+ * fixes what the paper leaves open:
+ *   N            = max(|dx|, |dy|, |dz|)  (Chebyshev length; eq. (1) of the
+ *                  paper uses the integer part of the Euclidean length),
+ *   k            = 0..N, so a segment has N + 1 voxels and both end points,
+ *   voxel of G_k = floor(G_k + 1/2) per axis (centres on integers, ties
+ *                  rounded up), evaluated exactly in integers as
+ *                  P0_a + floor((2 k d_a + N) / (2 N)),
+ *   S == E       gives the single voxel S.
+ * Many segments are handled in one call, as the paper's multi-segment
+ * experiments do in one kernel call (Section 4 and Section 5, experiment 3).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (HBM of the current HIP device),
+ *     h_* are host pointers.  The caller allocates and frees all of them,
+ *     including the workspace d_work; the library keeps no pointer after a
+ *     call returns and allocates no device memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call is stream-ordered and asynchronous unless it says it
+ *     synchronises.
+ *   - Argument errors detectable on the host are returned at once and launch
+ *     nothing.  Errors that depend on device data (end points out of range,
+ *     list capacity exceeded) are recorded in the device status word, the
+ *     first int32 of d_work, as a vox_status code; vox_read_status() fetches
+ *     it.  Such errors never cause an out-of-bounds write: the affected
+ *     output is left unwritten, as each entry point states.
+ *   - Entry points are re-entrant.  Calls that share a workspace must be
+ *     ordered (same stream, or synchronised).  vox_last_error() is
+ *     thread-local.
+ */
+#ifndef VOX_H
+#define VOX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VOX_ABI_VERSION 1
+
+/* One segment: start point (x0,y0,z0) = S, end point (x1,y1,z1) = E.
+ * Arrays of segments are dense, 24 bytes per segment, 4-byte aligned. */
+typedef struct vox_segment {
+    int32_t x0, y0, z0, x1, y1, z1;
+} vox_segment;
+
+typedef enum vox_status {
+    VOX_OK = 0,
+    VOX_ERR_INVALID_ARGUMENT = 1, /* bad pointer, size or flag            */
+    VOX_ERR_OUT_OF_RANGE = 2,     /* an end point outside the output range */
+    VOX_ERR_CAPACITY = 3,         /* voxel list larger than the capacity   */
+    VOX_ERR_DEVICE = 4,           /* a HIP runtime call failed             */
+    VOX_ERR_WORKSPACE = 5         /* workspace missing or too small        */
+} vox_status;
+
+/* Grid flag: zero the whole bit-volume before setting voxels.  Without it
+ * the voxels are ORed into the volume's current contents. */
+#define VOX_GRID_CLEAR 1u
+
+/* ---------------------------------------------------------------- lists */
+
+/* Workspace bytes for vox_segments_to_list with n segments and a voxel
+ * buffer of `capacity` voxels (capacity may be 0 for a size query). */
+size_t vox_list_workspace_bytes(int64_t n, int64_t capacity);
+
+/* Per-segment voxel lists (Fig. 3, output "array of voxels V^(k)").
+ *
+ *   d_segs     [n] segments, device.
+ *   n          number of segments, >= 0.
+ *   d_offsets  [n+1] int64 out, device: d_offsets[i] = sum_{j<i} (N_j + 1),
+ *              d_offsets[n] = total voxel count.  Always written.
+ *   d_voxels   [capacity][3] int16 out, device: voxel k of segment i is row
+ *              d_offsets[i] + k, columns x,y,z; segments in input order,
+ *              voxels from S to E.  NULL = size query (offsets only).
+ *   capacity   rows available in d_voxels (>= 0).
+ *   h_total    optional host out.  If non-NULL the call synchronises the
+ *              stream once, stores the total, and returns
+ *              VOX_ERR_OUT_OF_RANGE / VOX_ERR_CAPACITY from the device
+ *              status instead of VOX_OK.
+ *   d_work     workspace, >= vox_list_workspace_bytes(n, capacity) bytes,
+ *              256-byte aligned.
+ *
+ * Device-checked: every coordinate must lie in [-32768, 32767] (int16
+ * output) and total <= capacity; otherwise the status word is set and no
+ * voxel row is written (offsets still are). */
+vox_status vox_segments_to_list(const vox_segment *d_segs, int64_t n,
+                                int64_t *d_offsets, int16_t *d_voxels,
+                                int64_t capacity, int64_t *h_total,
+                                void *d_work, size_t work_bytes, void *stream);
+
+/* ----------------------------------------------------------------- grids */
+
+/* Workspace bytes for vox_segments_to_grid with n segments and the given
+ * volume (the bound covers the worst case of every segment crossing the
+ * whole volume). */
+size_t vox_grid_workspace_bytes(int64_t n, int32_t dim_x, int32_t dim_y, int32_t dim_z);
+
+/* Packed occupancy bit-volume of all voxels of all segments (the "scene
+ * voxel array" that the generated primitives are assembled into, Section 2
+ * and Section 3 around Fig. 1).
+ *
+ *   dim_x, dim_y, dim_z  volume size in voxels, each in [1, 2^20] and
+ *              dim_x*dim_y*dim_z <= 2^38.
+ *   d_grid     [ceil(dim_x*dim_y*dim_z / 32)] uint32, device, in/out.
+ *              Voxel (x,y,z) is bit b = (z*dim_y + y)*dim_x + x, stored in
+ *              word b / 32 at bit b % 32 (least significant bit first).
+ *   d_counts   optional [n] int32 out, device: N_i + 1.
+ *   flags      VOX_GRID_CLEAR or 0.
+ *   d_work     workspace, >= vox_grid_workspace_bytes(...) bytes, 256-byte
+ *              aligned.
+ *
+ * Device-checked: both end points of a segment must lie inside the volume
+ * (then every voxel does, as each coordinate is rounded from a value between
+ * two in-range integers).  A segment that fails sets VOX_ERR_OUT_OF_RANGE
+ * and contributes no voxel; the others are still written. */
+vox_status vox_segments_to_grid(const vox_segment *d_segs, int64_t n,
+                                int32_t dim_x, int32_t dim_y, int32_t dim_z,
+                                uint32_t *d_grid, int32_t *d_counts, uint32_t flags,
+                                void *d_work, size_t work_bytes, void *stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* One scene of a batch: its own segments and its own bit-volume, with the
+ * meaning of the vox_segments_to_grid arguments of the same names. */
+typedef struct vox_scene {
+    const vox_segment *segs; /* device */
+    int64_t n;
+    int32_t dim_x, dim_y, dim_z;
+    uint32_t flags;          /* VOX_GRID_CLEAR or 0 */
+    uint32_t *grid;          /* device */
+    int32_t *counts;         /* device, optional (NULL) */
+} vox_scene;
+
+/* Host-side planning of a batch: from the host array h_scenes[n_scenes]
+ * (whose pointers are device pointers) build the device descriptor table
+ * image in h_table (host memory, h_table_bytes long) and report the sizes
+ * the launch needs.  The caller copies h_table to device memory d_table
+ * (any way it likes) before vox_batch_scenes runs.  Pass h_table = NULL to
+ * query *table_bytes and *work_bytes only.  No device call is made. */
+vox_status vox_batch_plan(const vox_scene *h_scenes, int32_t n_scenes,
+                          void *h_table, size_t h_table_bytes,
+                          size_t *table_bytes, size_t *work_bytes);
+
+/* All scenes of a planned batch in one persistent, work-stealing launch
+ * sequence (the paper's advice to cut the number of kernel calls and load
+ * the GPU with many segments at once, Section 5, conclusions 3 and 4).
+ * Every scene's grid (and counts) ends up exactly as a separate
+ * vox_segments_to_grid call would leave it.
+ *
+ *   d_table    device copy of the table built by vox_batch_plan.
+ *   d_work     workspace, >= the work_bytes reported by vox_batch_plan.
+ *   max_scenes, max_segments, max_bricks
+ *              launch-shape bounds: the call is valid for any table whose
+ *              scene count, total segment count and total brick count
+ *              (reported in the table header) stay within them.
+ *
+ * The call reads nothing on the host, synchronises nothing and allocates
+ * nothing, so it can be captured into a HIP graph once and replayed after
+ * the caller rewrites d_table (same address) with another batch that fits
+ * the bounds and the workspace. */
+vox_status vox_batch_scenes(const void *d_table, int32_t max_scenes,
+                            int64_t max_segments, int64_t max_bricks,
+                            void *d_work, size_t work_bytes, void *stream);
+
+/* -------------------------------------------------------------- utilities */
+
+/* Synchronises `stream`, then copies the device status word of d_work into
+ * *h_status (a vox_status value).  Returns VOX_ERR_DEVICE if a HIP call
+ * fails. */
+vox_status vox_read_status(const void *d_work, int32_t *h_status, void *stream);
+
+/* Static description of a status code. */
+const char *vox_status_string(vox_status status);
+
+/* Message of the last host-side error on the calling thread ("" if none). */
+const char *vox_last_error(void);
+
+/* VOX_ABI_VERSION of the built library. */
+int vox_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOX_H */

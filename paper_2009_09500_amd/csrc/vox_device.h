@@ -1,0 +1,156 @@
+// Device-side building blocks shared by the voxelization kernels (gfx950,
+// wave64).  Internal to the HIP library; not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vox {
+
+constexpr int kWave = 64;
+
+// One segment as read from the caller's AoS array: start point and end
+// point.  Loaded with three 8-byte loads when the array is 8-byte aligned
+// (every torch allocation is), else six 4-byte loads.
+struct Seg {
+    int32_t p0[3];
+    int32_t p1[3];
+};
+
+template <bool kAligned8>
+__device__ __forceinline__ Seg load_seg(const int32_t* __restrict__ segs, int64_t i) {
+    Seg s;
+    const int32_t* p = segs + 6 * i;
+    if constexpr (kAligned8) {
+        const int2* q = reinterpret_cast<const int2*>(p);
+        int2 a = q[0], b = q[1], c = q[2];
+        s.p0[0] = a.x; s.p0[1] = a.y; s.p0[2] = b.x;
+        s.p1[0] = b.y; s.p1[1] = c.x; s.p1[2] = c.y;
+    } else {
+        s.p0[0] = p[0]; s.p0[1] = p[1]; s.p0[2] = p[2];
+        s.p1[0] = p[3]; s.p1[1] = p[4]; s.p1[2] = p[5];
+    }
+    return s;
+}
+
+// Chebyshev length N = max_a |p1_a - p0_a| in 64 bits (int32 inputs may
+// differ by up to 2^32 - 1).
+__device__ __forceinline__ int64_t seg_length(const Seg& s) {
+    int64_t n = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int64_t d = (int64_t)s.p1[a] - (int64_t)s.p0[a];
+        d = d < 0 ? -d : d;
+        n = d > n ? d : n;
+    }
+    return n;
+}
+
+__device__ __forceinline__ bool in_int16(const Seg& s) {
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ok &= (s.p0[a] >= -32768) & (s.p0[a] <= 32767) & (s.p1[a] >= -32768) & (s.p1[a] <= 32767);
+    }
+    return ok;
+}
+
+// Exact incremental evaluation of voxel k of a segment along one axis.
+//
+// With N the Chebyshev length, d = p1 - p0 and a = |d|, the coordinate is
+//   d >= 0:  p0 + floor((2 k a + N) / 2N)
+//   d <  0:  p0 - floor((2 k a + N - 1) / 2N)
+// (the second is the first with d negated and floor(x + 1/2) mirrored).
+// Keeping q = numerator / 2N and r = numerator mod 2N, k -> k + 1 adds 2a
+// to the numerator; as 2a <= 2N the quotient grows by at most one:
+//   r += 2a;  if (r >= 2N) { r -= 2N; ++q; }
+// This is Bresenham's error term; it reproduces the division exactly.
+struct AxisStep {
+    uint32_t q, r, two_a;
+};
+
+// Quotient and remainder of (2 k a + N - neg) / 2N for N >= 1.  32-bit when
+// the numerator fits (N <= 32767, as for every int16 coordinate pair except
+// the extreme ones), else 64-bit.
+__device__ __forceinline__ AxisStep axis_init(uint32_t a, uint32_t neg, uint32_t N, uint32_t k) {
+    AxisStep st;
+    st.two_a = 2u * a;
+    uint32_t two_n = 2u * N;
+    if (N <= 32767u) {
+        uint32_t num = 2u * k * a + N - neg;
+        st.q = num / two_n;
+        st.r = num - st.q * two_n;
+    } else {
+        uint64_t num = 2ull * k * a + N - neg;
+        uint64_t q = num / two_n;
+        st.q = (uint32_t)q;
+        st.r = (uint32_t)(num - q * two_n);
+    }
+    return st;
+}
+
+__device__ __forceinline__ void axis_step(AxisStep& st, uint32_t two_n) {
+    st.r += st.two_a;
+    bool c = st.r >= two_n;
+    st.r = c ? st.r - two_n : st.r;
+    st.q += c ? 1u : 0u;
+}
+
+// ------------------------------------------------------------ block scans
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Exclusive prefix sum over the block (one value per thread, thread order).
+// `lds` needs kBlock/64 entries; returns the block total in `total`.
+template <int kBlock, typename T>
+__device__ __forceinline__ T block_exclusive_sum(T v, T* lds, T& total) {
+    constexpr int kWaves = kBlock / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    T incl = wave_inclusive_sum(v);
+    if (lane == kWave - 1) lds[w] = incl;
+    __syncthreads();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        T x = lds[i];
+        pre += (i < w) ? x : T(0);
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + incl - v;
+}
+
+template <int kBlock, typename T>
+__device__ __forceinline__ T block_sum(T v, T* lds) {
+    constexpr int kWaves = kBlock / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    v = wave_sum(v);
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    T tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) tot += lds[i];
+    __syncthreads();
+    return tot;
+}
+
+}  // namespace vox

@@ -1,0 +1,108 @@
+// Bit-volume output, direct form: every voxel is ORed into its grid word
+// with a device-scope atomic.  Correct for any volume shape; used for
+// volumes the brick path does not cover.
+#include "vox_device.h"
+#include "vox_internal.h"
+
+namespace vox {
+
+constexpr int kGridBlock = 256;
+
+__global__ void k_grid_init(int32_t* status) {
+    if (threadIdx.x == 0) *status = 0;
+}
+
+__global__ __launch_bounds__(kGridBlock) void k_grid_clear(uint32_t* __restrict__ grid, int64_t nwords) {
+    const int64_t stride = (int64_t)gridDim.x * kGridBlock;
+    const int64_t n4 = nwords / 4;
+    uint4* g4 = reinterpret_cast<uint4*>(grid);
+    for (int64_t i = (int64_t)blockIdx.x * kGridBlock + threadIdx.x; i < n4; i += stride)
+        g4[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = n4 * 4 + (int64_t)blockIdx.x * kGridBlock + threadIdx.x; i < nwords; i += stride)
+        grid[i] = 0u;
+}
+
+// Thread per segment: range check, count, then every voxel of eq. (3) by
+// exact stepping, each ORed into the grid.
+template <bool kAligned8>
+__global__ __launch_bounds__(kGridBlock) void k_grid_direct(const int32_t* __restrict__ segs, int64_t n,
+                                                            int32_t dx, int32_t dy, int32_t dz,
+                                                            uint32_t* __restrict__ grid,
+                                                            int32_t* __restrict__ counts,
+                                                            int32_t* __restrict__ status) {
+    const int64_t i = (int64_t)blockIdx.x * kGridBlock + threadIdx.x;
+    if (i >= n) return;
+    Seg g = load_seg<kAligned8>(segs, i);
+    const int64_t N64 = seg_length(g);
+    if (counts) counts[i] = (int32_t)(N64 + 1 > 0x7FFFFFFFll ? 0x7FFFFFFFll : N64 + 1);
+    const int32_t dim[3] = {dx, dy, dz};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        ok &= (g.p0[a] >= 0) & (g.p0[a] < dim[a]) & (g.p1[a] >= 0) & (g.p1[a] < dim[a]);
+    if (!ok) {
+        atomicOr(status, kStatusOutOfRange);
+        return;
+    }
+    const uint32_t N = (uint32_t)N64;  // < 2^20 inside the volume
+    uint32_t neg[3];
+    AxisStep st[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int32_t d = g.p1[a] - g.p0[a];
+        neg[a] = d < 0;
+        st[a].two_a = 2u * (uint32_t)(d < 0 ? -d : d);
+        st[a].q = 0u;
+        st[a].r = N ? N - neg[a] : 0u;
+    }
+    const uint32_t two_n = 2u * N;
+    for (uint32_t k = 0; k <= N; ++k) {
+        int64_t c[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int32_t q = (int32_t)st[a].q;
+            c[a] = g.p0[a] + (neg[a] ? -q : q);
+            axis_step(st[a], two_n);
+        }
+        const uint64_t b = ((uint64_t)c[2] * (uint64_t)dy + (uint64_t)c[1]) * (uint64_t)dx + (uint64_t)c[0];
+        atomicOr(grid + (b >> 5), 1u << (uint32_t)(b & 31u));
+    }
+}
+
+size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz) {
+    (void)n; (void)dx; (void)dy; (void)dz;
+    return kAlign;
+}
+
+GridWork grid_workspace(void* d_work, int64_t n, int32_t dx, int32_t dy, int32_t dz) {
+    (void)n; (void)dx; (void)dy; (void)dz;
+    GridWork w;
+    w.status = static_cast<int32_t*>(d_work);
+    return w;
+}
+
+hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx, int32_t dy,
+                       int32_t dz, uint32_t* grid, int32_t* counts, uint32_t flags,
+                       const GridWork& w, hipStream_t stream) {
+    k_grid_init<<<1, 64, 0, stream>>>(w.status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nwords = ((int64_t)dx * dy * dz + 31) / 32;
+    if (flags & 1u) {
+        int64_t blocks = (nwords / 4 + kGridBlock - 1) / kGridBlock;
+        if (blocks > 8192) blocks = 8192;
+        if (blocks < 1) blocks = 1;
+        k_grid_clear<<<dim3((unsigned)blocks), kGridBlock, 0, stream>>>(grid, nwords);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n == 0) return hipSuccess;
+    dim3 gridDim((unsigned)((n + kGridBlock - 1) / kGridBlock));
+    if (aligned8)
+        k_grid_direct<true><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts, w.status);
+    else
+        k_grid_direct<false><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts, w.status);
+    return hipGetLastError();
+}
+
+}  // namespace vox

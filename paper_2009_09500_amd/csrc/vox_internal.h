@@ -1,0 +1,66 @@
+// Host-side launch interface between the C ABI layer (vox_api.cpp) and the
+// kernel files.  Internal; not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace vox {
+
+// Device status word bits (first int32 of every workspace).  The host maps
+// the set bits onto a vox_status code.
+constexpr int32_t kStatusOutOfRange = 1;
+constexpr int32_t kStatusCapacity = 2;
+
+// Workspace sections are 256-byte aligned.
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ------------------------------------------------------------- list path
+// Segment blocks of the count/offset kernels and voxel tiles of the list
+// kernel.
+constexpr int kCountBlock = 256;
+constexpr int kCountPerThread = 4;
+constexpr int64_t kSegsPerCountBlock = (int64_t)kCountBlock * kCountPerThread;
+constexpr int kListBlock = 256;
+constexpr int kListPerThread = 4;
+constexpr int64_t kListTile = (int64_t)kListBlock * kListPerThread;
+
+struct ListWork {
+    int32_t* status;       // [1]
+    int64_t* total;        // [1]
+    int64_t* block_sums;   // [nb]  block totals, then block prefixes
+    int32_t* block_flags;  // [nb]
+    uint32_t* counts;      // [n]
+    int32_t* tile_seg;     // [ntiles + 1]
+    int64_t nb;
+    int64_t ntiles;
+};
+
+size_t list_workspace_bytes(int64_t n, int64_t capacity);
+ListWork list_workspace(void* d_work, int64_t n, int64_t capacity);
+
+hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
+                             hipStream_t stream);
+hipError_t launch_list_scan(const ListWork& w, int64_t n, int64_t* offsets, int64_t capacity,
+                            bool want_voxels, hipStream_t stream);
+hipError_t launch_list_offsets(int64_t n, int64_t* offsets, const ListWork& w, int64_t capacity,
+                               bool want_voxels, hipStream_t stream);
+hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
+                              const ListWork& w, int16_t* voxels, int64_t capacity,
+                              int64_t tiles_to_launch, hipStream_t stream);
+
+// ------------------------------------------------------------- grid path
+struct GridWork {
+    int32_t* status;  // [1]
+};
+
+size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz);
+GridWork grid_workspace(void* d_work, int64_t n, int32_t dx, int32_t dy, int32_t dz);
+
+hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx, int32_t dy,
+                       int32_t dz, uint32_t* grid, int32_t* counts, uint32_t flags,
+                       const GridWork& w, hipStream_t stream);
+
+}  // namespace vox

@@ -1,0 +1,342 @@
+// Voxel lists: count -> scan -> offsets + tile map -> lane-per-voxel tiles.
+//
+// Steps of the path (arXiv 2009.09500, Section 4 lists them as host
+// preprocessing followed by one kernel; here all of them run on the GPU):
+//   1. count   N_i + 1 per segment ("the voxels number in the segment",
+//              host step 1 of Section 4), int16 range check;
+//   2. scan    exclusive prefix sum of the counts -> d_offsets (replaces the
+//              paper's padding of every segment to N_max, Section 5);
+//   3. tiles   each tile of kListTile consecutive output voxels learns the
+//              segment holding its first voxel;
+//   4. voxels  every lane computes kListPerThread consecutive voxels of the
+//              flat output with the exact stepping of eq. (3), stages them
+//              in LDS and the block writes the tile with 16-byte stores.
+#include "vox_device.h"
+#include "vox_internal.h"
+
+namespace vox {
+
+// ------------------------------------------------------------------ count
+
+template <bool kAligned8>
+__global__ __launch_bounds__(kCountBlock) void k_list_count(const int32_t* __restrict__ segs,
+                                                            int64_t n, uint32_t* __restrict__ counts,
+                                                            int64_t* __restrict__ block_sums,
+                                                            int32_t* __restrict__ block_flags) {
+    __shared__ int64_t red[kCountBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kSegsPerCountBlock;
+    int64_t sum = 0;
+    int32_t flag = 0;
+#pragma unroll
+    for (int s = 0; s < kCountPerThread; ++s) {
+        int64_t i = base + (int64_t)s * kCountBlock + threadIdx.x;
+        if (i < n) {
+            Seg g = load_seg<kAligned8>(segs, i);
+            int64_t c = seg_length(g) + 1;
+            flag |= in_int16(g) ? 0 : kStatusOutOfRange;
+            // Counts above 2^32 - 1 only arise from out-of-range input.
+            counts[i] = c > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)c;
+            sum += c > 0xFFFFFFFFll ? 0xFFFFFFFFll : c;
+        }
+    }
+    sum = block_sum<kCountBlock>(sum, red);
+    int32_t f = (int32_t)block_sum<kCountBlock>((int64_t)flag, red);
+    if (threadIdx.x == 0) {
+        block_sums[blockIdx.x] = sum;
+        block_flags[blockIdx.x] = f ? kStatusOutOfRange : 0;
+    }
+}
+
+// ------------------------------------------------------- scan of partials
+
+constexpr int kScanBlock = 1024;
+
+// One block: exclusive scan of the per-block sums in place, the total into
+// offsets[n] and *total, and the status word (out-of-range flags of the
+// count blocks, capacity).
+__global__ __launch_bounds__(kScanBlock) void k_list_scan(int64_t* __restrict__ block_sums,
+                                                          const int32_t* __restrict__ block_flags,
+                                                          int64_t nb, int64_t* __restrict__ offsets,
+                                                          int64_t n, int64_t* __restrict__ total,
+                                                          int32_t* __restrict__ status,
+                                                          int64_t capacity, int want_voxels) {
+    __shared__ int64_t lds[kScanBlock / kWave];
+    int64_t carry = 0;
+    int64_t flags = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += kScanBlock) {
+        int64_t i = c0 + threadIdx.x;
+        int64_t v = i < nb ? block_sums[i] : 0;
+        flags |= i < nb ? block_flags[i] : 0;
+        int64_t tot;
+        int64_t ex = block_exclusive_sum<kScanBlock>(v, lds, tot);
+        if (i < nb) block_sums[i] = carry + ex;
+        carry += tot;
+    }
+    int32_t f = (int32_t)block_sum<kScanBlock>(flags, lds);
+    if (threadIdx.x == 0) {
+        offsets[n] = carry;
+        *total = carry;
+        int32_t st = f ? kStatusOutOfRange : 0;
+        if (want_voxels && carry > capacity) st |= kStatusCapacity;
+        *status = st;
+    }
+}
+
+// --------------------------------------------------- offsets and tile map
+
+// Same segment blocks as the count kernel.  Each sub-tile of kCountBlock
+// consecutive segments is scanned by the block; every segment then records
+// itself as the first segment of each output tile whose first voxel it
+// holds.
+__global__ __launch_bounds__(kCountBlock) void k_list_offsets(
+    int64_t n, const uint32_t* __restrict__ counts, const int64_t* __restrict__ block_prefix,
+    int64_t* __restrict__ offsets, int32_t* __restrict__ tile_seg, int64_t tile_limit,
+    const int64_t* __restrict__ total, const int32_t* __restrict__ status) {
+    __shared__ int64_t lds[kCountBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kSegsPerCountBlock;
+    int64_t carry = block_prefix[blockIdx.x];
+    // Tiles are only needed when voxels will be written.
+    const bool tiles = tile_limit > 0 && *status == 0;
+    const int64_t tot = *total;
+    const int64_t ntiles = tot < tile_limit * kListTile ? (tot + kListTile - 1) / kListTile : tile_limit;
+    for (int s = 0; s < kCountPerThread; ++s) {
+        int64_t i = base + (int64_t)s * kCountBlock + threadIdx.x;
+        int64_t c = i < n ? (int64_t)counts[i] : 0;
+        int64_t sub;
+        int64_t ex = block_exclusive_sum<kCountBlock>(c, lds, sub);
+        int64_t off = carry + ex;
+        if (i < n) {
+            offsets[i] = off;
+            if (tiles) {
+                int64_t t0 = (off + kListTile - 1) / kListTile;
+                int64_t t1 = (off + c - 1) / kListTile;  // inclusive
+                if (t1 >= ntiles) t1 = ntiles - 1;
+                for (int64_t t = t0; t <= t1; ++t) tile_seg[t] = (int32_t)i;
+            }
+        }
+        carry += sub;
+    }
+}
+
+// ------------------------------------------------------------ voxel tiles
+
+// One tile = kListTile consecutive output voxels [j0, j1).  Its segments
+// s0..s1 are staged in LDS as packed int16 end points with their offsets
+// relative to j0; lane t computes voxels j0 + t*P .. j0 + t*P + P - 1
+// (P = kListPerThread), stepping exactly from one voxel to the next and
+// moving to the following segment when the voxel index reaches its offset.
+struct PackedSeg {
+    int16_t p0[3];
+    int16_t p1[3];
+};
+
+template <bool kAligned8>
+__global__ __launch_bounds__(kListBlock) void k_list_voxels(
+    const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
+    const int32_t* __restrict__ tile_seg, int16_t* __restrict__ voxels,
+    const int64_t* __restrict__ total_p, const int32_t* __restrict__ status) {
+    constexpr int kMaxSegs = (int)kListTile + 1;
+    __shared__ PackedSeg sseg[kMaxSegs];
+    __shared__ int32_t srel[kMaxSegs + 1];
+    __shared__ uint32_t stage[kListTile * 3 / 2];
+
+    if (*status != 0) return;
+    const int64_t total = *total_p;
+    const int64_t tile = blockIdx.x;
+    const int64_t j0 = tile * kListTile;
+    if (j0 >= total) return;
+    const int64_t j1 = j0 + kListTile < total ? j0 + kListTile : total;
+    const int64_t ntiles = (total + kListTile - 1) / kListTile;
+    const int32_t s0 = tile_seg[tile];
+    int32_t s1 = tile + 1 < ntiles ? tile_seg[tile + 1] : (int32_t)(n - 1);
+    const int nseg = s1 - s0 + 1;  // <= kListTile + 1
+
+    for (int s = threadIdx.x; s < nseg; s += kListBlock) {
+        Seg g = load_seg<kAligned8>(segs, (int64_t)s0 + s);
+        PackedSeg p;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p.p0[a] = (int16_t)g.p0[a];
+            p.p1[a] = (int16_t)g.p1[a];
+        }
+        sseg[s] = p;
+    }
+    for (int s = threadIdx.x; s <= nseg; s += kListBlock) {
+        int64_t o = (int64_t)s0 + s <= n ? offsets[(int64_t)s0 + s] : total;
+        int64_t rel = o - j0;
+        // A tile's own segments start within [-65535, kListTile].
+        rel = rel < -(1ll << 30) ? -(1ll << 30) : (rel > (1ll << 30) ? (1ll << 30) : rel);
+        srel[s] = (int32_t)rel;
+    }
+    __syncthreads();
+
+    const int first = threadIdx.x * kListPerThread;  // tile-relative voxel
+    const int count = (int)(j1 - j0);
+    if (first < count) {
+        // Segment of the first voxel: largest s with srel[s] <= first.
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (srel[mid] <= first) lo = mid; else hi = mid - 1;
+        }
+        int s = lo;
+        int next = srel[s + 1];
+        PackedSeg p = sseg[s];
+        uint32_t neg[3], a[3];
+        uint32_t N = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            int32_t d = (int32_t)p.p1[ax] - (int32_t)p.p0[ax];
+            neg[ax] = d < 0;
+            a[ax] = (uint32_t)(d < 0 ? -d : d);
+            N = a[ax] > N ? a[ax] : N;
+        }
+        uint32_t k = (uint32_t)(first - srel[s]);
+        AxisStep st[3];
+        if (N == 0) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) st[ax] = AxisStep{0u, 0u, 0u};
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) st[ax] = axis_init(a[ax], neg[ax], N, k);
+        }
+        uint32_t two_n = 2u * N;
+        int16_t out[kListPerThread * 3];
+#pragma unroll
+        for (int v = 0; v < kListPerThread; ++v) {
+            const int j = first + v;
+            if (j >= next && j < count) {
+                // First voxel of the following segment: k = 0.
+                ++s;
+                next = srel[s + 1];
+                p = sseg[s];
+                N = 0;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    int32_t d = (int32_t)p.p1[ax] - (int32_t)p.p0[ax];
+                    neg[ax] = d < 0;
+                    a[ax] = (uint32_t)(d < 0 ? -d : d);
+                    N = a[ax] > N ? a[ax] : N;
+                }
+                two_n = 2u * N;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    st[ax].q = 0u;
+                    st[ax].r = N - (N ? neg[ax] : 0u);
+                    st[ax].two_a = 2u * a[ax];
+                }
+            }
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                int32_t q = (int32_t)st[ax].q;
+                out[v * 3 + ax] = (int16_t)((int32_t)p.p0[ax] + (neg[ax] ? -q : q));
+                axis_step(st[ax], two_n);
+            }
+        }
+        // Stage: lane t owns 3*P int16 = 3*P/2 words at word 3*P/2*t.
+        uint32_t* dst = stage + (kListPerThread * 3 / 2) * threadIdx.x;
+#pragma unroll
+        for (int w = 0; w < kListPerThread * 3 / 2; ++w)
+            dst[w] = (uint32_t)(uint16_t)out[2 * w] | ((uint32_t)(uint16_t)out[2 * w + 1] << 16);
+    }
+    __syncthreads();
+
+    // Write the tile: bytes [6*j0, 6*j1).  j0 is a multiple of kListTile, so
+    // the start is 16-byte aligned whenever `voxels` is.
+    const int64_t bytes = 6 * (j1 - j0);
+    uint8_t* gbase = reinterpret_cast<uint8_t*>(voxels) + 6 * j0;
+    const int64_t n16 = bytes / 16;
+    const uint4* src = reinterpret_cast<const uint4*>(stage);
+    uint4* gdst = reinterpret_cast<uint4*>(gbase);
+    for (int64_t c = threadIdx.x; c < n16; c += kListBlock) gdst[c] = src[c];
+    // Tail (only in the last tile): 2-byte pieces.
+    const int64_t tail0 = n16 * 16;
+    const uint16_t* src16 = reinterpret_cast<const uint16_t*>(stage);
+    uint16_t* dst16 = reinterpret_cast<uint16_t*>(gbase);
+    for (int64_t c = tail0 / 2 + threadIdx.x; c < bytes / 2; c += kListBlock) dst16[c] = src16[c];
+}
+
+// ---------------------------------------------------------------- host side
+
+size_t list_workspace_bytes(int64_t n, int64_t capacity) {
+    int64_t nb = (n + kSegsPerCountBlock - 1) / kSegsPerCountBlock;
+    if (nb < 1) nb = 1;
+    int64_t ntiles = (capacity + kListTile - 1) / kListTile;
+    size_t b = kAlign;                                  // status, total
+    b += align_up((size_t)nb * sizeof(int64_t));         // block sums
+    b += align_up((size_t)nb * sizeof(int32_t));         // block flags
+    b += align_up((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));  // counts
+    b += align_up((size_t)(ntiles + 1) * sizeof(int32_t));      // tile map
+    return b;
+}
+
+ListWork list_workspace(void* d_work, int64_t n, int64_t capacity) {
+    ListWork w;
+    int64_t nb = (n + kSegsPerCountBlock - 1) / kSegsPerCountBlock;
+    if (nb < 1) nb = 1;
+    uint8_t* p = static_cast<uint8_t*>(d_work);
+    w.status = reinterpret_cast<int32_t*>(p);
+    w.total = reinterpret_cast<int64_t*>(p + 8);
+    p += kAlign;
+    w.block_sums = reinterpret_cast<int64_t*>(p);
+    p += align_up((size_t)nb * sizeof(int64_t));
+    w.block_flags = reinterpret_cast<int32_t*>(p);
+    p += align_up((size_t)nb * sizeof(int32_t));
+    w.counts = reinterpret_cast<uint32_t*>(p);
+    p += align_up((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    w.tile_seg = reinterpret_cast<int32_t*>(p);
+    w.nb = nb;
+    w.ntiles = (capacity + kListTile - 1) / kListTile;
+    return w;
+}
+
+hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
+                             hipStream_t stream) {
+    if (n == 0) {
+        // One block that writes a zero sum and no flag.
+        if (aligned8)
+            k_list_count<true><<<1, kCountBlock, 0, stream>>>(segs, 0, w.counts, w.block_sums, w.block_flags);
+        else
+            k_list_count<false><<<1, kCountBlock, 0, stream>>>(segs, 0, w.counts, w.block_sums, w.block_flags);
+        return hipGetLastError();
+    }
+    dim3 grid((unsigned)w.nb);
+    if (aligned8)
+        k_list_count<true><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums, w.block_flags);
+    else
+        k_list_count<false><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums, w.block_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_scan(const ListWork& w, int64_t n, int64_t* offsets, int64_t capacity,
+                            bool want_voxels, hipStream_t stream) {
+    k_list_scan<<<1, kScanBlock, 0, stream>>>(w.block_sums, w.block_flags, w.nb, offsets, n, w.total,
+                                              w.status, capacity, want_voxels ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_offsets(int64_t n, int64_t* offsets, const ListWork& w, int64_t capacity,
+                               bool want_voxels, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    int64_t tile_limit = want_voxels ? (capacity + kListTile - 1) / kListTile : 0;
+    k_list_offsets<<<dim3((unsigned)w.nb), kCountBlock, 0, stream>>>(
+        n, w.counts, w.block_sums, offsets, w.tile_seg, tile_limit, w.total, w.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
+                              const ListWork& w, int16_t* voxels, int64_t capacity,
+                              int64_t tiles_to_launch, hipStream_t stream) {
+    (void)capacity;
+    if (n == 0 || tiles_to_launch <= 0) return hipSuccess;
+    dim3 grid((unsigned)tiles_to_launch);
+    if (aligned8)
+        k_list_voxels<true><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
+                                                             w.total, w.status);
+    else
+        k_list_voxels<false><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
+                                                              w.total, w.status);
+    return hipGetLastError();
+}
+
+}  // namespace vox

@@ -1,0 +1,99 @@
+"""HIP bit-volumes against the CPU oracle, word by word (GPU)."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2009_09500_amd import binding, workloads
+from tests.gpu_helpers import dev, grid_host, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def assert_grid(segs, dims, base=None):
+    torch = pytest.importorskip("torch")
+    s = to_dev(segs)
+    if base is None:
+        g, c = binding.segments_to_grid(s, dims, want_counts=True)
+    else:
+        g = to_dev(base.view(np.int32))
+        g, c = binding.segments_to_grid(s, dims, grid=g, want_counts=True)
+    got = grid_host(g)
+    exp = oracle.grid(segs, dims, base=base)
+    if not np.array_equal(got, exp):
+        bad = np.flatnonzero(got != exp)
+        raise AssertionError("%d words differ, first %s" % (bad.size, bad[:5].tolist()))
+    assert np.array_equal(to_host(c), oracle.counts(segs))
+
+
+def random_in(dims, n, seed):
+    rng = np.random.default_rng(seed)
+    p = [np.stack([rng.integers(0, d, n) for d in dims], 1) for _ in range(2)]
+    return np.concatenate(p, 1).astype(np.int32)
+
+
+def test_small_uniform_256():
+    c = workloads.small_uniform()
+    assert_grid(c["segs"], c["dims"])
+
+
+def test_single_diagonal_256():
+    c = workloads.single_diagonal()
+    assert_grid(c["segs"], c["dims"])
+
+
+@pytest.mark.parametrize("dims", [(37, 5, 3), (100, 30, 7), (1, 1, 1), (33, 64, 2), (64, 64, 64)])
+def test_odd_volumes(dims):
+    assert_grid(random_in(dims, 500, sum(dims)), dims)
+
+
+def test_or_into_existing():
+    dims = (96, 40, 20)
+    rng = np.random.default_rng(9)
+    base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+    base &= rng.integers(0, 2**32, size=base.size, dtype=np.uint32)   # ~25% ones
+    nbits = dims[0] * dims[1] * dims[2]
+    if nbits % 32:
+        base[-1] &= (1 << (nbits % 32)) - 1
+    assert_grid(random_in(dims, 800, 10), dims, base=base)
+
+
+def test_arbitrary_length_scaled():
+    c = workloads.arbitrary_length(n=100_000, volume=512)
+    assert_grid(c["segs"], c["dims"])
+
+
+def test_wireframe_request():
+    q = workloads.wireframe_request(3)
+    assert_grid(q["segs"], q["dims"])
+
+
+def test_scenes_plain_calls():
+    for sc in workloads.scenes(n_scenes=6, seed=77):
+        assert_grid(sc["segs"], sc["dims"])
+
+
+def test_out_of_volume_segment_is_skipped():
+    torch = pytest.importorskip("torch")
+    dims = (64, 64, 64)
+    segs = random_in(dims, 200, 5)
+    bad = segs.copy()
+    bad[17] = [0, 0, 0, 64, 10, 10]
+    bad[99] = [-1, 3, 3, 5, 5, 5]
+    g = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev())
+    work = binding.workspace(binding.vox_grid_workspace_bytes(len(bad), dims), dev())
+    binding.vox_segments_to_grid(to_dev(bad), dims, g, None, binding.VOX_GRID_CLEAR, work)
+    assert binding.vox_read_status(work) == binding.VOX_ERR_OUT_OF_RANGE
+    keep = np.delete(segs, [17, 99], axis=0)
+    assert np.array_equal(grid_host(g), oracle.grid(keep, dims))
+
+
+def test_empty_clears():
+    torch = pytest.importorskip("torch")
+    dims = (128, 16, 16)
+    g = torch.full((binding.grid_words(dims),), -1, dtype=torch.int32, device=dev())
+    segs = torch.zeros((0, 6), dtype=torch.int32, device=dev())
+    binding.segments_to_grid(segs, dims, grid=None)
+    work = binding.workspace(binding.vox_grid_workspace_bytes(0, dims), dev())
+    binding.vox_segments_to_grid(segs, dims, g, None, binding.VOX_GRID_CLEAR, work)
+    assert not grid_host(g).any()
