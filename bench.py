@@ -1,0 +1,300 @@
+"""Benchmark of the voxelization hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+A step is one call of the grid path on the arbitrary-length workload:
+4 194 304 segments (seed 1003) voxelized into a cleared 2048^3 packed
+bit-volume (1 GiB) plus per-segment counts, inputs resident in HBM.  The
+timed region is exactly K steps between HIP events on the launch stream,
+bracketed by device synchronisation.  Prints ONE JSON line.
+
+Also reported (in "extra"): the fixed-length list workload (1 048 576
+segments, 68 157 440 voxels), the small 1000-segment workload and a single
+segment alone (launch latency), each timed the same way.
+
+The CPU baseline is the oracle (oracle/, single-threaded C) timed on a
+bounded sample of the same workload; it is a reported reference, not the
+target.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+METRIC = "voxels/sec + HBM GB/s (batched vs plain), p50/p99 scene latency"
+
+
+def _events_time(stream, fn, steps):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(steps):
+            fn()
+        end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end)
+
+
+def source_digest(files) -> str:
+    h = hashlib.sha256()
+    for f in sorted(files):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str, workload: str, sources):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_digest") != source_digest(sources):
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bench_grid(args, torch, binding, workloads, dev, stream):
+    c = workloads.arbitrary_length()
+    segs_np = c["segs"]
+    dims = c["dims"]
+    n = segs_np.shape[0]
+    segs = torch.from_numpy(segs_np).to(dev)
+    grid = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev)
+    counts = torch.empty(n, dtype=torch.int32, device=dev)
+    work = binding.workspace(binding.vox_grid_workspace_bytes(n, dims), dev)
+    voxels = int((np.abs(segs_np[:, 3:].astype(np.int64) - segs_np[:, :3]).max(1) + 1).sum())
+
+    def step():
+        binding.vox_segments_to_grid(segs, dims, grid, counts, binding.VOX_GRID_CLEAR, work,
+                                     stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert binding.vox_read_status(work, stream=stream) == binding.VOX_OK
+    binding.vox_profile_reset()
+    binding.vox_profile_enable(True)
+    ms = _events_time(stream, step, args.steps)
+    binding.vox_profile_enable(False)
+    prof = binding.vox_profile_records()
+    binding.vox_profile_reset()
+    grid_bytes = grid.numel() * 4
+    algo_bytes = 24 * n + 4 * n + grid_bytes
+    return {
+        "n": n, "dims": dims, "voxels": voxels, "ms_total": ms, "prof": prof,
+        "algo_bytes": algo_bytes, "grid_bytes": grid_bytes, "segs_np": segs_np,
+    }
+
+
+def bench_list(args, torch, binding, workloads, dev, stream):
+    c = workloads.fixed_length()
+    segs = torch.from_numpy(c["segs"]).to(dev)
+    n = segs.shape[0]
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    work0 = binding.workspace(binding.vox_list_workspace_bytes(n, 0), dev)
+    total = binding.vox_segments_to_list(segs, offsets, None, 0, work0, want_total=True,
+                                         stream=stream)
+    vox = torch.empty((total, 3), dtype=torch.int16, device=dev)
+    work = binding.workspace(binding.vox_list_workspace_bytes(n, total), dev)
+
+    def step():
+        binding.vox_segments_to_list(segs, offsets, vox, total, work, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    steps = max(args.steps, 5)
+    binding.vox_profile_reset()
+    binding.vox_profile_enable(True)
+    ms = _events_time(stream, step, steps) / steps
+    binding.vox_profile_enable(False)
+    prof = binding.vox_profile_records()
+    binding.vox_profile_reset()
+    algo = 24 * n + 8 * (n + 1) + 6 * total
+    kv = prof.get("list_voxels", (0.0, 1))
+    kv_ms = kv[0] / max(kv[1], 1)
+    return {
+        "workload": "fixed-length 1048576 segments x 65 voxels -> int16 lists (seed 1002)",
+        "voxels": total, "ms_per_call": round(ms, 4),
+        "voxels_per_s": total / (ms * 1e-3),
+        "hbm_gbs_algorithmic": algo / (ms * 1e-3) / 1e9,
+        "algorithmic_bytes": algo,
+        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
+        "list_voxels_kernel_gbs": (6 * total) / (kv_ms * 1e-3) / 1e9 if kv_ms > 0 else None,
+    }
+
+
+def bench_small(args, torch, binding, workloads, dev, stream):
+    out = {}
+    for name, c in (("small_1000_segments_256^3", workloads.small_uniform()),
+                    ("single_segment_256_voxels", workloads.single_diagonal())):
+        segs = torch.from_numpy(c["segs"]).to(dev)
+        n = segs.shape[0]
+        dims = c["dims"]
+        grid = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev)
+        work = binding.workspace(binding.vox_grid_workspace_bytes(n, dims), dev)
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        w0 = binding.workspace(binding.vox_list_workspace_bytes(n, 0), dev)
+        total = binding.vox_segments_to_list(segs, offsets, None, 0, w0, want_total=True,
+                                             stream=stream)
+        vox = torch.empty((total, 3), dtype=torch.int16, device=dev)
+        wl = binding.workspace(binding.vox_list_workspace_bytes(n, total), dev)
+
+        def g():
+            binding.vox_segments_to_grid(segs, dims, grid, None, binding.VOX_GRID_CLEAR, work,
+                                         stream=stream)
+
+        def l():
+            binding.vox_segments_to_list(segs, offsets, vox, total, wl, stream=stream)
+
+        for _ in range(3):
+            g()
+            l()
+        reps = 50
+        out[name] = {
+            "voxels": total,
+            "grid_us_per_call": round(_events_time(stream, g, reps) / reps * 1e3, 2),
+            "list_us_per_call": round(_events_time(stream, l, reps) / reps * 1e3, 2),
+        }
+    return out
+
+
+def cpu_baseline(segs_np, dims, seconds_target=15.0):
+    """The oracle on the first segments of the workload (bounded sample)."""
+    from oracle import oracle
+    o = oracle.default()
+    # Calibrate on a small prefix, then run the sample once.
+    probe = segs_np[:20000]
+    t = time.perf_counter()
+    o.grid(probe, dims)
+    dt = time.perf_counter() - t
+    per_seg = max(dt / probe.shape[0], 1e-9)
+    m = int(min(segs_np.shape[0], max(50000, seconds_target / per_seg)))
+    sample = segs_np[:m]
+    vox = int((np.abs(sample[:, 3:].astype(np.int64) - sample[:, :3]).max(1) + 1).sum())
+    t = time.perf_counter()
+    o.grid(sample, dims)
+    dt = time.perf_counter() - t
+    return {
+        "value": vox / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+        "sample": "first %d of %d segments (%d voxels) into the cleared %dx%dx%d volume, "
+                  "clear included; %.1f s" % (m, segs_np.shape[0], vox, dims[0], dims[1],
+                                                dims[2], dt),
+        "host_cpu": platform.processor() or platform.machine(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X and has "
+              "no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2009_09500_amd import binding, workloads
+
+    binding.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    r = bench_grid(args, torch, binding, workloads, dev, stream)
+    ms_step = r["ms_total"] / args.steps
+    value = r["voxels"] / (ms_step * 1e-3)
+    prof = r["prof"]
+    dom = max(prof.items(), key=lambda kv: kv[1][0]) if prof else ("", (0.0, 1))
+    dom_name, (dom_ms, dom_launches) = dom
+    dom_avg_ms = dom_ms / max(dom_launches, 1)
+    sources = ["paper_2009_09500_amd/csrc/" + f for f in
+               sorted(os.listdir(os.path.join(ROOT, "paper_2009_09500_amd", "csrc")))]
+    # Algorithmic bytes the dominant kernel must move per launch.
+    dom_algo = {"grid_direct": 24 * r["n"] + 4 * r["n"] + r["grid_bytes"]}.get(
+        dom_name, r["algo_bytes"])
+    achieved = dom_algo / (dom_avg_ms * 1e-3) / 1e9 if dom_avg_ms > 0 else 0.0
+    traffic = counter_traffic(dom_name, "arbitrary4m", sources)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "arbitrary-length: 4194304 segments (seed 1003), start uniform in "
+                        "[0,2048)^3, log-uniform length clipped to the volume -> cleared "
+                        "2048^3 packed bit-volume + per-segment counts",
+            "segments": r["n"], "voxels": r["voxels"], "volume": list(r["dims"]),
+            "parallelism": "single GPU",
+        },
+        "hbm_gbs_algorithmic": r["algo_bytes"] / (ms_step * 1e-3) / 1e9,
+        "hbm_frac_algorithmic": r["algo_bytes"] / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "algorithmic_bytes_per_step": r["algo_bytes"],
+        "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
+        "roofline": {
+            "kernel": dom_name,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": dom_algo,
+            "avg_launch_ms": dom_avg_ms,
+        },
+    }
+    if not args.no_extra:
+        line["extra"] = {
+            "list": bench_list(args, torch, binding, workloads, dev, stream),
+            "small": bench_small(args, torch, binding, workloads, dev, stream),
+        }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(r["segs_np"], r["dims"])
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

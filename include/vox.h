@@ -186,6 +186,27 @@ const char *vox_last_error(void);
 /* VOX_ABI_VERSION of the built library. */
 int vox_abi_version(void);
 
+/* ------------------------------------------------------- kernel timing */
+
+/* Tracing of the library's own kernels.  While enabled, each kernel launch
+ * of every entry point is bracketed by two HIP events recorded on the
+ * launch's stream, and its duration is added to a per-kernel record.  Do
+ * not enable it while a stream is being captured into a graph.  Process-wide
+ * and thread-safe. */
+vox_status vox_profile_enable(int enable);
+
+/* Drops all records (after waiting for pending events). */
+void vox_profile_reset(void);
+
+/* Number of per-kernel records. */
+int vox_profile_count(void);
+
+/* Record `index`: kernel name (copied into name[name_len]), summed
+ * duration in milliseconds and number of launches.  Synchronises on every
+ * pending event.  VOX_ERR_INVALID_ARGUMENT for a bad index. */
+vox_status vox_profile_read(int index, char *name, size_t name_len, double *total_ms,
+                            int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

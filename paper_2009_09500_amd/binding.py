@@ -85,6 +85,15 @@ def load(path: str | None = None):
     lib.vox_batch_scenes.restype = ctypes.c_int
     lib.vox_read_status.argtypes = [P, ctypes.POINTER(i32), P]
     lib.vox_read_status.restype = ctypes.c_int
+    lib.vox_profile_enable.argtypes = [ctypes.c_int]
+    lib.vox_profile_enable.restype = ctypes.c_int
+    lib.vox_profile_reset.argtypes = []
+    lib.vox_profile_reset.restype = None
+    lib.vox_profile_count.argtypes = []
+    lib.vox_profile_count.restype = ctypes.c_int
+    lib.vox_profile_read.argtypes = [ctypes.c_int, ctypes.c_char_p, sz,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.vox_profile_read.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -162,6 +171,27 @@ def vox_read_status(work, stream=None) -> int:
     out = ctypes.c_int32(-1)
     _check(lib, lib.vox_read_status(_ptr(work), ctypes.byref(out), _stream(stream)))
     return int(out.value)
+
+
+def vox_profile_enable(enable: bool = True):
+    load().vox_profile_enable(1 if enable else 0)
+
+
+def vox_profile_reset():
+    load().vox_profile_reset()
+
+
+def vox_profile_records() -> dict:
+    """{kernel name: (total ms, launches)} of the library's kernel timing."""
+    lib = load()
+    out = {}
+    buf = ctypes.create_string_buffer(128)
+    for i in range(lib.vox_profile_count()):
+        ms = ctypes.c_double(0)
+        cnt = ctypes.c_int64(0)
+        _check(lib, lib.vox_profile_read(i, buf, 128, ctypes.byref(ms), ctypes.byref(cnt)))
+        out[buf.value.decode()] = (float(ms.value), int(cnt.value))
+    return out
 
 
 # ------------------------------------------------------------- conveniences

@@ -2,6 +2,7 @@
 // with a device-scope atomic.  Correct for any volume shape; used for
 // volumes the brick path does not cover.
 #include "vox_device.h"
+#include "vox_exact.h"
 #include "vox_internal.h"
 
 namespace vox {
@@ -69,8 +70,19 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_direct(const int32_t* __res
     }
 }
 
+// The brick path serves volumes whose rows are whole words and whose piece
+// ids fit 32 bits; everything else takes the direct path.
+static bool use_bricks(int64_t n, int32_t dx, int32_t dy, int32_t dz, BrickGeom& bg) {
+    int lg[3];
+    default_brick_lg(dx, dy, dz, lg);
+    if (!brick_geometry(dx, dy, dz, lg, bg)) return false;
+    if (n >= (int64_t(1) << 32) - 1) return false;
+    return max_pieces(n, bg) < (uint64_t(1) << 32) - 1;
+}
+
 size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz) {
-    (void)n; (void)dx; (void)dy; (void)dz;
+    BrickGeom bg;
+    if (use_bricks(n, dx, dy, dz, bg)) return brick_workspace_bytes(n, bg);
     return kAlign;
 }
 
@@ -84,7 +96,13 @@ GridWork grid_workspace(void* d_work, int64_t n, int32_t dx, int32_t dy, int32_t
 hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx, int32_t dy,
                        int32_t dz, uint32_t* grid, int32_t* counts, uint32_t flags,
                        const GridWork& w, hipStream_t stream) {
-    k_grid_init<<<1, 64, 0, stream>>>(w.status);
+    BrickGeom bg;
+    if (use_bricks(n, dx, dy, dz, bg))
+        return launch_brick_grid(segs, n, aligned8, bg, grid, counts, flags, w.status, stream);
+    {
+        KernelTimer timer("grid_init", stream);
+        k_grid_init<<<1, 64, 0, stream>>>(w.status);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nwords = ((int64_t)dx * dy * dz + 31) / 32;
@@ -92,12 +110,14 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
         int64_t blocks = (nwords / 4 + kGridBlock - 1) / kGridBlock;
         if (blocks > 8192) blocks = 8192;
         if (blocks < 1) blocks = 1;
+        KernelTimer timer("grid_clear", stream);
         k_grid_clear<<<dim3((unsigned)blocks), kGridBlock, 0, stream>>>(grid, nwords);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n == 0) return hipSuccess;
     dim3 gridDim((unsigned)((n + kGridBlock - 1) / kGridBlock));
+    KernelTimer timer("grid_direct", stream);
     if (aligned8)
         k_grid_direct<true><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts, w.status);
     else

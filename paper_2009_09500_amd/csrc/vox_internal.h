@@ -13,6 +13,22 @@ namespace vox {
 constexpr int32_t kStatusOutOfRange = 1;
 constexpr int32_t kStatusCapacity = 2;
 
+// Scoped kernel timer: records HIP events on `stream` around the launch
+// made inside its scope when kernel timing is enabled (vox_profile_enable);
+// otherwise does nothing.  Names must be string literals.
+class KernelTimer {
+  public:
+    KernelTimer(const char* name, hipStream_t stream);
+    ~KernelTimer();
+    KernelTimer(const KernelTimer&) = delete;
+    KernelTimer& operator=(const KernelTimer&) = delete;
+
+  private:
+    const char* name_;
+    hipStream_t stream_;
+    hipEvent_t start_ = nullptr;
+};
+
 // Workspace sections are 256-byte aligned.
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -55,6 +71,27 @@ hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, con
 struct GridWork {
     int32_t* status;  // [1]
 };
+
+// Brick decomposition of a volume: bricks of 2^lg[a] voxels per axis,
+// nb[a] bricks per axis (edge bricks may be partial), brick id
+// (bz * nb[1] + by) * nb[0] + bx.
+struct BrickGeom {
+    int32_t dim[3];
+    int32_t lg[3];
+    int32_t nb[3];
+    uint32_t nbricks;
+};
+
+constexpr uint32_t kMaxBricks = 16384;  // LDS histogram of 64 KiB
+constexpr int kHistBlock = 1024;
+constexpr int kHistRows = 256;
+
+void default_brick_lg(int32_t dx, int32_t dy, int32_t dz, int lg[3]);
+uint64_t max_pieces(int64_t n, const BrickGeom& bg);
+size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg);
+hipError_t launch_brick_grid(const int32_t* segs, int64_t n, bool aligned8, const BrickGeom& bg,
+                             uint32_t* grid, int32_t* counts, uint32_t flags, void* d_work,
+                             hipStream_t stream);
 
 size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz);
 GridWork grid_workspace(void* d_work, int64_t n, int32_t dx, int32_t dy, int32_t dz);

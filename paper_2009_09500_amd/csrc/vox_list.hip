@@ -292,6 +292,7 @@ ListWork list_workspace(void* d_work, int64_t n, int64_t capacity) {
 
 hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
                              hipStream_t stream) {
+    KernelTimer timer("list_count", stream);
     if (n == 0) {
         // One block that writes a zero sum and no flag.
         if (aligned8)
@@ -310,6 +311,7 @@ hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, cons
 
 hipError_t launch_list_scan(const ListWork& w, int64_t n, int64_t* offsets, int64_t capacity,
                             bool want_voxels, hipStream_t stream) {
+    KernelTimer timer("list_scan", stream);
     k_list_scan<<<1, kScanBlock, 0, stream>>>(w.block_sums, w.block_flags, w.nb, offsets, n, w.total,
                                               w.status, capacity, want_voxels ? 1 : 0);
     return hipGetLastError();
@@ -319,6 +321,7 @@ hipError_t launch_list_offsets(int64_t n, int64_t* offsets, const ListWork& w, i
                                bool want_voxels, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     int64_t tile_limit = want_voxels ? (capacity + kListTile - 1) / kListTile : 0;
+    KernelTimer timer("list_offsets", stream);
     k_list_offsets<<<dim3((unsigned)w.nb), kCountBlock, 0, stream>>>(
         n, w.counts, w.block_sums, offsets, w.tile_seg, tile_limit, w.total, w.status);
     return hipGetLastError();
@@ -330,6 +333,7 @@ hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, con
     (void)capacity;
     if (n == 0 || tiles_to_launch <= 0) return hipSuccess;
     dim3 grid((unsigned)tiles_to_launch);
+    KernelTimer timer("list_voxels", stream);
     if (aligned8)
         k_list_voxels<true><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
                                                              w.total, w.status);

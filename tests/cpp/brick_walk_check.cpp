@@ -1,0 +1,50 @@
+// Host-side driver for the exact brick helpers of the HIP library
+// (paper_2009_09500_amd/csrc/vox_exact.h): prints, for every segment read
+// from stdin, the bricks walk_bricks visits and the k-window box_window gives
+// inside each of them.  Built and run by tests/test_brick_math.py (CPU only).
+//
+// stdin:  dx dy dz lgx lgy lgz n, then n lines x0 y0 z0 x1 y1 z1
+// stdout: per segment one line "i: b klo khi; b klo khi; ..."
+#include <cstdio>
+#include <vector>
+
+#include "vox_exact.h"
+
+int main() {
+    int dims[3], lg[3];
+    long long n;
+    if (scanf("%d %d %d %d %d %d %lld", &dims[0], &dims[1], &dims[2], &lg[0], &lg[1], &lg[2], &n) != 7)
+        return 2;
+    vox::BrickGeom bg;
+    if (!vox::brick_geometry(dims[0], dims[1], dims[2], lg, bg)) return 3;
+    for (long long i = 0; i < n; ++i) {
+        vox::Seg g;
+        if (scanf("%d %d %d %d %d %d", &g.p0[0], &g.p0[1], &g.p0[2], &g.p1[0], &g.p1[1], &g.p1[2]) != 6)
+            return 4;
+        printf("%lld:", i);
+        if (!vox::in_volume(g, bg)) {
+            printf(" out\n");
+            continue;
+        }
+        vox::SegAxes s = vox::seg_axes(g);
+        std::vector<uint32_t> bricks;
+        vox::walk_bricks(s, bg, [&](uint32_t b) { bricks.push_back(b); });
+        for (uint32_t b : bricks) {
+            int bx = (int)(b % (uint32_t)bg.nb[0]);
+            int by = (int)((b / (uint32_t)bg.nb[0]) % (uint32_t)bg.nb[1]);
+            int bz = (int)(b / ((uint32_t)bg.nb[0] * (uint32_t)bg.nb[1]));
+            int32_t lo[3] = {bx << lg[0], by << lg[1], bz << lg[2]};
+            int32_t hi[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                int32_t e = dims[ax] - lo[ax];
+                e = e < (1 << lg[ax]) ? e : (1 << lg[ax]);
+                hi[ax] = lo[ax] + e - 1;
+            }
+            uint32_t klo = 0, khi = 0;
+            if (s.N > 0) vox::box_window(s, lo, hi, klo, khi);
+            printf(" %u %u %u;", b, klo, khi);
+        }
+        printf("\n");
+    }
+    return 0;
+}
