@@ -126,6 +126,24 @@ vox_status vox_segments_to_grid(const vox_segment *d_segs, int64_t n,
                                 uint32_t *d_grid, int32_t *d_counts, uint32_t flags,
                                 void *d_work, size_t work_bytes, void *stream);
 
+/* ----------------------------------------------------------------- tuning */
+
+/* Launch-shape choice for bit-volume calls.  brick_lg[a] is log2 of the LDS
+ * brick size along axis a; all zero selects the library default.  The
+ * choice changes only speed and workspace size, never the output.  Supported
+ * shapes: 2^8 x 2^6 x 2^5, 2^8 x 2^6 x 2^6, 2^7 x 2^6 x 2^6, 2^7 x 2^7 x 2^6. */
+typedef struct vox_tuning {
+    int32_t brick_lg[3];
+} vox_tuning;
+
+/* Sets the process-wide tuning used by later grid and batch calls (NULL
+ * restores the default).  Workspace sizes depend on it: query them after
+ * setting it.  VOX_ERR_INVALID_ARGUMENT for an unsupported shape. */
+vox_status vox_set_tuning(const vox_tuning *tuning);
+
+/* Current process-wide tuning. */
+vox_status vox_get_tuning(vox_tuning *tuning);
+
 /* ---------------------------------------------------------------- batches */
 
 /* One scene of a batch: its own segments and its own bit-volume, with the

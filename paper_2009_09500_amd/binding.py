@@ -39,6 +39,11 @@ class VoxError(RuntimeError):
         self.status = status
 
 
+class VoxTuning(ctypes.Structure):
+    """struct vox_tuning of include/vox.h."""
+    _fields_ = [("brick_lg", ctypes.c_int32 * 3)]
+
+
 class VoxScene(ctypes.Structure):
     """struct vox_scene of include/vox.h."""
     _fields_ = [
@@ -85,6 +90,10 @@ def load(path: str | None = None):
     lib.vox_batch_scenes.restype = ctypes.c_int
     lib.vox_read_status.argtypes = [P, ctypes.POINTER(i32), P]
     lib.vox_read_status.restype = ctypes.c_int
+    lib.vox_set_tuning.argtypes = [ctypes.POINTER(VoxTuning)]
+    lib.vox_set_tuning.restype = ctypes.c_int
+    lib.vox_get_tuning.argtypes = [ctypes.POINTER(VoxTuning)]
+    lib.vox_get_tuning.restype = ctypes.c_int
     lib.vox_profile_enable.argtypes = [ctypes.c_int]
     lib.vox_profile_enable.restype = ctypes.c_int
     lib.vox_profile_reset.argtypes = []
@@ -171,6 +180,25 @@ def vox_read_status(work, stream=None) -> int:
     out = ctypes.c_int32(-1)
     _check(lib, lib.vox_read_status(_ptr(work), ctypes.byref(out), _stream(stream)))
     return int(out.value)
+
+
+def vox_set_tuning(brick_lg=None):
+    """Process-wide brick shape (log2 per axis) for grid calls; None = default."""
+    lib = load()
+    if brick_lg is None:
+        _check(lib, lib.vox_set_tuning(None))
+    else:
+        t = VoxTuning()
+        for a in range(3):
+            t.brick_lg[a] = int(brick_lg[a])
+        _check(lib, lib.vox_set_tuning(ctypes.byref(t)))
+
+
+def vox_get_tuning():
+    lib = load()
+    t = VoxTuning()
+    _check(lib, lib.vox_get_tuning(ctypes.byref(t)))
+    return tuple(int(v) for v in t.brick_lg)
 
 
 def vox_profile_enable(enable: bool = True):

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "vox.h"
 #include "vox_internal.h"
@@ -12,6 +13,9 @@
 namespace {
 
 thread_local char g_last_error[512] = "";
+
+std::mutex g_tuning_mu;
+vox_tuning g_tuning = {{0, 0, 0}};
 
 vox_status fail(vox_status st, const char* fmt, ...) {
     va_list ap;
@@ -46,7 +50,36 @@ vox_status check_dims(int32_t dx, int32_t dy, int32_t dz) {
 
 }  // namespace
 
+namespace vox {
+void tuned_brick_lg(int lg[3]) {
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    for (int a = 0; a < 3; ++a) lg[a] = g_tuning.brick_lg[a];
+}
+}  // namespace vox
+
 extern "C" {
+
+vox_status vox_set_tuning(const vox_tuning* tuning) {
+    vox_tuning t = {{0, 0, 0}};
+    if (tuning) {
+        t = *tuning;
+        const bool zero = t.brick_lg[0] == 0 && t.brick_lg[1] == 0 && t.brick_lg[2] == 0;
+        if (!zero && !vox::brick_shape_supported(t.brick_lg))
+            return fail(VOX_ERR_INVALID_ARGUMENT, "brick shape 2^%d x 2^%d x 2^%d has no compiled kernel",
+                        t.brick_lg[0], t.brick_lg[1], t.brick_lg[2]);
+    }
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning = t;
+    return ok();
+}
+
+vox_status vox_get_tuning(vox_tuning* tuning) {
+    if (!tuning) return fail(VOX_ERR_INVALID_ARGUMENT, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    *tuning = g_tuning;
+    return ok();
+}
+
 
 int vox_abi_version(void) { return VOX_ABI_VERSION; }
 

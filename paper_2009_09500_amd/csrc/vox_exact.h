@@ -51,8 +51,58 @@ constexpr uint32_t kNever = 0xFFFFFFFFu;
 // kNever if it never does (m > a).  a >= 1 when m <= a.
 __host__ __device__ __forceinline__ uint32_t k_reach(uint32_t m, uint32_t a, uint32_t N, uint32_t neg) {
     if (m > a) return kNever;
+    // Dominant axis: q(k) = k exactly.
+    if (a == N) return m;
     uint64_t x = 2ull * N * m - N + neg;
     return div_ceil_u64(x, 2u * a);
+}
+
+// Brick crossings along one axis.  Crossing t happens at
+// k_t = ceil(X_t / D) with D = 2a and X_t = 2 N m_t - N + neg, where m_t
+// grows by the brick size B per crossing, so X_t grows by 2 N B = Q D + R
+// (0 <= R < D).  Keeping the slack sl = k_t D - X_t in [0, D):
+//   k_{t+1} = k_t + Q + [sl < R],  sl_{t+1} = sl + [sl < R] D - R,
+// one division pair per axis and segment, none per crossing.
+struct AxisCross {
+    int32_t b, bend, dir;  // current brick, last brick, direction
+    uint32_t kn;           // k of the next crossing, kNever if none
+    uint32_t sl, Q, R, D;
+};
+
+__host__ __device__ __forceinline__ void cross_init(AxisCross& c, int32_t p0, int32_t p1, uint32_t a,
+                                                    uint32_t neg, uint32_t N, int lg) {
+    c.b = p0 >> lg;
+    c.bend = p1 >> lg;
+    c.dir = neg ? -1 : 1;
+    c.kn = kNever;
+    c.sl = c.Q = c.R = 0;
+    c.D = 1;
+    if (c.b == c.bend) return;
+    const uint32_t m = neg ? (uint32_t)(p0 - (c.b << lg) + 1) : (uint32_t)(((c.b + 1) << lg) - p0);
+    const uint32_t B = 1u << lg;
+    if (a == N) {  // dominant axis: crossings exactly B apart
+        c.kn = m;
+        c.Q = B;
+        return;
+    }
+    c.D = 2u * a;
+    uint32_t q, r;
+    divmod_u64(2ull * N * m - N + neg, c.D, q, r);
+    c.kn = r ? q + 1u : q;
+    c.sl = r ? c.D - r : 0u;
+    divmod_u64(2ull * N * B, c.D, c.Q, c.R);
+}
+
+// Advances an axis whose crossing c.kn has just happened.
+__host__ __device__ __forceinline__ void cross_step(AxisCross& c) {
+    c.b += c.dir;
+    if (c.b == c.bend) {
+        c.kn = kNever;
+        return;
+    }
+    const uint32_t carry = c.sl < c.R ? 1u : 0u;
+    c.kn += c.Q + carry;
+    c.sl = c.sl + (carry ? c.D : 0u) - c.R;
 }
 
 struct SegAxes {
@@ -78,39 +128,25 @@ __host__ __device__ __forceinline__ SegAxes seg_axes(const Seg& g) {
     return s;
 }
 
-// Walks the bricks of one in-volume segment in order, calling emit(brick id).
+// Walks the bricks of one in-volume segment in order, calling
+// emit(brick id, klo, khi) with the k-window [klo, khi] of the segment inside
+// each brick: a window ends where the next crossing begins.
 template <typename Emit>
 __host__ __device__ __forceinline__ void walk_bricks(const SegAxes& s, const BrickGeom& bg, Emit emit) {
-    int32_t b[3], bend[3];
-    uint32_t kn[3];
+    AxisCross c[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        b[ax] = s.p0[ax] >> bg.lg[ax];
-        bend[ax] = s.p1[ax] >> bg.lg[ax];
-        kn[ax] = kNever;
-        if (b[ax] != bend[ax]) {
-            uint32_t m = s.neg[ax] ? (uint32_t)(s.p0[ax] - (b[ax] << bg.lg[ax]) + 1)
-                                   : (uint32_t)(((b[ax] + 1) << bg.lg[ax]) - s.p0[ax]);
-            kn[ax] = k_reach(m, s.a[ax], s.N, s.neg[ax]);
-        }
-    }
+    for (int ax = 0; ax < 3; ++ax) cross_init(c[ax], s.p0[ax], s.p1[ax], s.a[ax], s.neg[ax], s.N, bg.lg[ax]);
+    uint32_t klo = 0;
     while (true) {
-        emit((uint32_t)((b[2] * bg.nb[1] + b[1]) * bg.nb[0] + b[0]));
-        uint32_t km = kn[0] < kn[1] ? kn[0] : kn[1];
-        km = km < kn[2] ? km : kn[2];
+        uint32_t km = c[0].kn < c[1].kn ? c[0].kn : c[1].kn;
+        km = km < c[2].kn ? km : c[2].kn;
+        emit((uint32_t)((c[2].b * bg.nb[1] + c[1].b) * bg.nb[0] + c[0].b), klo, km == kNever ? s.N : km - 1u);
         if (km == kNever) break;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            if (kn[ax] == km) {
-                b[ax] += s.neg[ax] ? -1 : 1;
-                kn[ax] = kNever;
-                if (b[ax] != bend[ax]) {
-                    uint32_t m = s.neg[ax] ? (uint32_t)(s.p0[ax] - (b[ax] << bg.lg[ax]) + 1)
-                                           : (uint32_t)(((b[ax] + 1) << bg.lg[ax]) - s.p0[ax]);
-                    kn[ax] = k_reach(m, s.a[ax], s.N, s.neg[ax]);
-                }
-            }
+            if (c[ax].kn == km) cross_step(c[ax]);
         }
+        klo = km;
     }
 }
 
@@ -164,7 +200,9 @@ __host__ __device__ __forceinline__ void box_window(const SegAxes& s, const int3
 // axis; false when the brick path cannot serve it (rows not whole words, or
 // more bricks than one LDS histogram holds).
 inline bool brick_geometry(int32_t dx, int32_t dy, int32_t dz, const int lg[3], BrickGeom& bg) {
-    if (dx % 32 != 0 || lg[0] < 5) return false;
+    // Rows of whole words; end points of staged segments and pieces are
+    // 16-bit.
+    if (dx % 32 != 0 || lg[0] < 5 || dx > 16384 || dy > 16384 || dz > 16384) return false;
     const int32_t dim[3] = {dx, dy, dz};
     uint64_t nb = 1;
     for (int ax = 0; ax < 3; ++ax) {

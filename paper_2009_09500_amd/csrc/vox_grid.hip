@@ -75,7 +75,15 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_direct(const int32_t* __res
 static bool use_bricks(int64_t n, int32_t dx, int32_t dy, int32_t dz, BrickGeom& bg) {
     int lg[3];
     default_brick_lg(dx, dy, dz, lg);
+    int tl[3];
+    tuned_brick_lg(tl);
+    if (tl[0] > 0) {
+        lg[0] = tl[0];
+        lg[1] = tl[1];
+        lg[2] = tl[2];
+    }
     if (!brick_geometry(dx, dy, dz, lg, bg)) return false;
+    if (!brick_shape_supported(bg.lg)) return false;
     if (n >= (int64_t(1) << 32) - 1) return false;
     return max_pieces(n, bg) < (uint64_t(1) << 32) - 1;
 }

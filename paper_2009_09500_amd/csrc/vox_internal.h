@@ -87,6 +87,9 @@ constexpr int kHistBlock = 1024;
 constexpr int kHistRows = 256;
 
 void default_brick_lg(int32_t dx, int32_t dy, int32_t dz, int lg[3]);
+bool brick_shape_supported(const int lg[3]);
+// Process-wide brick shape chosen with vox_set_tuning (all zero = default).
+void tuned_brick_lg(int lg[3]);
 uint64_t max_pieces(int64_t n, const BrickGeom& bg);
 size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg);
 hipError_t launch_brick_grid(const int32_t* segs, int64_t n, bool aligned8, const BrickGeom& bg,

@@ -27,9 +27,14 @@ int main() {
             continue;
         }
         vox::SegAxes s = vox::seg_axes(g);
-        std::vector<uint32_t> bricks;
-        vox::walk_bricks(s, bg, [&](uint32_t b) { bricks.push_back(b); });
-        for (uint32_t b : bricks) {
+        std::vector<uint32_t> bricks, los, his;
+        vox::walk_bricks(s, bg, [&](uint32_t b, uint32_t klo, uint32_t khi) {
+            bricks.push_back(b);
+            los.push_back(klo);
+            his.push_back(khi);
+        });
+        for (size_t p = 0; p < bricks.size(); ++p) {
+            const uint32_t b = bricks[p];
             int bx = (int)(b % (uint32_t)bg.nb[0]);
             int by = (int)((b / (uint32_t)bg.nb[0]) % (uint32_t)bg.nb[1]);
             int bz = (int)(b / ((uint32_t)bg.nb[0] * (uint32_t)bg.nb[1]));
@@ -40,8 +45,13 @@ int main() {
                 e = e < (1 << lg[ax]) ? e : (1 << lg[ax]);
                 hi[ax] = lo[ax] + e - 1;
             }
+            // The walk's own window and the clipped window must agree.
             uint32_t klo = 0, khi = 0;
             if (s.N > 0) vox::box_window(s, lo, hi, klo, khi);
+            if (klo != los[p] || khi != his[p]) {
+                printf(" MISMATCH walk %u %u box %u %u;", los[p], his[p], klo, khi);
+                continue;
+            }
             printf(" %u %u %u;", b, klo, khi);
         }
         printf("\n");

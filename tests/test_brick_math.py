@@ -71,6 +71,9 @@ def inside(dims, n, seed):
 CASES = [
     ((256, 256, 256), (7, 7, 6)),
     ((2048, 2048, 2048), (7, 7, 6)),
+    ((2048, 2048, 2048), (8, 6, 5)),
+    ((512, 512, 512), (8, 6, 6)),
+    ((8192, 64, 16384), (8, 6, 5)),
     ((96, 40, 20), (5, 3, 2)),
     ((64, 64, 64), (7, 7, 6)),
     ((512, 512, 512), (8, 6, 6)),

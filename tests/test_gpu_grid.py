@@ -97,3 +97,31 @@ def test_empty_clears():
     work = binding.workspace(binding.vox_grid_workspace_bytes(0, dims), dev())
     binding.vox_segments_to_grid(segs, dims, g, None, binding.VOX_GRID_CLEAR, work)
     assert not grid_host(g).any()
+
+
+SHAPES = [(8, 6, 5), (8, 6, 6), (7, 6, 6), (7, 7, 6)]
+
+
+@pytest.mark.parametrize("lg", SHAPES)
+def test_every_brick_shape(lg):
+    """Each compiled brick shape gives the oracle's volume (default restored)."""
+    binding.vox_set_tuning(lg)
+    try:
+        assert binding.vox_get_tuning() == lg
+        c = workloads.arbitrary_length(n=40_000, volume=512)
+        assert_grid(c["segs"], c["dims"])
+        dims = (96, 40, 20)
+        rng = np.random.default_rng(11)
+        base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+        assert_grid(random_in(dims, 300, 12), dims, base=base)
+        sc = workloads.scenes(n_scenes=3, seed=90)
+        for x in sc:
+            assert_grid(x["segs"], x["dims"])
+    finally:
+        binding.vox_set_tuning(None)
+
+
+def test_unsupported_shape_rejected():
+    with pytest.raises(binding.VoxError):
+        binding.vox_set_tuning((9, 9, 9))
+    assert binding.vox_get_tuning() == (0, 0, 0)
