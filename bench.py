@@ -10,7 +10,10 @@ bracketed by device synchronisation.  Prints ONE JSON line.
 
 Also reported (in "extra"): the fixed-length list workload (1 048 576
 segments, 68 157 440 voxels), the small 1000-segment workload and a single
-segment alone (launch latency), each timed the same way.
+segment alone (launch latency), each timed the same way; the 256-scene
+workload as plain calls, one batched launch sequence and a graph replay;
+and the serving loop on wireframe requests (saturation throughput, then a
+Poisson sweep with p50/p99 request latency).
 
 The CPU baseline is the oracle (oracle/, single-threaded C) timed on a
 bounded sample of the same workload; it is a reported reference, not the
@@ -182,6 +185,108 @@ def bench_small(args, torch, binding, workloads, dev, stream):
     return out
 
 
+def bench_batch(args, torch, binding, workloads, dev, stream):
+    """The scene workload: 256 volumes, one plain call each vs one batched
+    launch sequence vs a HIP-graph replay of it (all clearing)."""
+    sc = workloads.scenes()
+    clear = binding.VOX_GRID_CLEAR
+    segs = [torch.from_numpy(x["segs"]).to(dev) for x in sc]
+    grids = [torch.empty(binding.grid_words(x["dims"]), dtype=torch.int32, device=dev) for x in sc]
+    n = sum(s.shape[0] for s in segs)
+    voxels = sum(int((np.abs(x["segs"][:, 3:].astype(np.int64) - x["segs"][:, :3]).max(1) + 1).sum())
+                 for x in sc)
+    algo = 24 * n + sum(g.numel() * 4 for g in grids)
+    work = binding.workspace(max(binding.vox_grid_workspace_bytes(s.shape[0], x["dims"])
+                                 for s, x in zip(segs, sc)), dev)
+
+    def plain():
+        for s, x, g in zip(segs, sc, grids):
+            binding.vox_segments_to_grid(s, x["dims"], g, None, clear, work, stream=stream)
+
+    table, launch = binding.vox_batch_plan([(s, x["dims"], g, None, clear)
+                                            for s, x, g in zip(segs, sc, grids)])
+    d_table = torch.from_numpy(table).to(dev)
+    bwork = binding.workspace(launch.work_bytes, dev)
+
+    def batched():
+        binding.vox_batch_scenes(d_table, launch, bwork, stream=stream)
+
+    for _ in range(2):
+        plain()
+        batched()
+    torch.cuda.synchronize()
+    assert binding.vox_read_status(bwork, stream=stream) == binding.VOX_OK
+    side = torch.cuda.Stream(device=dev)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        binding.vox_batch_scenes(d_table, launch, bwork, stream=side)
+    torch.cuda.synchronize()
+    reps = max(args.steps // 4, 3)
+    t_plain = _events_time(stream, plain, reps) / reps
+    t_batch = _events_time(stream, batched, reps) / reps
+    t_graph = _events_time(stream, graph.replay, reps) / reps
+    binding.vox_profile_reset()
+    binding.vox_profile_enable(True)
+    batched()
+    torch.cuda.synchronize()
+    binding.vox_profile_enable(False)
+    prof = binding.vox_profile_records()
+    binding.vox_profile_reset()
+
+    def rate(ms):
+        return {"ms": round(ms, 4), "voxels_per_s": voxels / (ms * 1e-3),
+                "hbm_gbs_algorithmic": algo / (ms * 1e-3) / 1e9}
+    return {
+        "workload": "256 scenes (seed 1004), volumes 64^3..512^3, %d segments, cleared grids" % n,
+        "segments": n, "voxels": voxels, "algorithmic_bytes": algo,
+        "plain_256_calls": rate(t_plain), "batched": rate(t_batch), "graph_replay": rate(t_graph),
+        "speedup_batched_vs_plain": t_plain / t_batch,
+        "speedup_graph_vs_plain": t_plain / t_graph,
+        "batched_kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
+        "launch": launch.as_dict(),
+    }
+
+
+def bench_serving(args, torch, binding, workloads, dev, n_requests=1000, pool_size=24):
+    """Wireframe requests into resident 512^3 grids: saturation throughput
+    (all requests at t=0), then Poisson arrivals at fractions of it."""
+    from paper_2009_09500_amd import serving
+    pool = [workloads.wireframe_request(r) for r in range(pool_size)]
+    pinned = [torch.from_numpy(w["segs"]).pin_memory() for w in pool]
+    dims = pool[0]["dims"]
+
+    def requests(arrivals):
+        return [serving.Request(i, pool[i % pool_size]["segs"], dims, float(t),
+                                dev={"pinned": pinned[i % pool_size]})
+                for i, t in enumerate(arrivals)]
+
+    def once(arrivals):
+        sched = serving.Scheduler(n_slots=48, budget_bytes=8 << 30, max_batch_segments=2_000_000,
+                                  max_batch_scenes=32)
+        out = serving.run(requests(arrivals), ex, sched)
+        assert ex.status() == binding.VOX_OK
+        return out
+
+    ex = serving.GpuExecutor(dims, n_slots=48, device=dev)
+    once(np.zeros(pool_size))                                   # warm-up
+    sat = once(np.zeros(n_requests))
+    sweep = []
+    for f in (0.25, 0.5, 0.75, 1.0, 1.25):
+        rate = f * sat["requests_per_s"]
+        st = once(serving.poisson_arrivals(n_requests, rate, seed=int(f * 100)))
+        st["offered_rate_per_s"] = rate
+        st["fraction_of_saturation"] = f
+        sweep.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})
+    edges = [w["segs"].shape[0] for w in pool]
+    return {
+        "workload": "wireframe requests: geodesic icospheres (seeds 1005+r, %d distinct, "
+                    "%d..%d edges) into resident 512^3 grids" % (pool_size, min(edges), max(edges)),
+        "requests_per_rate": n_requests,
+        "saturation": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sat.items()},
+        "poisson_sweep": sweep,
+    }
+
+
 def cpu_baseline(segs_np, dims, seconds_target=15.0):
     """The oracle on the first segments of the workload (bounded sample)."""
     from oracle import oracle
@@ -214,6 +319,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -246,7 +352,10 @@ def main():
     sources = ["paper_2009_09500_amd/csrc/" + f for f in
                sorted(os.listdir(os.path.join(ROOT, "paper_2009_09500_amd", "csrc")))]
     # Algorithmic bytes the dominant kernel must move per launch.
-    dom_algo = {"grid_direct": 24 * r["n"] + 4 * r["n"] + r["grid_bytes"]}.get(
+    # brick_fill writes the volume once (the clear is fused); grid_direct
+    # reads the segments, writes the counts and sets the volume's words.
+    dom_algo = {"brick_fill": r["grid_bytes"],
+                "grid_direct": 24 * r["n"] + 4 * r["n"] + r["grid_bytes"]}.get(
         dom_name, r["algo_bytes"])
     achieved = dom_algo / (dom_avg_ms * 1e-3) / 1e9 if dom_avg_ms > 0 else 0.0
     traffic = counter_traffic(dom_name, "arbitrary4m", sources)
@@ -290,7 +399,10 @@ def main():
         line["extra"] = {
             "list": bench_list(args, torch, binding, workloads, dev, stream),
             "small": bench_small(args, torch, binding, workloads, dev, stream),
+            "batch": bench_batch(args, torch, binding, workloads, dev, stream),
         }
+        if not args.no_serving:
+            line["extra"]["serving"] = bench_serving(args, torch, binding, workloads, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(r["segs_np"], r["dims"])
     print(json.dumps(line))

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define VOX_ABI_VERSION 1
+#define VOX_ABI_VERSION 2
 
 /* One segment: start point (x0,y0,z0) = S, end point (x1,y1,z1) = E.
  * Arrays of segments are dense, 24 bytes per segment, 4-byte aligned. */
@@ -58,7 +58,8 @@ typedef enum vox_status {
     VOX_ERR_OUT_OF_RANGE = 2,     /* an end point outside the output range */
     VOX_ERR_CAPACITY = 3,         /* voxel list larger than the capacity   */
     VOX_ERR_DEVICE = 4,           /* a HIP runtime call failed             */
-    VOX_ERR_WORKSPACE = 5         /* workspace missing or too small        */
+    VOX_ERR_WORKSPACE = 5,        /* workspace missing or too small        */
+    VOX_ERR_BATCH_MISMATCH = 6    /* batch table does not fit its launch   */
 } vox_status;
 
 /* Grid flag: zero the whole bit-volume before setting voxels.  Without it
@@ -147,45 +148,72 @@ vox_status vox_get_tuning(vox_tuning *tuning);
 /* ---------------------------------------------------------------- batches */
 
 /* One scene of a batch: its own segments and its own bit-volume, with the
- * meaning of the vox_segments_to_grid arguments of the same names. */
+ * meaning of the vox_segments_to_grid arguments of the same names.  Batch
+ * scenes take the brick path: dim_x must be a multiple of 32 and every
+ * side at most 16384, with at most 16384 bricks per scene. */
 typedef struct vox_scene {
-    const vox_segment *segs; /* device */
+    const vox_segment *segs; /* device, 4-byte aligned; may be NULL if n == 0 */
     int64_t n;
     int32_t dim_x, dim_y, dim_z;
     uint32_t flags;          /* VOX_GRID_CLEAR or 0 */
-    uint32_t *grid;          /* device */
+    uint32_t *grid;          /* device, 16-byte aligned */
     int32_t *counts;         /* device, optional (NULL) */
 } vox_scene;
 
-/* Host-side planning of a batch: from the host array h_scenes[n_scenes]
- * (whose pointers are device pointers) build the device descriptor table
- * image in h_table (host memory, h_table_bytes long) and report the sizes
- * the launch needs.  The caller copies h_table to device memory d_table
- * (any way it likes) before vox_batch_scenes runs.  Pass h_table = NULL to
- * query *table_bytes and *work_bytes only.  No device call is made. */
+/* Launch shape of a batch: the kernels are sized by these values, and a
+ * table fits a launch when its own values stay within them (same brick
+ * shape).  Filled in by vox_batch_plan; vox_batch_launch_cover widens one
+ * launch to cover another, so one captured graph can serve several tables. */
+typedef struct vox_batch_launch {
+    int64_t rows;                 /* histogram workgroups                  */
+    int64_t bricks;               /* bricks over all scenes                */
+    int32_t brick_lg[3];          /* brick shape (log2 voxels per axis)     */
+    int32_t max_scene_bricks;     /* largest per-scene brick count         */
+    uint64_t work_bytes;          /* workspace bytes the launch needs      */
+    uint64_t table_bytes;         /* bytes of the table image              */
+} vox_batch_launch;
+
+/* Host-side planning of a batch (no device call is made).  From the host
+ * array h_scenes[n_scenes] (n_scenes >= 1; its pointers are device
+ * pointers) build the table image in h_table (host memory, h_table_bytes
+ * long) and describe the launch in *launch.  Pass h_table = NULL to fill
+ * *launch only (launch->table_bytes is the size to provide).  The brick
+ * shape is the process-wide tuning if set, else the default of the largest
+ * scene.  The caller copies the image to device memory (any way it likes,
+ * 16-byte aligned) before vox_batch_scenes runs; the copy must stay valid
+ * until the batch's kernels have finished.
+ * Host-checked errors: the vox_segments_to_grid argument rules per scene
+ * (VOX_ERR_INVALID_ARGUMENT, with the scene index in vox_last_error), a
+ * volume the brick path cannot take, h_table_bytes too small, totals beyond
+ * 2^32 - 1 bricks or pieces. */
 vox_status vox_batch_plan(const vox_scene *h_scenes, int32_t n_scenes,
                           void *h_table, size_t h_table_bytes,
-                          size_t *table_bytes, size_t *work_bytes);
+                          vox_batch_launch *launch);
 
-/* All scenes of a planned batch in one persistent, work-stealing launch
- * sequence (the paper's advice to cut the number of kernel calls and load
- * the GPU with many segments at once, Section 5, conclusions 3 and 4).
- * Every scene's grid (and counts) ends up exactly as a separate
- * vox_segments_to_grid call would leave it.
+/* Grows *bound so that every table fitting *launch also fits *bound
+ * (element-wise maximum).  VOX_ERR_INVALID_ARGUMENT if the brick shapes
+ * differ (a zeroed *bound takes the shape of *launch). */
+vox_status vox_batch_launch_cover(vox_batch_launch *bound, const vox_batch_launch *launch);
+
+/* All scenes of a planned batch in one launch sequence of the grid
+ * kernels, each kernel a single launch over every scene (the paper's advice
+ * to cut the number of kernel calls and load the GPU with many segments at
+ * once, Section 5, conclusions), with the bricks of all scenes taken from
+ * one work-stealing counter by persistent workgroups.  Every scene's grid
+ * (and counts) ends up exactly as a separate vox_segments_to_grid call
+ * would leave it; the device status word covers all scenes.
  *
- *   d_table    device copy of the table built by vox_batch_plan.
- *   d_work     workspace, >= the work_bytes reported by vox_batch_plan.
- *   max_scenes, max_segments, max_bricks
- *              launch-shape bounds: the call is valid for any table whose
- *              scene count, total segment count and total brick count
- *              (reported in the table header) stay within them.
+ *   d_table    device copy of a table image from vox_batch_plan.
+ *   launch     launch shape (host struct): the plan's own, or a cover of
+ *              several plans.
+ *   d_work     workspace, >= launch->work_bytes, 256-byte aligned.
  *
- * The call reads nothing on the host, synchronises nothing and allocates
+ * Reads no device memory on the host, synchronises nothing and allocates
  * nothing, so it can be captured into a HIP graph once and replayed after
- * the caller rewrites d_table (same address) with another batch that fits
- * the bounds and the workspace. */
-vox_status vox_batch_scenes(const void *d_table, int32_t max_scenes,
-                            int64_t max_segments, int64_t max_bricks,
+ * the caller rewrites d_table (same address) with another table that fits
+ * `launch`.  Device-checked: a table that does not fit the launch or the
+ * workspace writes nothing and sets VOX_ERR_BATCH_MISMATCH. */
+vox_status vox_batch_scenes(const void *d_table, const vox_batch_launch *launch,
                             void *d_work, size_t work_bytes, void *stream);
 
 /* -------------------------------------------------------------- utilities */
@@ -208,9 +236,9 @@ int vox_abi_version(void);
 
 /* Tracing of the library's own kernels.  While enabled, each kernel launch
  * of every entry point is bracketed by two HIP events recorded on the
- * launch's stream, and its duration is added to a per-kernel record.  Do
- * not enable it while a stream is being captured into a graph.  Process-wide
- * and thread-safe. */
+ * launch's stream, and its duration is added to a per-kernel record.
+ * Launches made while their stream is being captured into a graph are not
+ * timed.  Process-wide and thread-safe. */
 vox_status vox_profile_enable(int enable);
 
 /* Drops all records (after waiting for pending events). */

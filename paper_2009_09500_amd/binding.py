@@ -26,6 +26,7 @@ VOX_ERR_OUT_OF_RANGE = 2
 VOX_ERR_CAPACITY = 3
 VOX_ERR_DEVICE = 4
 VOX_ERR_WORKSPACE = 5
+VOX_ERR_BATCH_MISMATCH = 6
 VOX_GRID_CLEAR = 1
 
 _lib = None
@@ -58,6 +59,24 @@ class VoxScene(ctypes.Structure):
     ]
 
 
+class VoxBatchLaunch(ctypes.Structure):
+    """struct vox_batch_launch of include/vox.h."""
+    _fields_ = [
+        ("rows", ctypes.c_int64),
+        ("bricks", ctypes.c_int64),
+        ("brick_lg", ctypes.c_int32 * 3),
+        ("max_scene_bricks", ctypes.c_int32),
+        ("work_bytes", ctypes.c_uint64),
+        ("table_bytes", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"rows": int(self.rows), "bricks": int(self.bricks),
+                "brick_lg": tuple(int(v) for v in self.brick_lg),
+                "max_scene_bricks": int(self.max_scene_bricks),
+                "work_bytes": int(self.work_bytes), "table_bytes": int(self.table_bytes)}
+
+
 def load(path: str | None = None):
     """Load libvox.so (built by `python -m paper_2009_09500_amd.build`)."""
     global _lib
@@ -84,9 +103,12 @@ def load(path: str | None = None):
     lib.vox_grid_workspace_bytes.restype = sz
     lib.vox_segments_to_grid.argtypes = [P, i64, i32, i32, i32, P, P, u32, P, sz, P]
     lib.vox_segments_to_grid.restype = ctypes.c_int
-    lib.vox_batch_plan.argtypes = [P, i32, P, sz, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    LP = ctypes.POINTER(VoxBatchLaunch)
+    lib.vox_batch_plan.argtypes = [ctypes.POINTER(VoxScene), i32, P, sz, LP]
     lib.vox_batch_plan.restype = ctypes.c_int
-    lib.vox_batch_scenes.argtypes = [P, i32, i64, i64, P, sz, P]
+    lib.vox_batch_launch_cover.argtypes = [LP, LP]
+    lib.vox_batch_launch_cover.restype = ctypes.c_int
+    lib.vox_batch_scenes.argtypes = [P, LP, P, sz, P]
     lib.vox_batch_scenes.restype = ctypes.c_int
     lib.vox_read_status.argtypes = [P, ctypes.POINTER(i32), P]
     lib.vox_read_status.restype = ctypes.c_int
@@ -172,6 +194,52 @@ def vox_segments_to_grid(segs, dims, grid, counts, flags: int, work, stream=None
     st = lib.vox_segments_to_grid(_ptr(segs), segs.shape[0], dx, dy, dz, _ptr(grid), _ptr(counts),
                                   int(flags), _ptr(work), work.numel() * work.element_size(),
                                   _stream(stream))
+    _check(lib, st)
+
+
+def _scene_array(scenes):
+    """ctypes array of vox_scene from (segs, dims, grid, counts, flags) tuples
+    of device tensors (counts may be None)."""
+    arr = (VoxScene * len(scenes))()
+    for i, (segs, dims, grid, counts, flags) in enumerate(scenes):
+        _check_segs(segs)
+        sc = arr[i]
+        sc.segs = segs.data_ptr() if segs.shape[0] > 0 else 0
+        sc.n = segs.shape[0]
+        sc.dim_x, sc.dim_y, sc.dim_z = (int(d) for d in dims)
+        sc.flags = int(flags)
+        sc.grid = grid.data_ptr()
+        sc.counts = counts.data_ptr() if counts is not None else 0
+    return arr
+
+
+def vox_batch_plan(scenes):
+    """Plans a batch of (segs, dims, grid, counts, flags) scenes.  Returns
+    (table image as a numpy uint8 array, VoxBatchLaunch)."""
+    import numpy as np
+    lib = load()
+    arr = _scene_array(scenes)
+    launch = VoxBatchLaunch()
+    _check(lib, lib.vox_batch_plan(arr, len(scenes), None, 0, ctypes.byref(launch)))
+    table = np.zeros(int(launch.table_bytes), dtype=np.uint8)
+    _check(lib, lib.vox_batch_plan(arr, len(scenes), ctypes.c_void_p(table.ctypes.data),
+                                   table.nbytes, ctypes.byref(launch)))
+    return table, launch
+
+
+def vox_batch_launch_cover(bound: VoxBatchLaunch, launch: VoxBatchLaunch) -> VoxBatchLaunch:
+    """Widens `bound` in place to cover `launch`; returns it."""
+    lib = load()
+    _check(lib, lib.vox_batch_launch_cover(ctypes.byref(bound), ctypes.byref(launch)))
+    return bound
+
+
+def vox_batch_scenes(d_table, launch: VoxBatchLaunch, work, stream=None):
+    """Runs a planned batch; d_table is a device uint8 tensor holding the
+    table image."""
+    lib = load()
+    st = lib.vox_batch_scenes(_ptr(d_table), ctypes.byref(launch), _ptr(work),
+                              work.numel() * work.element_size(), _stream(stream))
     _check(lib, st)
 
 
@@ -267,3 +335,23 @@ def segments_to_grid(segs, dims, grid=None, want_counts: bool = False, stream=No
     if status != VOX_OK:
         raise VoxError(status, load().vox_status_string(status).decode())
     return (grid, counts) if want_counts else grid
+
+
+def batch_to_grids(scenes, stream=None):
+    """Cleared bit-volumes of several scenes in one batched launch sequence.
+    `scenes` holds (segs, dims) pairs of device tensors; returns the grids
+    (int32 storage of the packed words)."""
+    import torch
+    if not scenes:
+        return []
+    dev = scenes[0][0].device
+    grids = [torch.empty(grid_words(d), dtype=torch.int32, device=dev) for _, d in scenes]
+    table, launch = vox_batch_plan([(s, d, g, None, VOX_GRID_CLEAR)
+                                    for (s, d), g in zip(scenes, grids)])
+    d_table = torch.from_numpy(table).to(dev)
+    work = workspace(launch.work_bytes, dev)
+    vox_batch_scenes(d_table, launch, work, stream=stream)
+    status = vox_read_status(work, stream=stream)
+    if status != VOX_OK:
+        raise VoxError(status, load().vox_status_string(status).decode())
+    return grids

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "vox.h"
 #include "vox_internal.h"
@@ -93,6 +94,7 @@ const char* vox_status_string(vox_status status) {
         case VOX_ERR_CAPACITY: return "voxel list exceeds capacity";
         case VOX_ERR_DEVICE: return "HIP runtime error";
         case VOX_ERR_WORKSPACE: return "workspace missing or too small";
+        case VOX_ERR_BATCH_MISMATCH: return "batch table does not fit its launch or workspace";
     }
     return "unknown status";
 }
@@ -188,25 +190,132 @@ vox_status vox_segments_to_grid(const vox_segment* d_segs, int64_t n, int32_t di
     if (work_bytes < need) return fail(VOX_ERR_WORKSPACE, "workspace %zu bytes, need %zu", work_bytes, need);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
-    vox::GridWork w = vox::grid_workspace(d_work, n, dim_x, dim_y, dim_z);
+    vox::GridWork w = vox::grid_workspace(d_work, work_bytes, n, dim_x, dim_y, dim_z);
     hipError_t e = vox::launch_grid(reinterpret_cast<const int32_t*>(d_segs), n, aligned(d_segs, 8),
                                     dim_x, dim_y, dim_z, d_grid, d_counts, flags, w, s);
     if (e != hipSuccess) return device_fail(e, "grid");
     return ok();
 }
 
-vox_status vox_batch_plan(const vox_scene* h_scenes, int32_t n_scenes, void* h_table,
-                          size_t h_table_bytes, size_t* table_bytes, size_t* work_bytes) {
-    (void)h_scenes; (void)n_scenes; (void)h_table; (void)h_table_bytes; (void)table_bytes;
-    (void)work_bytes;
-    return fail(VOX_ERR_INVALID_ARGUMENT, "vox_batch_plan: not available in this build");
+vox_status vox_batch_plan(const vox_scene* h_scenes, int32_t n_scenes, void* h_table, size_t h_table_bytes,
+                          vox_batch_launch* launch) {
+    if (launch == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "launch is NULL");
+    if (n_scenes < 1 || h_scenes == nullptr)
+        return fail(VOX_ERR_INVALID_ARGUMENT, "need h_scenes with n_scenes >= 1");
+    // Brick shape: the tuning if set, else the default of the largest volume.
+    int lg[3];
+    vox::tuned_brick_lg(lg);
+    if (lg[0] == 0) {
+        int64_t best = -1;
+        for (int32_t i = 0; i < n_scenes; ++i) {
+            const vox_scene& sc = h_scenes[i];
+            const int64_t v = (int64_t)sc.dim_x * sc.dim_y * sc.dim_z;
+            if (v > best) {
+                best = v;
+                vox::default_brick_lg(sc.dim_x, sc.dim_y, sc.dim_z, lg);
+            }
+        }
+    }
+    std::vector<vox::BrickScene> scenes((size_t)n_scenes);
+    for (int32_t i = 0; i < n_scenes; ++i) {
+        const vox_scene& in = h_scenes[i];
+        if (in.n < 0 || in.n > (int64_t(1) << 31) - 2)
+            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: n must lie in [0, 2^31 - 2]", i);
+        if (in.n > 0 && in.segs == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: segs is NULL", i);
+        if (in.segs && !aligned(in.segs, 4))
+            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: segs not 4-byte aligned", i);
+        if (check_dims(in.dim_x, in.dim_y, in.dim_z) != VOX_OK)
+            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: %s", i, g_last_error);
+        if (in.grid == nullptr || !aligned(in.grid, 16))
+            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: grid NULL or not 16-byte aligned", i);
+        if (in.counts && !aligned(in.counts, 4))
+            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: counts not 4-byte aligned", i);
+        if (in.flags & ~VOX_GRID_CLEAR) return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: unknown flag bits", i);
+        vox::BrickScene& sc = scenes[(size_t)i];
+        if (!vox::brick_geometry_for(in.dim_x, in.dim_y, in.dim_z, lg, sc.bg))
+            return fail(VOX_ERR_INVALID_ARGUMENT,
+                        "scene %d: volume %d x %d x %d cannot take bricks of 2^%d x 2^%d x 2^%d (dim_x a multiple "
+                        "of 32, sides <= 16384, <= 16384 bricks)",
+                        i, in.dim_x, in.dim_y, in.dim_z, lg[0], lg[1], lg[2]);
+        sc.segs = reinterpret_cast<const int32_t*>(in.segs);
+        sc.counts = in.counts;
+        sc.grid = in.grid;
+        sc.n = in.n;
+        sc.flags = ((in.flags & VOX_GRID_CLEAR) ? vox::kSceneClear : 0u) |
+                   (aligned(in.segs, 8) ? vox::kSceneAligned8 : 0u);
+    }
+    vox::BrickTable t{};
+    for (int a = 0; a < 3; ++a) t.lg[a] = lg[a];
+    if (!vox::brick_table_layout(t, scenes.data(), (uint32_t)n_scenes))
+        return fail(VOX_ERR_INVALID_ARGUMENT, "batch too large: more than 2^32 - 1 bricks or pieces");
+    launch->rows = t.rows;
+    launch->bricks = t.bricks;
+    for (int a = 0; a < 3; ++a) launch->brick_lg[a] = lg[a];
+    launch->max_scene_bricks = (int32_t)t.max_nb;
+    launch->work_bytes = t.work_bytes;
+    launch->table_bytes = t.table_bytes;
+    if (h_table == nullptr) return ok();
+    if (h_table_bytes < t.table_bytes)
+        return fail(VOX_ERR_INVALID_ARGUMENT, "h_table holds %zu bytes, the table needs %llu", h_table_bytes,
+                    (unsigned long long)t.table_bytes);
+    uint8_t* out = static_cast<uint8_t*>(h_table);
+    std::memset(out, 0, (size_t)t.table_bytes);
+    std::memcpy(out, &t, sizeof(t));
+    std::memcpy(out + vox::kTableScenes, scenes.data(), scenes.size() * sizeof(vox::BrickScene));
+    if (n_scenes > 1) {
+        uint32_t* row_scene = reinterpret_cast<uint32_t*>(out + vox::kTableScenes +
+                                                          scenes.size() * sizeof(vox::BrickScene));
+        uint32_t* brick_scene = row_scene + t.rows;
+        for (int32_t i = 0; i < n_scenes; ++i) {
+            const vox::BrickScene& sc = scenes[(size_t)i];
+            for (uint32_t r = 0; r < sc.rows; ++r) row_scene[sc.row_base + r] = (uint32_t)i;
+            for (uint32_t b = 0; b < sc.bg.nbricks; ++b) brick_scene[sc.brick_base + b] = (uint32_t)i;
+        }
+    }
+    return ok();
 }
 
-vox_status vox_batch_scenes(const void* d_table, int32_t max_scenes, int64_t max_segments,
-                            int64_t max_bricks, void* d_work, size_t work_bytes, void* stream) {
-    (void)d_table; (void)max_scenes; (void)max_segments; (void)max_bricks; (void)d_work;
-    (void)work_bytes; (void)stream;
-    return fail(VOX_ERR_INVALID_ARGUMENT, "vox_batch_scenes: not available in this build");
+vox_status vox_batch_launch_cover(vox_batch_launch* bound, const vox_batch_launch* launch) {
+    if (bound == nullptr || launch == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "NULL argument");
+    const bool empty = bound->brick_lg[0] == 0 && bound->brick_lg[1] == 0 && bound->brick_lg[2] == 0;
+    if (!empty && (bound->brick_lg[0] != launch->brick_lg[0] || bound->brick_lg[1] != launch->brick_lg[1] ||
+                   bound->brick_lg[2] != launch->brick_lg[2]))
+        return fail(VOX_ERR_INVALID_ARGUMENT, "brick shapes differ");
+    for (int a = 0; a < 3; ++a) bound->brick_lg[a] = launch->brick_lg[a];
+    if (launch->rows > bound->rows) bound->rows = launch->rows;
+    if (launch->bricks > bound->bricks) bound->bricks = launch->bricks;
+    if (launch->max_scene_bricks > bound->max_scene_bricks) bound->max_scene_bricks = launch->max_scene_bricks;
+    if (launch->work_bytes > bound->work_bytes) bound->work_bytes = launch->work_bytes;
+    if (launch->table_bytes > bound->table_bytes) bound->table_bytes = launch->table_bytes;
+    return ok();
+}
+
+vox_status vox_batch_scenes(const void* d_table, const vox_batch_launch* launch, void* d_work, size_t work_bytes,
+                            void* stream) {
+    if (d_table == nullptr || !aligned(d_table, 16))
+        return fail(VOX_ERR_INVALID_ARGUMENT, "d_table NULL or not 16-byte aligned");
+    if (launch == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "launch is NULL");
+    if (launch->rows < 1 || launch->rows >= (int64_t(1) << 31) || launch->bricks < 1 ||
+        launch->bricks >= 0xFFFFFFFFll || launch->max_scene_bricks < 1 ||
+        launch->max_scene_bricks > (int32_t)vox::kMaxBricks)
+        return fail(VOX_ERR_INVALID_ARGUMENT, "launch sizes out of range (use vox_batch_plan)");
+    if (!vox::brick_shape_supported(launch->brick_lg))
+        return fail(VOX_ERR_INVALID_ARGUMENT, "brick shape 2^%d x 2^%d x 2^%d has no compiled kernel",
+                    launch->brick_lg[0], launch->brick_lg[1], launch->brick_lg[2]);
+    if (d_work == nullptr || !aligned(d_work, vox::kAlign))
+        return fail(VOX_ERR_WORKSPACE, "d_work NULL or not 256-byte aligned");
+    if (work_bytes < launch->work_bytes)
+        return fail(VOX_ERR_WORKSPACE, "workspace %zu bytes, the launch needs %llu", work_bytes,
+                    (unsigned long long)launch->work_bytes);
+    vox::BrickLaunch L;
+    L.rows = (uint32_t)launch->rows;
+    L.bricks = (uint32_t)launch->bricks;
+    for (int a = 0; a < 3; ++a) L.lg[a] = launch->brick_lg[a];
+    L.max_nb = (uint32_t)launch->max_scene_bricks;
+    hipError_t e = vox::launch_bricks(d_table, L, nullptr, nullptr, d_work, work_bytes,
+                                      static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_fail(e, "batch");
+    return ok();
 }
 
 vox_status vox_read_status(const void* d_work, int32_t* h_status, void* stream) {
@@ -217,7 +326,8 @@ vox_status vox_read_status(const void* d_work, int32_t* h_status, void* stream) 
     hipError_t e = hipMemcpyAsync(&raw, d_work, sizeof(raw), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(e, "read status");
-    if (raw & vox::kStatusOutOfRange) *h_status = VOX_ERR_OUT_OF_RANGE;
+    if (raw & vox::kStatusLaunch) *h_status = VOX_ERR_BATCH_MISMATCH;
+    else if (raw & vox::kStatusOutOfRange) *h_status = VOX_ERR_OUT_OF_RANGE;
     else if (raw & vox::kStatusCapacity) *h_status = VOX_ERR_CAPACITY;
     else *h_status = VOX_OK;
     return ok();

@@ -11,8 +11,15 @@
 // brick form a single k-interval, and the brick changes exactly when one
 // coordinate crosses a brick boundary (exact helpers in vox_exact.h).
 //
-// Pipeline (one stream, no host synchronisation):
-//   init      status word and work counter to zero
+// Every kernel reads its volumes from a scene table (BrickTable followed by
+// BrickScene entries): a plain call is a table of one scene, written into
+// the workspace by the init kernel; a batch is a table of many scenes built
+// on the host, whose bricks and histogram rows are numbered globally so that
+// each kernel below is still one launch for the whole batch.
+//
+// Pipeline (one stream, no host synchronisation, no allocation):
+//   init      status word and work counter to zero; checks that the table
+//             fits the launch and the workspace
 //   hist      per segment: count N+1, range check, walk its bricks and count
 //             pieces per brick in an LDS histogram; one histogram row per
 //             workgroup
@@ -59,17 +66,102 @@ __device__ __forceinline__ uint32_t block_exclusive_sum_lds(uint32_t v, uint32_t
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Global-memory views: volume pointers come from the scene table, so the
+// compiler cannot infer their address space; without these casts it emits
+// flat stores, which also count against the LDS wait counter.
+typedef __attribute__((address_space(1))) u32x4 global_u32x4;
+typedef __attribute__((address_space(1))) uint32_t global_u32;
 
 typedef int16_t i16x2 __attribute__((ext_vector_type(2)));
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void k_brick_init(int32_t* status, uint32_t* work_counter) {
-    if (threadIdx.x == 0) {
-        *status = 0;
-        *work_counter = 0;
+__host__ __device__ constexpr uint64_t up256(uint64_t v) { return (v + 255u) & ~uint64_t(255); }
+
+// Piece record (16 bytes): start point, direction and the k-window inside
+// its brick; everything the fill needs, so it reads records and never
+// gathers segments.
+struct Piece {
+    uint16_t p0[3];
+    int16_t d[3];
+    uint16_t klo, khi;  // inclusive
+};
+static_assert(sizeof(Piece) == 16, "16-byte piece records");
+
+// Sections of the workspace (layout in vox_internal.h).
+struct WorkView {
+    int32_t* status;
+    uint32_t* counter;
+    uint32_t* ok;
+    uint32_t* hist;
+    uint32_t* totals;
+    uint32_t* bin_base;
+    Piece* recs;
+};
+
+__host__ __device__ inline WorkView work_view(uint8_t* work, uint64_t hist_words, uint32_t bricks) {
+    WorkView v;
+    v.status = reinterpret_cast<int32_t*>(work);
+    v.counter = reinterpret_cast<uint32_t*>(work + 4);
+    v.ok = reinterpret_cast<uint32_t*>(work + 8);
+    uint8_t* p = work + kWorkData;
+    v.hist = reinterpret_cast<uint32_t*>(p);
+    p += up256(hist_words * 4u);
+    v.totals = reinterpret_cast<uint32_t*>(p);
+    p += up256((uint64_t)bricks * 4u);
+    v.bin_base = reinterpret_cast<uint32_t*>(p);
+    p += up256(((uint64_t)bricks + 1u) * 4u);
+    v.recs = reinterpret_cast<Piece*>(p);
+    return v;
+}
+
+size_t brick_work_bytes(uint64_t hist_words, uint32_t bricks, uint64_t pieces) {
+    return (size_t)(kWorkData + up256(hist_words * 4u) + up256((uint64_t)bricks * 4u) +
+                    up256(((uint64_t)bricks + 1u) * 4u) + pieces * sizeof(Piece));
+}
+
+// The scene table as the kernels see it.
+struct TableView {
+    BrickTable h;
+    const BrickScene* scenes;
+    const uint32_t* row_scene;    // null with one scene
+    const uint32_t* brick_scene;  // null with one scene
+};
+
+__device__ __forceinline__ TableView table_view(const uint8_t* table) {
+    TableView v;
+    v.h = *reinterpret_cast<const BrickTable*>(table);
+    v.scenes = reinterpret_cast<const BrickScene*>(table + kTableScenes);
+    if (v.h.n_scenes > 1) {
+        v.row_scene = reinterpret_cast<const uint32_t*>(v.scenes + v.h.n_scenes);
+        v.brick_scene = v.row_scene + v.h.rows;
+    } else {
+        v.row_scene = v.brick_scene = nullptr;
     }
+    return v;
+}
+
+// Status word, work counter and the launch check: the table must come from
+// the planner, fit the launch bounds the kernels were sized for, and fit the
+// workspace; otherwise every later kernel returns at once and the status
+// says so.  A plain call passes its one-scene table by value and it is
+// written into the workspace here.
+__global__ void k_brick_init(BrickTable one_t, BrickScene one_s, uint32_t has_one, const uint8_t* table,
+                             uint8_t* work, uint64_t work_bytes, BrickLaunch L) {
+    if (threadIdx.x != 0) return;
+    if (has_one) {
+        *reinterpret_cast<BrickTable*>(work + kWorkTable) = one_t;
+        *reinterpret_cast<BrickScene*>(work + kWorkTable + kTableScenes) = one_s;
+    }
+    const BrickTable t = has_one ? one_t : *reinterpret_cast<const BrickTable*>(table);
+    const bool ok = t.magic == kTableMagic && t.n_scenes >= 1 && t.rows <= L.rows && t.bricks <= L.bricks &&
+                    t.max_nb <= L.max_nb && t.lg[0] == L.lg[0] && t.lg[1] == L.lg[1] && t.lg[2] == L.lg[2] &&
+                    t.work_bytes <= work_bytes;
+    int32_t* w = reinterpret_cast<int32_t*>(work);
+    w[0] = ok ? 0 : kStatusLaunch;  // status
+    w[1] = 0;                       // work counter
+    w[2] = ok ? 1 : 0;              // launch ok
 }
 
 // Segment range of histogram/scatter workgroup g.
@@ -114,8 +206,7 @@ __device__ __forceinline__ uint32_t order_bin(const StagedSeg& g, const BrickGeo
 // Loads segments [base, base + cnt) into the stage (all threads of the
 // block), writes counts, flags out-of-volume segments, and builds the order
 // of the in-volume ones.
-template <bool kAligned8>
-__device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs, int64_t base, uint32_t cnt,
+__device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs, bool a8, int64_t base, uint32_t cnt,
                                                const BrickGeom& bg, Stage& st, int32_t* __restrict__ counts,
                                                bool& bad) {
     if (threadIdx.x < kOrderBins) st.bins[threadIdx.x] = 0;
@@ -124,7 +215,7 @@ __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs,
     uint32_t mine = 0;
     int slot = 0;
     for (uint32_t t = threadIdx.x; t < cnt; t += kHistBlock, ++slot) {
-        const Seg g = load_seg<kAligned8>(segs, base + t);
+        const Seg g = a8 ? load_seg<true>(segs, base + t) : load_seg<false>(segs, base + t);
         if (counts) {
             const int64_t c = seg_length(g) + 1;
             counts[base + t] = (int32_t)(c > 0x7FFFFFFFll ? 0x7FFFFFFFll : c);
@@ -221,27 +312,32 @@ __device__ __forceinline__ void walk_ordered(const Stage& st, const BrickGeom& b
     }
 }
 
-template <bool kAligned8>
-__global__ __launch_bounds__(kHistBlock) void k_brick_hist(const int32_t* __restrict__ segs, int64_t n,
-                                                           BrickGeom bg, uint32_t* __restrict__ hist,
-                                                           int32_t* __restrict__ counts,
-                                                           int32_t* __restrict__ status) {
+__global__ __launch_bounds__(kHistBlock) void k_brick_hist(const uint8_t* __restrict__ table,
+                                                           uint8_t* __restrict__ work) {
     extern __shared__ uint32_t lh[];
     __shared__ Stage st;
+    const TableView tv = table_view(table);
+    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
+    const uint32_t r = blockIdx.x;
+    if (*wv.ok == 0 || r >= tv.h.rows) return;
+    const BrickScene sc = tv.scenes[tv.row_scene ? tv.row_scene[r] : 0u];
+    const BrickGeom& bg = sc.bg;
     const uint32_t NB = bg.nbricks;
+    const uint32_t g = r - sc.row_base;
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) lh[b] = 0;
     int64_t lo, hi;
-    seg_range(n, blockIdx.x, gridDim.x, lo, hi);
+    seg_range(sc.n, (int)g, (int)sc.rows, lo, hi);
+    const bool a8 = (sc.flags & kSceneAligned8) != 0;
     bool bad = false;
     for (int64_t base = lo; base < hi; base += kStage) {
         const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
-        stage_segments<kAligned8>(segs, base, cnt, bg, st, counts, bad);
+        stage_segments(sc.segs, a8, base, cnt, bg, st, sc.counts, bad);
         walk_ordered(st, bg, [&](uint32_t b, uint32_t, uint32_t, uint32_t) { atomicAdd(&lh[b], 1u); });
         lds_barrier();
     }
-    if (bad) atomicOr(status, kStatusOutOfRange);
+    if (bad) atomicOr(wv.status, kStatusOutOfRange);
     lds_barrier();
-    uint32_t* row = hist + (size_t)blockIdx.x * NB;
+    uint32_t* row = wv.hist + sc.hist_off + (size_t)g * NB;
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) row[b] = lh[b];
 }
 
@@ -249,21 +345,37 @@ constexpr int kColBins = 64;
 constexpr int kColSplit = 4;  // row chunks per brick
 constexpr int kColRows = (kHistRows + kColSplit - 1) / kColSplit;
 
-// Block of 256 threads = 64 bricks x 4 row chunks: per brick, exclusive
-// prefix of hist[g][b] over the G rows (in place) and the brick total.
-__global__ __launch_bounds__(256) void k_brick_colscan(uint32_t* __restrict__ hist, int G, uint32_t NB,
-                                                       uint32_t* __restrict__ totals) {
+// Block of 256 threads = 64 global bricks x 4 row chunks: per brick,
+// exclusive prefix of its scene's histogram column over the scene's rows
+// (in place) and the brick total.
+__global__ __launch_bounds__(256) void k_brick_colscan(const uint8_t* __restrict__ table,
+                                                       uint8_t* __restrict__ work) {
     __shared__ uint32_t part[kColSplit][kColBins];
+    const TableView tv = table_view(table);
+    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
+    if (*wv.ok == 0) return;
     const int bl = threadIdx.x % kColBins;
     const int ch = threadIdx.x / kColBins;
-    const uint32_t b = blockIdx.x * kColBins + bl;
+    const uint32_t gb = blockIdx.x * kColBins + bl;
+    const bool valid = gb < tv.h.bricks;
+    uint32_t b = 0, NB = 0;
+    int G = 0;
+    uint64_t off = 0;
+    if (valid) {
+        const BrickScene& sc = tv.scenes[tv.brick_scene ? tv.brick_scene[gb] : 0u];
+        b = gb - sc.brick_base;
+        NB = sc.bg.nbricks;
+        G = (int)sc.rows;
+        off = sc.hist_off;
+    }
+    uint32_t* hist = wv.hist + off;
     const int g0 = ch * kColRows;
     uint32_t v[kColRows];
     uint32_t sum = 0;
 #pragma unroll
     for (int r = 0; r < kColRows; ++r) {
         const int g = g0 + r;
-        v[r] = (b < NB && g < G) ? hist[(size_t)g * NB + b] : 0u;
+        v[r] = (valid && g < G) ? hist[(size_t)g * NB + b] : 0u;
         sum += v[r];
     }
     part[ch][bl] = sum;
@@ -277,64 +389,66 @@ __global__ __launch_bounds__(256) void k_brick_colscan(uint32_t* __restrict__ hi
 #pragma unroll
     for (int r = 0; r < kColRows; ++r) {
         const int g = g0 + r;
-        if (b < NB && g < G) hist[(size_t)g * NB + b] = run;
+        if (valid && g < G) hist[(size_t)g * NB + b] = run;
         run += v[r];
     }
-    if (ch == 0 && b < NB) totals[b] = tot;
+    if (ch == 0 && valid) wv.totals[gb] = tot;
 }
 
 constexpr int kBaseBlock = 1024;
 
-// One block: bin_base[b] = sum of totals before b; bin_base[NB] = total.
-__global__ __launch_bounds__(kBaseBlock) void k_brick_base(const uint32_t* __restrict__ totals, uint32_t NB,
-                                                           uint32_t* __restrict__ bin_base) {
+// One block: bin_base[b] = sum of totals before global brick b;
+// bin_base[bricks] = total.
+__global__ __launch_bounds__(kBaseBlock) void k_brick_base(const uint8_t* __restrict__ table,
+                                                           uint8_t* __restrict__ work) {
     __shared__ uint32_t lds[kBaseBlock / kWave];
+    const TableView tv = table_view(table);
+    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
+    if (*wv.ok == 0) return;
+    const uint32_t NB = tv.h.bricks;
     uint32_t carry = 0;
     for (uint32_t c0 = 0; c0 < NB; c0 += kBaseBlock) {
-        uint32_t i = c0 + threadIdx.x;
-        uint32_t v = i < NB ? totals[i] : 0u;
+        const uint32_t i = c0 + threadIdx.x;
+        const uint32_t v = i < NB ? wv.totals[i] : 0u;
         uint32_t tot;
-        uint32_t ex = block_exclusive_sum<kBaseBlock>(v, lds, tot);
-        if (i < NB) bin_base[i] = carry + ex;
+        const uint32_t ex = block_exclusive_sum<kBaseBlock>(v, lds, tot);
+        if (i < NB) wv.bin_base[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) bin_base[NB] = carry;
+    if (threadIdx.x == 0) wv.bin_base[NB] = carry;
 }
 
-// Piece record (16 bytes): start point, direction and the k-window inside
-// its brick; everything the fill needs, so it reads records and never
-// gathers segments.
-struct Piece {
-    uint16_t p0[3];
-    int16_t d[3];
-    uint16_t klo, khi;  // inclusive
-};
-static_assert(sizeof(Piece) == 16, "16-byte piece records");
-
-template <bool kAligned8>
-__global__ __launch_bounds__(kHistBlock) void k_brick_scatter(const int32_t* __restrict__ segs, int64_t n,
-                                                              BrickGeom bg, const uint32_t* __restrict__ hist,
-                                                              const uint32_t* __restrict__ bin_base,
-                                                              Piece* __restrict__ recs) {
+__global__ __launch_bounds__(kHistBlock) void k_brick_scatter(const uint8_t* __restrict__ table,
+                                                              uint8_t* __restrict__ work) {
     extern __shared__ uint32_t cur[];
     __shared__ Stage st;
+    const TableView tv = table_view(table);
+    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
+    const uint32_t r = blockIdx.x;
+    if (*wv.ok == 0 || r >= tv.h.rows) return;
+    const BrickScene sc = tv.scenes[tv.row_scene ? tv.row_scene[r] : 0u];
+    const BrickGeom& bg = sc.bg;
     const uint32_t NB = bg.nbricks;
-    const uint32_t* row = hist + (size_t)blockIdx.x * NB;
-    for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) cur[b] = bin_base[b] + row[b];
+    const uint32_t g = r - sc.row_base;
+    const uint32_t* row = wv.hist + sc.hist_off + (size_t)g * NB;
+    const uint32_t* base_b = wv.bin_base + sc.brick_base;
+    for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) cur[b] = base_b[b] + row[b];
     int64_t lo, hi;
-    seg_range(n, blockIdx.x, gridDim.x, lo, hi);
+    seg_range(sc.n, (int)g, (int)sc.rows, lo, hi);
+    const bool a8 = (sc.flags & kSceneAligned8) != 0;
+    Piece* __restrict__ recs = wv.recs;
     bool bad = false;
     for (int64_t base = lo; base < hi; base += kStage) {
         const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
-        stage_segments<kAligned8>(segs, base, cnt, bg, st, nullptr, bad);
+        stage_segments(sc.segs, a8, base, cnt, bg, st, nullptr, bad);
         walk_ordered(st, bg, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j) {
             const uint32_t pos = atomicAdd(&cur[b], 1u);
-            const StagedSeg g = st.seg[j];
+            const StagedSeg sg = st.seg[j];
             Piece pc;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                pc.p0[ax] = g.p0[ax];
-                pc.d[ax] = (int16_t)((int32_t)g.p1[ax] - (int32_t)g.p0[ax]);
+                pc.p0[ax] = sg.p0[ax];
+                pc.d[ax] = (int16_t)((int32_t)sg.p1[ax] - (int32_t)sg.p0[ax]);
             }
             pc.klo = (uint16_t)klo;
             pc.khi = (uint16_t)khi;
@@ -373,9 +487,11 @@ __device__ __forceinline__ void divmod_rcp(uint32_t x, uint32_t y, float rcp, ui
 // The dominant axis moves by one voxel per step.  The two other axes keep
 // their error terms as biased 16-bit halves u = r - 2N + 32768 of one
 // register (r the remainder of eq. (3)'s division, so u in [32768-2N, 32768)):
-// adding 2a sets bit 15 exactly when that coordinate advances, the carry
-// bits then subtract 2N from their halves and add the axes' signed strides to
-// the bit index with one packed dot product.  Needs 2N <= 32768.
+// adding 2a sets bit 15 exactly when that coordinate advances.  An
+// arithmetic shift turns those bits into 0 / -1 halves, which subtract 2N
+// from their halves in one packed multiply-add and add the axes' signed
+// strides to the bit index in one packed dot product (with the strides
+// stored negated).  Needs 2N <= 32768.
 template <bool kFull, int kChunk, int LGX, int LGY>
 __device__ __forceinline__ void set_chunk(uint32_t* brick, const u32x4& rec, uint32_t k0, int len,
                                           const int32_t org[3]) {
@@ -417,45 +533,47 @@ __device__ __forceinline__ void set_chunk(uint32_t* brick, const u32x4& rec, uin
                   (pb + (negb ? -(int32_t)qb : (int32_t)qb) - ob) * (sb < 0 ? -sb : sb);
     u16x2 E = {(uint16_t)(ra + 32768u - two_n), (uint16_t)(rb + 32768u - two_n)};
     const u16x2 T = {(uint16_t)(2u * aa), (uint16_t)(2u * ab)};
-    const u16x2 M = {(uint16_t)(0u - two_n), (uint16_t)(0u - two_n)};
-    const i16x2 S = {(int16_t)sa, (int16_t)sb};
-    const u16x2 k15 = {15, 15};
+    const u16x2 N2 = {(uint16_t)two_n, (uint16_t)two_n};
+    const i16x2 S = {(int16_t)(-sa), (int16_t)(-sb)};
+    const i16x2 k15 = {15, 15};
     if constexpr (kFull) {
 #pragma unroll 8
         for (int k = 0; k < kChunk; ++k) {
             atomicOr(&brick[(uint32_t)idx >> 5], 1u << ((uint32_t)idx & 31u));
             E = E + T;
-            const u16x2 C = E >> k15;
-            E = E + C * M;
-            idx = __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, C), S, idx, false) + sm;
+            const i16x2 C = __builtin_bit_cast(i16x2, E) >> k15;  // -1 where the axis advances
+            E = E + __builtin_bit_cast(u16x2, C) * N2;
+            idx = __builtin_amdgcn_sdot2(C, S, idx, false) + sm;
         }
     } else {
         for (int k = 0; k < len; ++k) {
             atomicOr(&brick[(uint32_t)idx >> 5], 1u << ((uint32_t)idx & 31u));
             E = E + T;
-            const u16x2 C = E >> k15;
-            E = E + C * M;
-            idx = __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, C), S, idx, false) + sm;
+            const i16x2 C = __builtin_bit_cast(i16x2, E) >> k15;  // -1 where the axis advances
+            E = E + __builtin_bit_cast(u16x2, C) * N2;
+            idx = __builtin_amdgcn_sdot2(C, S, idx, false) + sm;
         }
     }
 }
 
 // Launch shape of the fill kernel per brick shape: threads, pieces per batch,
-// voxels per chunk, chunk-table capacity.  One workgroup per CU; a batch
-// holds (nearly) a whole brick so every wave gets many chunks between
-// barriers and the longest chunk is short next to a wave's share.
+// voxels per chunk, chunk-table capacity and workgroups per CU.  A 128 KiB
+// brick takes a whole CU (one workgroup of 1024 threads); 64 KiB bricks run
+// two workgroups of 512 threads per CU, so that one workgroup's barrier
+// phases and brick flush overlap the other's voxel work.
 template <int LGX, int LGY, int LGZ>
 struct FillCfg {
-    static constexpr int kBlock = 1024;
-    static constexpr int kBatch = (LGX + LGY + LGZ) >= 20 ? 1024 : 2048;
+    static constexpr bool kBig = (LGX + LGY + LGZ) >= 20;
+    static constexpr int kBlock = kBig ? 1024 : 512;
+    static constexpr int kBatch = kBig ? 1024 : 512;
     static constexpr int kChunk = 32;
     static constexpr int kCtab = 3 * kBatch;
+    static constexpr int kWgsPerCu = kBig ? 1 : 2;
 };
 
-template <int LGX, int LGY, int LGZ, bool kVec>
-__global__ __launch_bounds__((FillCfg<LGX, LGY, LGZ>::kBlock))
-void k_brick_fill(BrickGeom bg, const Piece* __restrict__ recs, const uint32_t* __restrict__ bin_base,
-                  uint32_t* __restrict__ grid, uint32_t clear, uint32_t* __restrict__ work_counter) {
+template <int LGX, int LGY, int LGZ>
+__global__ __launch_bounds__((FillCfg<LGX, LGY, LGZ>::kBlock), (FillCfg<LGX, LGY, LGZ>::kWgsPerCu))
+void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work) {
     using Shape = BrickShape<LGX, LGY, LGZ>;
     using Cfg = FillCfg<LGX, LGY, LGZ>;
     constexpr int kBlock = Cfg::kBlock, kBatch = Cfg::kBatch, kChunk = Cfg::kChunk, kCtab = Cfg::kCtab;
@@ -477,10 +595,14 @@ void k_brick_fill(BrickGeom bg, const Piece* __restrict__ recs, const uint32_t* 
     __shared__ uint32_t tot_s, round_s, cut_s;
     __shared__ uint32_t next_s[3];
 
-    const uint32_t NB = bg.nbricks;
-    const int64_t row_words = (int64_t)bg.dim[0] >> 5;
+    const TableView tv = table_view(table);
+    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
+    if (*wv.ok == 0) return;
+    const uint32_t NB = tv.h.bricks;  // global bricks of all scenes
+    uint32_t* __restrict__ work_counter = wv.counter;
+    const uint32_t* __restrict__ bin_base = wv.bin_base;
     const uint32_t lane = __lane_id();
-    const u32x4* recv = reinterpret_cast<const u32x4*>(recs);
+    const u32x4* recv = reinterpret_cast<const u32x4*>(wv.recs);
     if (threadIdx.x < kChunk) lenc[0][threadIdx.x] = lenc[1][threadIdx.x] = 0;
     uint32_t set = 0;
 
@@ -516,9 +638,17 @@ void k_brick_fill(BrickGeom bg, const Piece* __restrict__ recs, const uint32_t* 
                 nhi = bin_base[nb + 1];
             }
         }
-        const int bx = (int)(b % (uint32_t)bg.nb[0]);
-        const int by = (int)((b / (uint32_t)bg.nb[0]) % (uint32_t)bg.nb[1]);
-        const int bz = (int)(b / ((uint32_t)bg.nb[0] * (uint32_t)bg.nb[1]));
+        // The brick's scene and its place in that scene's volume.
+        const uint32_t gb = __builtin_amdgcn_readfirstlane(b);
+        const BrickScene& sc = tv.scenes[tv.brick_scene ? tv.brick_scene[gb] : 0u];
+        const BrickGeom bg = sc.bg;
+        uint32_t* __restrict__ grid = sc.grid;
+        const bool clear = (sc.flags & kSceneClear) != 0;
+        const uint32_t lb = gb - sc.brick_base;
+        const int64_t row_words = (int64_t)bg.dim[0] >> 5;
+        const int bx = (int)(lb % (uint32_t)bg.nb[0]);
+        const int by = (int)((lb / (uint32_t)bg.nb[0]) % (uint32_t)bg.nb[1]);
+        const int bz = (int)(lb / ((uint32_t)bg.nb[0] * (uint32_t)bg.nb[1]));
         const int32_t org[3] = {bx << LGX, by << LGY, bz << LGZ};
         int32_t ext[3];
         {
@@ -656,16 +786,20 @@ void k_brick_fill(BrickGeom bg, const Piece* __restrict__ recs, const uint32_t* 
         // Flush: brick rows -> volume words.  The owner writes every word of
         // its brick, so a clearing call needs no other pass.
         const int rows = ext[1] * ext[2];
-        if constexpr (kVec) {
+        // Whole 16-byte units when the volume's rows hold whole brick rows.
+        const bool vec = Shape::kBXw % 4 == 0 && (bg.dim[0] & ((1 << LGX) - 1)) == 0;
+        if (vec) {
             // 16-byte units, Shape::kBXw / 4 per row, rows full width.
             constexpr int kUpr = Shape::kBXw / 4;
             const int units = rows * kUpr;
+            const bool full_y = ext[1] == (1 << LGY);  // rows per slab a power of two
             for (int t = threadIdx.x; t < units; t += kBlock) {
                 const int part = t % kUpr, r = t / kUpr;
-                const int y = r % ext[1], z = r / ext[1];
+                const int y = full_y ? (r & ((1 << LGY) - 1)) : r % ext[1];
+                const int z = full_y ? (r >> LGY) : r / ext[1];
                 const u32x4 v = *reinterpret_cast<const u32x4*>(
                     &brick[(((uint32_t)z << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + 4u * part]);
-                u32x4* dst = reinterpret_cast<u32x4*>(
+                global_u32x4* dst = (global_u32x4*)(
                     grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words + (org[0] >> 5) +
                     4 * part);
                 if (clear) {
@@ -681,7 +815,7 @@ void k_brick_fill(BrickGeom bg, const Piece* __restrict__ recs, const uint32_t* 
                 const int xw = t % xws, r = t / xws;
                 const int y = r % ext[1], z = r / ext[1];
                 const uint32_t v = brick[(((uint32_t)z << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + xw];
-                uint32_t* dst = grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words +
+                global_u32* dst = (global_u32*)grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words +
                                 (org[0] >> 5) + xw;
                 if (clear) *dst = v;
                 else *dst |= v;
@@ -693,7 +827,6 @@ void k_brick_fill(BrickGeom bg, const Piece* __restrict__ recs, const uint32_t* 
 
 // ---------------------------------------------------------------- host side
 
-
 // Brick shapes with a compiled fill kernel.
 static const int kShapes[][3] = {{8, 6, 5}, {8, 6, 6}, {7, 6, 6}, {7, 7, 6}};
 
@@ -703,124 +836,165 @@ bool brick_shape_supported(const int lg[3]) {
     return false;
 }
 
-void default_brick_lg(int32_t dx, int32_t dy, int32_t dz, int lg[3]) {
-    (void)dx; (void)dy; (void)dz;
-    lg[0] = 8;  // 256: 32-byte brick rows
-    lg[1] = 6;  // 64
-    lg[2] = 5;  // 32
+bool brick_geometry_for(int32_t dx, int32_t dy, int32_t dz, const int lg[3], BrickGeom& bg) {
+    return brick_geometry(dx, dy, dz, lg, bg);
 }
 
+// 256 x 64 x 64 bricks (128 KiB of LDS) when the volume still has at least
+// 4096 of them, i.e. 16 per CU for the work stealing to balance; otherwise
+// 256 x 64 x 32.  Rows of 256 voxels are 32 bytes, whole memory sectors.
+void default_brick_lg(int32_t dx, int32_t dy, int32_t dz, int lg[3]) {
+    const int64_t big = ((int64_t)(dx + 255) >> 8) * ((dy + 63) >> 6) * ((dz + 63) >> 6);
+    lg[0] = 8;
+    lg[1] = 6;
+    lg[2] = big >= 4096 ? 6 : 5;
+}
+
+// Worst case of pieces: every segment crossing every brick boundary of
+// every axis once.
 uint64_t max_pieces(int64_t n, const BrickGeom& bg) {
     return (uint64_t)n * (uint64_t)(1 + (bg.nb[0] - 1) + (bg.nb[1] - 1) + (bg.nb[2] - 1));
 }
 
-int hist_blocks(int64_t n) {
-    int64_t g = (n + 4095) / 4096;
+int hist_rows(int64_t n) {
+    int64_t g = (n + kSegsPerRow - 1) / kSegsPerRow;
     if (g > kHistRows) g = kHistRows;
     if (g < 1) g = 1;
     return (int)g;
 }
 
-size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg) {
-    const int G = hist_blocks(n);
-    size_t b = kAlign;                                                  // status, counter
-    b += align_up((size_t)G * bg.nbricks * sizeof(uint32_t));          // hist rows
-    b += align_up((size_t)bg.nbricks * sizeof(uint32_t));              // totals
-    b += align_up((size_t)(bg.nbricks + 1) * sizeof(uint32_t));        // bin base
-    b += align_up((size_t)max_pieces(n, bg) * sizeof(Piece));          // piece records
-    return b;
+bool brick_table_layout(BrickTable& t, BrickScene* scenes, uint32_t n_scenes) {
+    uint64_t rows = 0, bricks = 0, hist = 0, pieces = 0;
+    uint32_t max_nb = 0;
+    for (uint32_t i = 0; i < n_scenes; ++i) {
+        BrickScene& sc = scenes[i];
+        sc.rows = (uint32_t)hist_rows(sc.n);
+        sc.row_base = (uint32_t)rows;
+        sc.brick_base = (uint32_t)bricks;
+        sc.hist_off = hist;
+        rows += sc.rows;
+        bricks += sc.bg.nbricks;
+        hist += (uint64_t)sc.rows * sc.bg.nbricks;
+        pieces += max_pieces(sc.n, sc.bg);
+        max_nb = sc.bg.nbricks > max_nb ? sc.bg.nbricks : max_nb;
+        if (rows >= (1u << 31) || bricks >= 0xFFFFFFFFull || pieces >= 0xFFFFFFFFull) return false;
+    }
+    t.magic = kTableMagic;
+    t.n_scenes = n_scenes;
+    t.rows = (uint32_t)rows;
+    t.bricks = (uint32_t)bricks;
+    t.max_nb = max_nb;
+    t.hist_words = hist;
+    t.pieces = pieces;
+    t.work_bytes = brick_work_bytes(hist, (uint32_t)bricks, pieces);
+    t.table_bytes = kTableScenes + (uint64_t)n_scenes * sizeof(BrickScene) +
+                    (n_scenes > 1 ? 4u * (rows + bricks) : 0u);
+    return true;
 }
 
-template <int LGX, int LGY, int LGZ>
-static hipError_t launch_fill(const BrickGeom& bg, const Piece* recs, const uint32_t* bin_base, uint32_t* grid,
-                              uint32_t clear, uint32_t* counter, hipStream_t stream) {
-    using Shape = BrickShape<LGX, LGY, LGZ>;
-    constexpr int kBlock = FillCfg<LGX, LGY, LGZ>::kBlock;
-    const bool vec = (bg.dim[0] % (1 << LGX)) == 0 && Shape::kBXw % 4 == 0;
+size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg) {
+    return brick_work_bytes((uint64_t)hist_rows(n) * bg.nbricks, bg.nbricks, max_pieces(n, bg));
+}
+
+static int device_cus() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    int wgs = cus;
-    if ((uint32_t)wgs > bg.nbricks) wgs = (int)bg.nbricks;
-    if (vec)
-        k_brick_fill<LGX, LGY, LGZ, true><<<wgs, kBlock, 0, stream>>>(bg, recs, bin_base, grid, clear, counter);
-    else
-        k_brick_fill<LGX, LGY, LGZ, false><<<wgs, kBlock, 0, stream>>>(bg, recs, bin_base, grid, clear, counter);
+    return cus;
+}
+
+template <int LGX, int LGY, int LGZ>
+static hipError_t launch_fill(const uint8_t* table, uint8_t* work, uint32_t bricks, hipStream_t stream) {
+    constexpr int kBlock = FillCfg<LGX, LGY, LGZ>::kBlock;
+    int wgs = device_cus() * FillCfg<LGX, LGY, LGZ>::kWgsPerCu;
+    if ((uint32_t)wgs > bricks) wgs = (int)bricks;
+    k_brick_fill<LGX, LGY, LGZ><<<wgs, kBlock, 0, stream>>>(table, work);
     return hipGetLastError();
 }
 
-hipError_t launch_brick_grid(const int32_t* segs, int64_t n, bool aligned8, const BrickGeom& bg,
-                             uint32_t* grid, int32_t* counts, uint32_t flags, void* d_work,
-                             hipStream_t stream) {
-    const int G = hist_blocks(n);
-    uint8_t* p = static_cast<uint8_t*>(d_work);
-    int32_t* status = reinterpret_cast<int32_t*>(p);
-    uint32_t* counter = reinterpret_cast<uint32_t*>(p + 4);
-    p += kAlign;
-    uint32_t* hist = reinterpret_cast<uint32_t*>(p);
-    p += align_up((size_t)G * bg.nbricks * sizeof(uint32_t));
-    uint32_t* totals = reinterpret_cast<uint32_t*>(p);
-    p += align_up((size_t)bg.nbricks * sizeof(uint32_t));
-    uint32_t* bin_base = reinterpret_cast<uint32_t*>(p);
-    p += align_up((size_t)(bg.nbricks + 1) * sizeof(uint32_t));
-    Piece* recs = reinterpret_cast<Piece*>(p);
-    const size_t hist_lds = (size_t)bg.nbricks * sizeof(uint32_t);
+hipError_t launch_bricks(const void* d_table, const BrickLaunch& L, const BrickTable* one_table,
+                         const BrickScene* one_scene, void* d_work, size_t work_bytes, hipStream_t stream) {
+    if (L.rows < 1 || L.bricks < 1 || L.max_nb < 1 || L.max_nb > kMaxBricks || !brick_shape_supported(L.lg))
+        return hipErrorInvalidValue;
+    uint8_t* work = static_cast<uint8_t*>(d_work);
+    const bool one = one_table != nullptr && one_scene != nullptr;
+    const uint8_t* table = one ? work + kWorkTable : static_cast<const uint8_t*>(d_table);
     hipError_t e;
     {
+        // The histogram kernels may use up to 64 KiB of dynamic LDS.
+        static hipError_t attr = [] {
+            const void* ks[2] = {(const void*)k_brick_hist, (const void*)k_brick_scatter};
+            for (const void* k : ks) {
+                hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)(kMaxBricks * sizeof(uint32_t)));
+                if (r != hipSuccess) return r;
+            }
+            return hipSuccess;
+        }();
+        if (attr != hipSuccess) return attr;
+    }
+    {
         KernelTimer t("brick_init", stream);
-        k_brick_init<<<1, 64, 0, stream>>>(status, counter);
+        BrickTable ot{};
+        BrickScene os{};
+        if (one) {
+            ot = *one_table;
+            os = *one_scene;
+        }
+        k_brick_init<<<1, 64, 0, stream>>>(ot, os, one ? 1u : 0u, table, work, (uint64_t)work_bytes, L);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    {
-        // Dynamic LDS (the brick histogram) beyond the default limit.
-        const void* ks[4] = {(const void*)k_brick_hist<true>, (const void*)k_brick_hist<false>,
-                             (const void*)k_brick_scatter<true>, (const void*)k_brick_scatter<false>};
-        for (const void* k : ks)
-            if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hist_lds)) !=
-                hipSuccess)
-                return e;
-    }
+    const size_t hist_lds = (size_t)L.max_nb * sizeof(uint32_t);
     {
         KernelTimer t("brick_hist", stream);
-        if (aligned8)
-            k_brick_hist<true><<<G, kHistBlock, hist_lds, stream>>>(segs, n, bg, hist, counts, status);
-        else
-            k_brick_hist<false><<<G, kHistBlock, hist_lds, stream>>>(segs, n, bg, hist, counts, status);
+        k_brick_hist<<<L.rows, kHistBlock, hist_lds, stream>>>(table, work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         KernelTimer t("brick_colscan", stream);
-        k_brick_colscan<<<(bg.nbricks + kColBins - 1) / kColBins, 256, 0, stream>>>(hist, G, bg.nbricks,
-                                                                                    totals);
+        k_brick_colscan<<<(L.bricks + kColBins - 1) / kColBins, 256, 0, stream>>>(table, work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         KernelTimer t("brick_base", stream);
-        k_brick_base<<<1, kBaseBlock, 0, stream>>>(totals, bg.nbricks, bin_base);
+        k_brick_base<<<1, kBaseBlock, 0, stream>>>(table, work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         KernelTimer t("brick_scatter", stream);
-        if (aligned8)
-            k_brick_scatter<true><<<G, kHistBlock, hist_lds, stream>>>(segs, n, bg, hist, bin_base, recs);
-        else
-            k_brick_scatter<false><<<G, kHistBlock, hist_lds, stream>>>(segs, n, bg, hist, bin_base, recs);
+        k_brick_scatter<<<L.rows, kHistBlock, hist_lds, stream>>>(table, work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    const uint32_t clear = (flags & 1u) ? 1u : 0u;
     KernelTimer t("brick_fill", stream);
-    const int* lg = bg.lg;
-    if (lg[0] == 8 && lg[1] == 6 && lg[2] == 5)
-        return launch_fill<8, 6, 5>(bg, recs, bin_base, grid, clear, counter, stream);
-    if (lg[0] == 8 && lg[1] == 6 && lg[2] == 6)
-        return launch_fill<8, 6, 6>(bg, recs, bin_base, grid, clear, counter, stream);
-    if (lg[0] == 7 && lg[1] == 6 && lg[2] == 6)
-        return launch_fill<7, 6, 6>(bg, recs, bin_base, grid, clear, counter, stream);
-    if (lg[0] == 7 && lg[1] == 7 && lg[2] == 6)
-        return launch_fill<7, 7, 6>(bg, recs, bin_base, grid, clear, counter, stream);
+    const int* lg = L.lg;
+    if (lg[0] == 8 && lg[1] == 6 && lg[2] == 5) return launch_fill<8, 6, 5>(table, work, L.bricks, stream);
+    if (lg[0] == 8 && lg[1] == 6 && lg[2] == 6) return launch_fill<8, 6, 6>(table, work, L.bricks, stream);
+    if (lg[0] == 7 && lg[1] == 6 && lg[2] == 6) return launch_fill<7, 6, 6>(table, work, L.bricks, stream);
+    if (lg[0] == 7 && lg[1] == 7 && lg[2] == 6) return launch_fill<7, 7, 6>(table, work, L.bricks, stream);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_brick_grid(const int32_t* segs, int64_t n, bool aligned8, const BrickGeom& bg,
+                             uint32_t* grid, int32_t* counts, uint32_t flags, void* d_work,
+                             size_t work_bytes, hipStream_t stream) {
+    BrickTable t{};
+    BrickScene sc{};
+    sc.segs = segs;
+    sc.counts = counts;
+    sc.grid = grid;
+    sc.n = n;
+    sc.bg = bg;
+    sc.flags = ((flags & 1u) ? kSceneClear : 0u) | (aligned8 ? kSceneAligned8 : 0u);
+    for (int a = 0; a < 3; ++a) t.lg[a] = bg.lg[a];
+    if (!brick_table_layout(t, &sc, 1)) return hipErrorInvalidValue;
+    BrickLaunch L;
+    L.rows = t.rows;
+    L.bricks = t.bricks;
+    for (int a = 0; a < 3; ++a) L.lg[a] = bg.lg[a];
+    L.max_nb = t.max_nb;
+    return launch_bricks(nullptr, L, &t, &sc, d_work, work_bytes, stream);
 }
 
 }  // namespace vox

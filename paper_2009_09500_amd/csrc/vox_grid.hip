@@ -94,10 +94,11 @@ size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz) {
     return kAlign;
 }
 
-GridWork grid_workspace(void* d_work, int64_t n, int32_t dx, int32_t dy, int32_t dz) {
+GridWork grid_workspace(void* d_work, size_t work_bytes, int64_t n, int32_t dx, int32_t dy, int32_t dz) {
     (void)n; (void)dx; (void)dy; (void)dz;
     GridWork w;
     w.status = static_cast<int32_t*>(d_work);
+    w.bytes = work_bytes;
     return w;
 }
 
@@ -106,7 +107,7 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
                        const GridWork& w, hipStream_t stream) {
     BrickGeom bg;
     if (use_bricks(n, dx, dy, dz, bg))
-        return launch_brick_grid(segs, n, aligned8, bg, grid, counts, flags, w.status, stream);
+        return launch_brick_grid(segs, n, aligned8, bg, grid, counts, flags, w.status, w.bytes, stream);
     {
         KernelTimer timer("grid_init", stream);
         k_grid_init<<<1, 64, 0, stream>>>(w.status);

@@ -69,6 +69,9 @@ void drain() {
 
 KernelTimer::KernelTimer(const char* name, hipStream_t stream) : name_(name), stream_(stream) {
     if (!g_enabled.load(std::memory_order_relaxed)) return;
+    // Launches being captured into a graph are not timed.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream_, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lk(g_mu);
     start_ = take_event();
     if (start_ && hipEventRecord(start_, stream_) != hipSuccess) {

@@ -28,7 +28,7 @@ def test_abi_version_matches_header(lib):
 
 
 def test_status_strings(lib):
-    for code in range(6):
+    for code in range(7):
         assert lib.vox_status_string(code)
     assert lib.vox_status_string(99) == b"unknown status"
 
@@ -36,7 +36,8 @@ def test_status_strings(lib):
 def test_status_codes_match_header():
     text = open(binding.HEADER).read()
     for name in ("VOX_OK", "VOX_ERR_INVALID_ARGUMENT", "VOX_ERR_OUT_OF_RANGE",
-                 "VOX_ERR_CAPACITY", "VOX_ERR_DEVICE", "VOX_ERR_WORKSPACE"):
+                 "VOX_ERR_CAPACITY", "VOX_ERR_DEVICE", "VOX_ERR_WORKSPACE",
+                 "VOX_ERR_BATCH_MISMATCH"):
         v = int(re.search(name + r" = (\d+)", text).group(1))
         assert getattr(binding, name) == v
 

@@ -53,3 +53,21 @@ def test_full_scenes_plain_calls(oracle_jobs_dir):
         if oracle_jobs.block_digests(grid_host(g)) != exp["digests"][s]:
             bad.append(s)
     assert not bad, "scenes differ: %s" % bad[:10]
+
+
+def test_full_scenes_one_batch(oracle_jobs_dir):
+    """All 256 scenes of the batch workload in one batched launch sequence."""
+    torch = pytest.importorskip("torch")
+    sc = workloads.scenes()
+    grids = [torch.empty(binding.grid_words(x["dims"]), dtype=torch.int32, device=dev())
+             for x in sc]
+    segs = [to_dev(x["segs"]) for x in sc]
+    table, launch = binding.vox_batch_plan([(s, x["dims"], g, None, binding.VOX_GRID_CLEAR)
+                                            for s, x, g in zip(segs, sc, grids)])
+    work = binding.workspace(launch.work_bytes, dev())
+    binding.vox_batch_scenes(torch.from_numpy(table).to(dev()), launch, work)
+    assert binding.vox_read_status(work) == binding.VOX_OK
+    exp = oracle_jobs.wait_result(oracle_jobs_dir, "scenes", timeout=100)
+    bad = [s for s, g in enumerate(grids)
+           if oracle_jobs.block_digests(grid_host(g)) != exp["digests"][s]]
+    assert not bad, "scenes differ: %s" % bad[:10]
