@@ -255,9 +255,12 @@ def bench_serving(args, torch, binding, workloads, dev, n_requests=1000, pool_si
     pinned = [torch.from_numpy(w["segs"]).pin_memory() for w in pool]
     dims = pool[0]["dims"]
 
+    vox = [int((np.abs(w["segs"][:, 3:].astype(np.int64) - w["segs"][:, :3]).max(1) + 1).sum())
+           for w in pool]
+
     def requests(arrivals):
         return [serving.Request(i, pool[i % pool_size]["segs"], dims, float(t),
-                                dev={"pinned": pinned[i % pool_size]})
+                                voxels=vox[i % pool_size], dev={"pinned": pinned[i % pool_size]})
                 for i, t in enumerate(arrivals)]
 
     def once(arrivals):

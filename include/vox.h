@@ -152,7 +152,7 @@ vox_status vox_get_tuning(vox_tuning *tuning);
  * scenes take the brick path: dim_x must be a multiple of 32 and every
  * side at most 16384, with at most 16384 bricks per scene. */
 typedef struct vox_scene {
-    const vox_segment *segs; /* device, 4-byte aligned; may be NULL if n == 0 */
+    const vox_segment *segs; /* device, 8-byte aligned; may be NULL if n == 0 */
     int64_t n;
     int32_t dim_x, dim_y, dim_z;
     uint32_t flags;          /* VOX_GRID_CLEAR or 0 */

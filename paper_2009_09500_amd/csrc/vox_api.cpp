@@ -222,8 +222,8 @@ vox_status vox_batch_plan(const vox_scene* h_scenes, int32_t n_scenes, void* h_t
         if (in.n < 0 || in.n > (int64_t(1) << 31) - 2)
             return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: n must lie in [0, 2^31 - 2]", i);
         if (in.n > 0 && in.segs == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: segs is NULL", i);
-        if (in.segs && !aligned(in.segs, 4))
-            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: segs not 4-byte aligned", i);
+        if (in.segs && !aligned(in.segs, 8))
+            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: segs not 8-byte aligned", i);
         if (check_dims(in.dim_x, in.dim_y, in.dim_z) != VOX_OK)
             return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: %s", i, g_last_error);
         if (in.grid == nullptr || !aligned(in.grid, 16))
@@ -241,8 +241,7 @@ vox_status vox_batch_plan(const vox_scene* h_scenes, int32_t n_scenes, void* h_t
         sc.counts = in.counts;
         sc.grid = in.grid;
         sc.n = in.n;
-        sc.flags = ((in.flags & VOX_GRID_CLEAR) ? vox::kSceneClear : 0u) |
-                   (aligned(in.segs, 8) ? vox::kSceneAligned8 : 0u);
+        sc.flags = (in.flags & VOX_GRID_CLEAR) ? vox::kSceneClear : 0u;
     }
     vox::BrickTable t{};
     for (int a = 0; a < 3; ++a) t.lg[a] = lg[a];

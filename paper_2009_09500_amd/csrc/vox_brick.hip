@@ -206,7 +206,7 @@ __device__ __forceinline__ uint32_t order_bin(const StagedSeg& g, const BrickGeo
 // Loads segments [base, base + cnt) into the stage (all threads of the
 // block), writes counts, flags out-of-volume segments, and builds the order
 // of the in-volume ones.
-__device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs, bool a8, int64_t base, uint32_t cnt,
+__device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs, int64_t base, uint32_t cnt,
                                                const BrickGeom& bg, Stage& st, int32_t* __restrict__ counts,
                                                bool& bad) {
     if (threadIdx.x < kOrderBins) st.bins[threadIdx.x] = 0;
@@ -215,7 +215,7 @@ __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs,
     uint32_t mine = 0;
     int slot = 0;
     for (uint32_t t = threadIdx.x; t < cnt; t += kHistBlock, ++slot) {
-        const Seg g = a8 ? load_seg<true>(segs, base + t) : load_seg<false>(segs, base + t);
+        const Seg g = load_seg<true>(segs, base + t);
         if (counts) {
             const int64_t c = seg_length(g) + 1;
             counts[base + t] = (int32_t)(c > 0x7FFFFFFFll ? 0x7FFFFFFFll : c);
@@ -327,11 +327,10 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_hist(const uint8_t* __rest
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) lh[b] = 0;
     int64_t lo, hi;
     seg_range(sc.n, (int)g, (int)sc.rows, lo, hi);
-    const bool a8 = (sc.flags & kSceneAligned8) != 0;
     bool bad = false;
     for (int64_t base = lo; base < hi; base += kStage) {
         const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
-        stage_segments(sc.segs, a8, base, cnt, bg, st, sc.counts, bad);
+        stage_segments(sc.segs, base, cnt, bg, st, sc.counts, bad);
         walk_ordered(st, bg, [&](uint32_t b, uint32_t, uint32_t, uint32_t) { atomicAdd(&lh[b], 1u); });
         lds_barrier();
     }
@@ -435,12 +434,11 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(const uint8_t* __r
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) cur[b] = base_b[b] + row[b];
     int64_t lo, hi;
     seg_range(sc.n, (int)g, (int)sc.rows, lo, hi);
-    const bool a8 = (sc.flags & kSceneAligned8) != 0;
     Piece* __restrict__ recs = wv.recs;
     bool bad = false;
     for (int64_t base = lo; base < hi; base += kStage) {
         const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
-        stage_segments(sc.segs, a8, base, cnt, bg, st, nullptr, bad);
+        stage_segments(sc.segs, base, cnt, bg, st, nullptr, bad);
         walk_ordered(st, bg, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j) {
             const uint32_t pos = atomicAdd(&cur[b], 1u);
             const StagedSeg sg = st.seg[j];
@@ -976,7 +974,7 @@ hipError_t launch_bricks(const void* d_table, const BrickLaunch& L, const BrickT
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_brick_grid(const int32_t* segs, int64_t n, bool aligned8, const BrickGeom& bg,
+hipError_t launch_brick_grid(const int32_t* segs, int64_t n, const BrickGeom& bg,
                              uint32_t* grid, int32_t* counts, uint32_t flags, void* d_work,
                              size_t work_bytes, hipStream_t stream) {
     BrickTable t{};
@@ -986,7 +984,7 @@ hipError_t launch_brick_grid(const int32_t* segs, int64_t n, bool aligned8, cons
     sc.grid = grid;
     sc.n = n;
     sc.bg = bg;
-    sc.flags = ((flags & 1u) ? kSceneClear : 0u) | (aligned8 ? kSceneAligned8 : 0u);
+    sc.flags = (flags & 1u) ? kSceneClear : 0u;
     for (int a = 0; a < 3; ++a) t.lg[a] = bg.lg[a];
     if (!brick_table_layout(t, &sc, 1)) return hipErrorInvalidValue;
     BrickLaunch L;

