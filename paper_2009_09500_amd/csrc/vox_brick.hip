@@ -554,43 +554,40 @@ __device__ __forceinline__ void set_chunk(uint32_t* brick, const u32x4& rec, uin
     }
 }
 
-// Launch shape of the fill kernel per brick shape: threads, pieces per batch,
-// voxels per chunk, chunk-table capacity and workgroups per CU.  A 128 KiB
-// brick takes a whole CU (one workgroup of 1024 threads); 64 KiB bricks run
-// two workgroups of 512 threads per CU, so that one workgroup's barrier
-// phases and brick flush overlap the other's voxel work.
+// Launch shape of the fill kernel per brick shape: threads, voxels per chunk
+// and workgroups per CU.  A 128 KiB brick takes a whole CU (one workgroup of
+// 1024 threads); 64 KiB bricks run two workgroups of 512 threads per CU, so
+// that one workgroup's brick start and flush overlap the other's voxel work.
 template <int LGX, int LGY, int LGZ>
 struct FillCfg {
     static constexpr bool kBig = (LGX + LGY + LGZ) >= 20;
     static constexpr int kBlock = kBig ? 1024 : 512;
-    static constexpr int kBatch = kBig ? 1024 : 512;
     static constexpr int kChunk = 32;
-    static constexpr int kCtab = 3 * kBatch;
     static constexpr int kWgsPerCu = kBig ? 1 : 2;
 };
 
+// Persistent fill.  Workgroups take bricks from a global counter (work
+// stealing: bricks differ a lot in work).  Inside a brick the waves work
+// independently, with no workgroup barrier until the brick is done: a wave
+// takes the next 64 piece records (one per lane), cuts them into chunks of at
+// most kChunk voxels, lists the chunks in its own LDS table (full chunks
+// first) and runs them in rounds of 64, one chunk per lane, reading each
+// chunk's record from the owning lane with ds_bpermute.  The next 64 records
+// are loaded while the current ones run.
 template <int LGX, int LGY, int LGZ>
 __global__ __launch_bounds__((FillCfg<LGX, LGY, LGZ>::kBlock), (FillCfg<LGX, LGY, LGZ>::kWgsPerCu))
 void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work) {
     using Shape = BrickShape<LGX, LGY, LGZ>;
     using Cfg = FillCfg<LGX, LGY, LGZ>;
-    constexpr int kBlock = Cfg::kBlock, kBatch = Cfg::kBatch, kChunk = Cfg::kChunk, kCtab = Cfg::kCtab;
-    constexpr int kPpt = kBatch / kBlock;                           // pieces per thread and batch
+    constexpr int kBlock = Cfg::kBlock, kChunk = Cfg::kChunk;
+    constexpr int kWaves = kBlock / kWave;
     constexpr int kMaxChunks = ((1 << Shape::kMaxLg) + kChunk - 1) / kChunk;  // per piece
-    static_assert(kBatch % kBlock == 0, "whole pieces per thread");
-    static_assert(kBatch * kMaxChunks <= 65536, "chunk table entries are 16-bit");
-    static_assert(kChunk <= kWave, "chunk-length buckets are scanned by one wave");
-    static_assert(kMaxChunks <= kCtab, "a batch always takes its first piece");
+    constexpr int kUpr = Shape::kBXw / 4;  // 16-byte units per brick row
+    static_assert(kWave * kMaxChunks <= 65536 && kWave <= 64, "chunk entries: lane in 6 bits");
     // The brick first, so its addresses need no base offset.
     __shared__ __align__(16) uint32_t brick[Shape::kWords];
-    __shared__ u32x4 pieces[kBatch];
-    __shared__ uint16_t ctab[kCtab];
-    // Chunks per length bucket (bucket 0: full chunks; bucket l: partial
-    // chunks of kChunk - l voxels), then bucket offsets; two sets used by
-    // alternate batches so clearing one needs no extra barrier.
-    __shared__ uint32_t lenc[2][kChunk];
-    __shared__ uint32_t red[kBlock / kWave];
-    __shared__ uint32_t tot_s, round_s, cut_s;
+    __shared__ uint16_t ent[kWaves][kWave * kMaxChunks];  // per-wave chunk tables
+    __shared__ uint32_t cursor_s;
     __shared__ uint32_t next_s[3];
 
     const TableView tv = table_view(table);
@@ -600,15 +597,12 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
     uint32_t* __restrict__ work_counter = wv.counter;
     const uint32_t* __restrict__ bin_base = wv.bin_base;
     const uint32_t lane = __lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
+    uint16_t* my_ent = ent[wave];
     const u32x4* recv = reinterpret_cast<const u32x4*>(wv.recs);
-    if (threadIdx.x < kChunk) lenc[0][threadIdx.x] = lenc[1][threadIdx.x] = 0;
-    uint32_t set = 0;
 
-    // Bricks are taken from a global counter (work stealing: bricks differ
-    // a lot in work).  The next brick and its bin range are claimed by
-    // thread 0 at the start of the current one, so their memory latency
-    // overlaps this brick's work, and the next brick's first records are
-    // loaded before this brick is flushed.
+    // The next brick and its bin range are claimed by thread 0 at the start
+    // of the current one, so their memory latency overlaps this brick's work.
     if (threadIdx.x == 0) {
         const uint32_t nb = atomicAdd(work_counter, 1u);
         next_s[0] = nb;
@@ -618,14 +612,6 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
     lds_barrier();
     uint32_t b = next_s[0];
     uint32_t p_lo = next_s[1], p_hi = next_s[2];
-    // Records of this thread's pieces in the next batch (consecutive), kept
-    // as raw 16-byte vectors.
-    u32x4 rec_n[kPpt];
-#pragma unroll
-    for (int j = 0; j < kPpt; ++j) {
-        const uint32_t pos = p_lo + threadIdx.x * kPpt + j;
-        rec_n[j] = (b < NB && pos < p_hi) ? recv[pos] : (u32x4){0u, 0u, 0u, 0u};
-    }
 
     while (b < NB) {
         uint32_t nb = 0, nlo = 0, nhi = 0;
@@ -661,111 +647,67 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
             u32x4* b4 = reinterpret_cast<u32x4*>(brick);
             for (uint32_t w = threadIdx.x; w < Shape::kWords / 4; w += kBlock) b4[w] = (u32x4){0, 0, 0, 0};
         }
+        if (threadIdx.x == 0) cursor_s = p_lo;
+        lds_barrier();
 
-        uint32_t p0 = p_lo;
-        while (p0 < p_hi) {
-            uint32_t* cnt = lenc[set];
-            const uint32_t nbatch = p_hi - p0 < (uint32_t)kBatch ? p_hi - p0 : (uint32_t)kBatch;
-            // Chunks of this thread's pieces.
-            u32x4 rec[kPpt];
-            uint32_t nch[kPpt], mysum = 0;
-#pragma unroll
-            for (int j = 0; j < kPpt; ++j) {
-                rec[j] = rec_n[j];
-                const uint32_t pos = threadIdx.x * kPpt + j;
-                nch[j] = 0;
-                if (pos < nbatch) {
-                    const uint32_t len = (rec[j].w >> 16) - (rec[j].w & 0xFFFFu) + 1u;
-                    nch[j] = (len + kChunk - 1) / kChunk;
-                }
-                mysum += nch[j];
-            }
-            if (threadIdx.x == 0) cut_s = nbatch;
-            uint32_t total;
-            uint32_t run = block_exclusive_sum_lds<kBlock>(mysum, red, total);
-            // Batch cut: the first piece whose chunks overflow the table.
-            if (total > (uint32_t)kCtab) {
-#pragma unroll
-                for (int j = 0; j < kPpt; ++j) {
-                    if (run <= (uint32_t)kCtab && run + nch[j] > (uint32_t)kCtab)
-                        atomicMin(&cut_s, threadIdx.x * kPpt + j);
-                    run += nch[j];
-                }
-            }
-            lds_barrier();
-            const uint32_t cut = cut_s;
-            // Bucket counts of the pieces inside the cut.
-            uint32_t rf[kPpt], rp[kPpt];
-#pragma unroll
-            for (int j = 0; j < kPpt; ++j) {
-                const uint32_t pos = threadIdx.x * kPpt + j;
-                rf[j] = rp[j] = 0;
-                if (pos < cut) {
-                    pieces[pos] = rec[j];
-                    const uint32_t len = (rec[j].w >> 16) - (rec[j].w & 0xFFFFu) + 1u;
-                    const uint32_t nfull = len / kChunk, part = len % kChunk;
-                    if (nfull) rf[j] = atomicAdd(&cnt[0], nfull);
-                    if (part) rp[j] = atomicAdd(&cnt[kChunk - part], 1u);
-                }
-            }
-            lds_barrier();
-            if (threadIdx.x < kWave) {  // bucket offsets, one bucket per lane
-                const uint32_t c = threadIdx.x < kChunk ? cnt[threadIdx.x] : 0u;
-                const uint32_t incl = wave_inclusive_sum(c);
-                if (threadIdx.x < kChunk) cnt[threadIdx.x] = incl - c;
-                if (threadIdx.x == kWave - 1) {
-                    tot_s = incl;
-                    round_s = 0;
-                }
-            }
-            lds_barrier();
-#pragma unroll
-            for (int j = 0; j < kPpt; ++j) {
-                const uint32_t pos = threadIdx.x * kPpt + j;
-                if (pos < cut) {
-                    const uint32_t len = (rec[j].w >> 16) - (rec[j].w & 0xFFFFu) + 1u;
-                    const uint32_t nfull = len / kChunk, part = len % kChunk;
-                    for (uint32_t c = 0; c < nfull; ++c)
-                        ctab[cnt[0] + rf[j] + c] = (uint16_t)(pos * kMaxChunks + c);
-                    if (part) ctab[cnt[kChunk - part] + rp[j]] = (uint16_t)(pos * kMaxChunks + nfull);
-                }
-            }
-            if (threadIdx.x < kChunk) lenc[set ^ 1][threadIdx.x] = 0;
-            const uint32_t tot = tot_s;
-            const uint32_t full = cnt[1];  // chunks before the first partial bucket
-            // Next batch's records, in flight during this batch's rounds.
-            p0 += cut;
-#pragma unroll
-            for (int j = 0; j < kPpt; ++j) {
-                const uint32_t pos = p0 + threadIdx.x * kPpt + j;
-                rec_n[j] = pos < p_hi ? recv[pos] : (u32x4){0u, 0u, 0u, 0u};
-            }
-            lds_barrier();
+        // This wave's groups of 64 records; the next group is claimed and
+        // loaded before the current one runs.
+        uint32_t gbase = 0;
+        if (lane == 0) gbase = atomicAdd(&cursor_s, (uint32_t)kWave);
+        gbase = __builtin_amdgcn_readfirstlane(gbase);
+        u32x4 rec_n = (gbase + lane < p_hi) ? recv[gbase + lane] : (u32x4){0u, 0u, 0u, 0u};
+        while (gbase < p_hi) {
+            const uint32_t i = gbase + lane;
+            const u32x4 rec = rec_n;
+            const uint32_t len = i < p_hi ? (rec.w >> 16) - (rec.w & 0xFFFFu) + 1u : 0u;
+            // rec has arrived (len is made from it); the next group's load is
+            // issued only now, so no later wait for rec waits for it too.
+            asm volatile("" ::"v"(len) : "memory");
+            if (lane == 0) gbase = atomicAdd(&cursor_s, (uint32_t)kWave);
+            gbase = __builtin_amdgcn_readfirstlane(gbase);
+            rec_n = (gbase + lane < p_hi) ? recv[gbase + lane] : (u32x4){0u, 0u, 0u, 0u};
 
-            // Rounds of kWave chunks, longest first, taken by whichever wave
-            // is free: every wave runs chunks of (nearly) one length.
-            const uint32_t rounds = (tot + kWave - 1) / kWave;
-            while (true) {
-                uint32_t r = 0;
-                if (lane == 0) r = atomicAdd(&round_s, 1u);
-                r = __builtin_amdgcn_readfirstlane(r);
-                if (r >= rounds) break;
-                const uint32_t c = r * kWave + lane;
-                if (c >= tot) continue;
-                const uint32_t e = ctab[c];
-                const u32x4 q = pieces[e / kMaxChunks];
-                const uint32_t k0 = (q.w & 0xFFFFu) + (e % kMaxChunks) * kChunk;
-                if (c < full) {
-                    set_chunk<true, kChunk, LGX, LGY>(brick, q, k0, kChunk, org);
-                } else {
-                    set_chunk<false, kChunk, LGX, LGY>(brick, q, k0, (int)((q.w >> 16) - k0 + 1u), org);
+            // Chunks of this lane's piece: full ones first in the table, then
+            // the one partial chunk of each piece.  Both counts in one scan
+            // (full chunks in the low half: at most 64 * kMaxChunks).
+            const uint32_t nfull = len / kChunk, npart = (len % kChunk) ? 1u : 0u;
+            const uint32_t inc = wave_inclusive_sum(nfull | (npart << 16));
+            const uint32_t incf = inc & 0xFFFFu, incp = inc >> 16;
+            const uint32_t tot = __builtin_amdgcn_readlane(inc, kWave - 1);
+            const uint32_t tf = tot & 0xFFFFu;
+            const uint32_t tt = tf + (tot >> 16);
+            for (uint32_t j = 0; j < nfull; ++j) my_ent[incf - nfull + j] = (uint16_t)(lane | (j << 6));
+            if (npart) my_ent[tf + incp - 1] = (uint16_t)(lane | (nfull << 6));
+            // Make the table writes visible to the wave's own reads below.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+            for (uint32_t q = 0; q < tt; q += kWave) {
+                const uint32_t c = q + lane;
+                const uint32_t e = c < tt ? my_ent[c] : 0u;
+                const int src = (int)((e & 63u) << 2);
+                u32x4 r;
+                r.x = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)rec.x);
+                r.y = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)rec.y);
+                r.z = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)rec.z);
+                r.w = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)rec.w);
+                const uint32_t k0 = (r.w & 0xFFFFu) + (e >> 6) * kChunk;
+                if (q + kWave <= tf) {
+                    set_chunk<true, kChunk, LGX, LGY>(brick, r, k0, kChunk, org);
+                } else if (c < tt) {
+                    const uint32_t left = (r.w >> 16) - k0 + 1u;
+                    set_chunk<false, kChunk, LGX, LGY>(brick, r, k0, (int)(left < kChunk ? left : kChunk), org);
                 }
             }
-            set ^= 1;
-            lds_barrier();
+            // The table is rewritten by the next group.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        lds_barrier();  // every wave done with this brick
 
-        // Hand over the next brick; its first records load during the flush.
+        // Hand over the next brick.
         if (threadIdx.x == 0) {
             next_s[0] = nb;
             next_s[1] = nlo;
@@ -775,11 +717,6 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
         b = next_s[0];
         p_lo = next_s[1];
         p_hi = next_s[2];
-#pragma unroll
-        for (int j = 0; j < kPpt; ++j) {
-            const uint32_t pos = p_lo + threadIdx.x * kPpt + j;
-            rec_n[j] = (b < NB && pos < p_hi) ? recv[pos] : (u32x4){0u, 0u, 0u, 0u};
-        }
 
         // Flush: brick rows -> volume words.  The owner writes every word of
         // its brick, so a clearing call needs no other pass.
@@ -787,8 +724,7 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
         // Whole 16-byte units when the volume's rows hold whole brick rows.
         const bool vec = Shape::kBXw % 4 == 0 && (bg.dim[0] & ((1 << LGX) - 1)) == 0;
         if (vec) {
-            // 16-byte units, Shape::kBXw / 4 per row, rows full width.
-            constexpr int kUpr = Shape::kBXw / 4;
+            // 16-byte units, kUpr per row, rows full width.
             const int units = rows * kUpr;
             const bool full_y = ext[1] == (1 << LGY);  // rows per slab a power of two
             for (int t = threadIdx.x; t < units; t += kBlock) {
@@ -801,7 +737,7 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
                     grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words + (org[0] >> 5) +
                     4 * part);
                 if (clear) {
-                    __builtin_nontemporal_store(v, dst);
+                    *dst = v;
                 } else {
                     *dst = *dst | v;
                 }
