@@ -667,17 +667,32 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
             gbase = __builtin_amdgcn_readfirstlane(gbase);
             rec_n = (gbase + lane < p_hi) ? recv[gbase + lane] : (u32x4){0u, 0u, 0u, 0u};
 
-            // Chunks of this lane's piece: full ones first in the table, then
-            // the one partial chunk of each piece.  Both counts in one scan
-            // (full chunks in the low half: at most 64 * kMaxChunks).
-            const uint32_t nfull = len / kChunk, npart = (len % kChunk) ? 1u : 0u;
-            const uint32_t inc = wave_inclusive_sum(nfull | (npart << 16));
-            const uint32_t incf = inc & 0xFFFFu, incp = inc >> 16;
-            const uint32_t tot = __builtin_amdgcn_readlane(inc, kWave - 1);
-            const uint32_t tf = tot & 0xFFFFu;
-            const uint32_t tt = tf + (tot >> 16);
-            for (uint32_t j = 0; j < nfull; ++j) my_ent[incf - nfull + j] = (uint16_t)(lane | (j << 6));
-            if (npart) my_ent[tf + incp - 1] = (uint16_t)(lane | (nfull << 6));
+            // Chunks of this lane's piece: its full chunks, then its one
+            // partial chunk (if any).  The wave's table lists all full
+            // chunks first, then the partial ones in four length classes,
+            // longest first, so that most rounds run chunks of one length.
+            // Two packed DPP scans count all five lists (full chunks: at most
+            // 64 * kMaxChunks; each class: at most 64).
+            const uint32_t nfull = len / kChunk, pl = len % kChunk;
+            const uint32_t c3 = pl >= 3 * kChunk / 4, c2 = pl >= kChunk / 2 && pl < 3 * kChunk / 4;
+            const uint32_t c1 = pl >= kChunk / 4 && pl < kChunk / 2, c0 = pl > 0 && pl < kChunk / 4;
+            const uint32_t ia = wave_inclusive_sum_dpp(nfull | (c3 << 16));
+            const uint32_t ib = wave_inclusive_sum_dpp(c2 | (c1 << 10) | (c0 << 20));
+            const uint32_t ta = __builtin_amdgcn_readlane(ia, kWave - 1);
+            const uint32_t tb = __builtin_amdgcn_readlane(ib, kWave - 1);
+            const uint32_t tf = ta & 0xFFFFu;                      // full chunks
+            const uint32_t o2 = tf + (ta >> 16);                   // start of class 2
+            const uint32_t o1 = o2 + (tb & 0x3FFu);
+            const uint32_t o0 = o1 + ((tb >> 10) & 0x3FFu);
+            const uint32_t tt = o0 + (tb >> 20);
+            for (uint32_t j = 0; j < nfull; ++j) my_ent[(ia & 0xFFFFu) - nfull + j] = (uint16_t)(lane | (j << 6));
+            if (pl) {
+                const uint32_t pos = c3   ? tf + (ia >> 16) - 1u
+                                     : c2 ? o2 + (ib & 0x3FFu) - 1u
+                                     : c1 ? o1 + ((ib >> 10) & 0x3FFu) - 1u
+                                          : o0 + (ib >> 20) - 1u;
+                my_ent[pos] = (uint16_t)(lane | (nfull << 6));
+            }
             // Make the table writes visible to the wave's own reads below.
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();

@@ -109,6 +109,20 @@ __device__ __forceinline__ T wave_inclusive_sum(T v) {
     return v;
 }
 
+// Inclusive sum over the 64 lanes of a wave with DPP moves (rows of 16:
+// shifts by 1, 2, 4, 8; then row 15 broadcast into rows 1 and 3, lane 31
+// into rows 2 and 3).  All lanes must be active.
+__device__ __forceinline__ uint32_t wave_inclusive_sum_dpp(uint32_t x) {
+    uint32_t s = x;
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x111, 0xf, 0xf, true);  // row_shr:1
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x112, 0xf, 0xf, true);  // row_shr:2
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x114, 0xf, 0xf, true);  // row_shr:4
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x118, 0xf, 0xf, true);  // row_shr:8
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x142, 0xa, 0xf, false); // row_bcast:15
+    s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x143, 0xc, 0xf, false); // row_bcast:31
+    return s;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
