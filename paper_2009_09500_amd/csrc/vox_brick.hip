@@ -92,7 +92,7 @@ static_assert(sizeof(Piece) == 16, "16-byte piece records");
 // Sections of the workspace (layout in vox_internal.h).
 struct WorkView {
     int32_t* status;
-    uint32_t* counter;
+    uint32_t* counter;   // [kXcds] brick queues of the fill, one per XCD
     uint32_t* ok;
     uint32_t* hist;
     uint32_t* totals;
@@ -103,7 +103,7 @@ struct WorkView {
 __host__ __device__ inline WorkView work_view(uint8_t* work, uint64_t hist_words, uint32_t bricks) {
     WorkView v;
     v.status = reinterpret_cast<int32_t*>(work);
-    v.counter = reinterpret_cast<uint32_t*>(work + 4);
+    v.counter = reinterpret_cast<uint32_t*>(work + 16);
     v.ok = reinterpret_cast<uint32_t*>(work + 8);
     uint8_t* p = work + kWorkData;
     v.hist = reinterpret_cast<uint32_t*>(p);
@@ -142,7 +142,25 @@ __device__ __forceinline__ TableView table_view(const uint8_t* table) {
     return v;
 }
 
-// Status word, work counter and the launch check: the table must come from
+// Brick queues of the fill.  The 8 XCDs of the chip each have their own L2;
+// workgroup w runs on XCD w % 8.  Groups of 8 consecutive bricks (along x, the
+// fastest brick axis) are dealt to the XCDs in turn, so neighbouring bricks,
+// whose 32-byte row pieces share memory lines, are flushed through the same
+// L2 at about the same time and reach HBM as whole lines.  A workgroup takes
+// from its own XCD's queue first and then from the others.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ uint32_t claim_brick(uint32_t* queues, uint32_t xcd, uint32_t NB) {
+    for (uint32_t k = 0; k < (uint32_t)kXcds; ++k) {
+        const uint32_t x = (xcd + k) & (kXcds - 1);
+        const uint32_t c = atomicAdd(&queues[x], 1u);
+        const uint32_t g = (c >> 3) * (8u * kXcds) + x * 8u + (c & 7u);
+        if (g < NB) return g;
+    }
+    return NB;
+}
+
+// Status word, brick queues and the launch check: the table must come from
 // the planner, fit the launch bounds the kernels were sized for, and fit the
 // workspace; otherwise every later kernel returns at once and the status
 // says so.  A plain call passes its one-scene table by value and it is
@@ -160,8 +178,8 @@ __global__ void k_brick_init(BrickTable one_t, BrickScene one_s, uint32_t has_on
                     t.work_bytes <= work_bytes;
     int32_t* w = reinterpret_cast<int32_t*>(work);
     w[0] = ok ? 0 : kStatusLaunch;  // status
-    w[1] = 0;                       // work counter
     w[2] = ok ? 1 : 0;              // launch ok
+    for (int x = 0; x < kXcds; ++x) w[4 + x] = 0;  // brick queues
 }
 
 // Segment range of histogram/scatter workgroup g.
@@ -566,7 +584,7 @@ struct FillCfg {
     static constexpr int kWgsPerCu = kBig ? 1 : 2;
 };
 
-// Persistent fill.  Workgroups take bricks from a global counter (work
+// Persistent fill.  Workgroups take bricks from the brick queues (work
 // stealing: bricks differ a lot in work).  Inside a brick the waves work
 // independently, with no workgroup barrier until the brick is done: a wave
 // takes the next 64 piece records (one per lane), cuts them into chunks of at
@@ -604,7 +622,7 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
     // The next brick and its bin range are claimed by thread 0 at the start
     // of the current one, so their memory latency overlaps this brick's work.
     if (threadIdx.x == 0) {
-        const uint32_t nb = atomicAdd(work_counter, 1u);
+        const uint32_t nb = claim_brick(work_counter, blockIdx.x % kXcds, NB);
         next_s[0] = nb;
         next_s[1] = nb < NB ? bin_base[nb] : 0u;
         next_s[2] = nb < NB ? bin_base[nb + 1] : 0u;
@@ -616,7 +634,7 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
     while (b < NB) {
         uint32_t nb = 0, nlo = 0, nhi = 0;
         if (threadIdx.x == 0) {
-            nb = atomicAdd(work_counter, 1u);
+            nb = claim_brick(work_counter, blockIdx.x % kXcds, NB);
             if (nb < NB) {
                 nlo = bin_base[nb];
                 nhi = bin_base[nb + 1];

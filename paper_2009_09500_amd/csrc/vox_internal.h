@@ -133,7 +133,7 @@ struct BrickLaunch {
     uint32_t max_nb;
 };
 
-// Workspace: [status, work counter, launch-ok flag] | the one-scene table of
+// Workspace: [status word, launch-ok flag, 8 brick queues] | the one-scene table of
 // a plain call | histogram rows | brick totals | bin offsets | piece records.
 constexpr size_t kWorkTable = kAlign;
 constexpr size_t kWorkData = kAlign + 512;
