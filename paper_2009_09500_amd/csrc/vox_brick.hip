@@ -626,6 +626,11 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
         next_s[0] = nb;
         next_s[1] = nb < NB ? bin_base[nb] : 0u;
         next_s[2] = nb < NB ? bin_base[nb + 1] : 0u;
+        cursor_s = next_s[1];
+    }
+    {
+        u32x4* b4 = reinterpret_cast<u32x4*>(brick);
+        for (uint32_t w = threadIdx.x; w < Shape::kWords / 4; w += kBlock) b4[w] = (u32x4){0, 0, 0, 0};
     }
     lds_barrier();
     uint32_t b = next_s[0];
@@ -661,12 +666,8 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
                 ext[ax] = e < (1 << lgs[ax]) ? e : (1 << lgs[ax]);
             }
         }
-        {
-            u32x4* b4 = reinterpret_cast<u32x4*>(brick);
-            for (uint32_t w = threadIdx.x; w < Shape::kWords / 4; w += kBlock) b4[w] = (u32x4){0, 0, 0, 0};
-        }
-        if (threadIdx.x == 0) cursor_s = p_lo;
-        lds_barrier();
+        // (The brick is zero and cursor_s = p_lo: set before the barrier that
+        // ended the previous brick.)
 
         // This wave's groups of 64 records; the next group is claimed and
         // loaded before the current one runs.
@@ -738,21 +739,17 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        lds_barrier();  // every wave done with this brick
-
-        // Hand over the next brick.
+        // Hand over the next brick (read by all after the barrier).
         if (threadIdx.x == 0) {
             next_s[0] = nb;
             next_s[1] = nlo;
             next_s[2] = nhi;
         }
-        lds_barrier();
-        b = next_s[0];
-        p_lo = next_s[1];
-        p_hi = next_s[2];
+        lds_barrier();  // every wave done with this brick
 
-        // Flush: brick rows -> volume words.  The owner writes every word of
-        // its brick, so a clearing call needs no other pass.
+        // Flush: brick rows -> volume words, zeroing the brick on the way.
+        // The owner writes every word of its brick, so a clearing call needs
+        // no other pass.
         const int rows = ext[1] * ext[2];
         // Whole 16-byte units when the volume's rows hold whole brick rows.
         const bool vec = Shape::kBXw % 4 == 0 && (bg.dim[0] & ((1 << LGX) - 1)) == 0;
@@ -764,8 +761,10 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
                 const int part = t % kUpr, r = t / kUpr;
                 const int y = full_y ? (r & ((1 << LGY) - 1)) : r % ext[1];
                 const int z = full_y ? (r >> LGY) : r / ext[1];
-                const u32x4 v = *reinterpret_cast<const u32x4*>(
+                u32x4* src = reinterpret_cast<u32x4*>(
                     &brick[(((uint32_t)z << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + 4u * part]);
+                const u32x4 v = *src;
+                *src = (u32x4){0u, 0u, 0u, 0u};  // zero for the next brick
                 global_u32x4* dst = (global_u32x4*)(
                     grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words + (org[0] >> 5) +
                     4 * part);
@@ -781,13 +780,21 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
             for (int t = threadIdx.x; t < total; t += kBlock) {
                 const int xw = t % xws, r = t / xws;
                 const int y = r % ext[1], z = r / ext[1];
-                const uint32_t v = brick[(((uint32_t)z << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + xw];
+                uint32_t* src = &brick[(((uint32_t)z << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + xw];
+                const uint32_t v = *src;
+                *src = 0u;  // zero for the next brick
                 global_u32* dst = (global_u32*)grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words +
                                 (org[0] >> 5) + xw;
                 if (clear) *dst = v;
                 else *dst |= v;
             }
         }
+        // Every word that can hold a bit (inside the volume) was read and
+        // zeroed above; the others were never set.  Next brick:
+        b = next_s[0];
+        p_lo = next_s[1];
+        p_hi = next_s[2];
+        if (threadIdx.x == 0) cursor_s = p_lo;
         lds_barrier();
     }
 }
