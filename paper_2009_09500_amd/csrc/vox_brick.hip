@@ -160,6 +160,17 @@ __device__ __forceinline__ uint32_t claim_brick(uint32_t* queues, uint32_t xcd, 
     return NB;
 }
 
+// Histogram row of workgroup w out of G.  Each XCD takes a contiguous block
+// of rows (workgroup w runs on XCD w % 8): a bin holds the records of row 0,
+// then row 1, ..., so the scatter's short per-row runs of one bin that share
+// memory lines are written through one L2 at about the same time.
+__device__ __forceinline__ uint32_t xcd_row(uint32_t w, uint32_t G) {
+    const uint32_t x = w % kXcds, a = w / kXcds;
+    uint32_t start = 0;
+    for (uint32_t i = 0; i < x; ++i) start += (G - i + kXcds - 1) / kXcds;  // rows of XCD i
+    return start + a;
+}
+
 // Status word, brick queues and the launch check: the table must come from
 // the planner, fit the launch bounds the kernels were sized for, and fit the
 // workspace; otherwise every later kernel returns at once and the status
@@ -336,7 +347,7 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_hist(const uint8_t* __rest
     __shared__ Stage st;
     const TableView tv = table_view(table);
     const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
-    const uint32_t r = blockIdx.x;
+    const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
     if (*wv.ok == 0 || r >= tv.h.rows) return;
     const BrickScene sc = tv.scenes[tv.row_scene ? tv.row_scene[r] : 0u];
     const BrickGeom& bg = sc.bg;
@@ -441,7 +452,7 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(const uint8_t* __r
     __shared__ Stage st;
     const TableView tv = table_view(table);
     const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
-    const uint32_t r = blockIdx.x;
+    const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
     if (*wv.ok == 0 || r >= tv.h.rows) return;
     const BrickScene sc = tv.scenes[tv.row_scene ? tv.row_scene[r] : 0u];
     const BrickGeom& bg = sc.bg;
