@@ -495,73 +495,106 @@ struct BrickShape {
     static constexpr int kMaxLg = LGX > LGY ? (LGX > LGZ ? LGX : LGZ) : (LGY > LGZ ? LGY : LGZ);
 };
 
-// floor(x / y) and remainder for x < 2^32 and quotients below 2^15, from a
-// hardware reciprocal estimate corrected in integers (exact).
+// floor(x / y) and remainder for x < 2^31, 1 <= y < 2^16 and quotients
+// below 2^15, from a hardware reciprocal estimate corrected in integers
+// (exact).  The estimate's relative error is below 2^-21 (x and y are exact
+// or rounded once in float, the reciprocal is within one ulp), so x * rcp is
+// within 2^15 * 2^-21 of x / y and its floor within one of the quotient.
 __device__ __forceinline__ void divmod_rcp(uint32_t x, uint32_t y, float rcp, uint32_t& q, uint32_t& r) {
     uint32_t qq = (uint32_t)((float)x * rcp);
-    int32_t rr = (int32_t)(x - qq * y);
+    int32_t rr = (int32_t)(x - __umul24(qq, y));
     if (rr < 0) { --qq; rr += (int32_t)y; }
-    if (rr < 0) { --qq; rr += (int32_t)y; }
-    if (rr >= (int32_t)y) { ++qq; rr -= (int32_t)y; }
     if (rr >= (int32_t)y) { ++qq; rr -= (int32_t)y; }
     q = qq;
     r = (uint32_t)rr;
 }
 
-// Sets the bits of voxels k0 .. k0 + len - 1 (len <= kChunk; exactly kChunk
-// when kFull) of one piece.
-//
-// The dominant axis moves by one voxel per step.  The two other axes keep
-// their error terms as biased 16-bit halves u = r - 2N + 32768 of one
-// register (r the remainder of eq. (3)'s division, so u in [32768-2N, 32768)):
-// adding 2a sets bit 15 exactly when that coordinate advances.  An
-// arithmetic shift turns those bits into 0 / -1 halves, which subtract 2N
-// from their halves in one packed multiply-add and add the axes' signed
-// strides to the bit index in one packed dot product (with the strides
-// stored negated).  Needs 2N <= 32768.
-template <bool kFull, int kChunk, int LGX, int LGY>
-__device__ __forceinline__ void set_chunk(uint32_t* brick, const u32x4& rec, uint32_t k0, int len,
-                                          const int32_t org[3]) {
-    constexpr int32_t kSy = 1 << LGX, kSz = 1 << (LGX + LGY);
+// Stepping state of a piece at its first voxel, made once per piece by the
+// lane that loaded its record and read by the lanes that run its chunks
+// (16 bytes, like the record):
+//   x: E0, the two minor axes' error terms as biased 16-bit halves
+//      u = r - 2N + 32768 (r the remainder of eq. (3)'s division at k = klo)
+//   y: T, the halves' increments 2a
+//   z: 2N | (len - 1) << 16 | m << 25 | neg_m << 27 | neg_a << 28 | neg_b << 29
+//      (m the dominant axis, a and b the other two in axis order)
+//   w: bit index of the voxel at k = klo inside the brick
+template <int LGX, int LGY>
+__device__ __forceinline__ u32x4 digest_piece(const u32x4& rec, const int32_t org[3]) {
     // Record words: x0|y0<<16, z0|dx<<16, dy|dz<<16, klo|khi<<16.
     const int32_t p0[3] = {(int32_t)(rec.x & 0xFFFFu), (int32_t)(rec.x >> 16), (int32_t)(rec.y & 0xFFFFu)};
     const int32_t d[3] = {(int32_t)(int16_t)(rec.y >> 16), (int32_t)(int16_t)(rec.z & 0xFFFFu),
                           (int32_t)(int16_t)(rec.z >> 16)};
+    const uint32_t klo = rec.w & 0xFFFFu, len = (rec.w >> 16) - klo + 1u;
     const uint32_t a0 = (uint32_t)(d[0] < 0 ? -d[0] : d[0]);
-    const uint32_t a1_ = (uint32_t)(d[1] < 0 ? -d[1] : d[1]);
-    const uint32_t a2_ = (uint32_t)(d[2] < 0 ? -d[2] : d[2]);
-    const uint32_t N = a0 > a1_ ? (a0 > a2_ ? a0 : a2_) : (a1_ > a2_ ? a1_ : a2_);
-    // Dominant axis m (first of the maximal ones) and the two minor axes,
-    // chosen with selects only.
-    const bool m0 = a0 == N, m1 = !m0 && a1_ == N;
-    const bool m2 = !m0 && !m1;
-    const int32_t st0 = d[0] < 0 ? -1 : 1, st1 = d[1] < 0 ? -kSy : kSy, st2 = d[2] < 0 ? -kSz : kSz;
-    const int32_t sm = m0 ? st0 : (m1 ? st1 : st2);
-    // Minor axis 1: the lower-numbered of the two; minor axis 2: the other.
-    const uint32_t aa = m0 ? a1_ : a0, ab = m2 ? a1_ : a2_;
-    const int32_t sa = m0 ? st1 : st0, sb = m2 ? st1 : st2;
-    const int32_t pa = m0 ? p0[1] : p0[0], pb = m2 ? p0[1] : p0[2];
-    const int32_t oa = m0 ? org[1] : org[0], ob = m2 ? org[1] : org[2];
-    const int32_t pm = m0 ? p0[0] : (m1 ? p0[1] : p0[2]);
-    const int32_t om = m0 ? org[0] : (m1 ? org[1] : org[2]);
-    const uint32_t nega = (uint32_t)(sa < 0), negb = (uint32_t)(sb < 0);
+    const uint32_t a1 = (uint32_t)(d[1] < 0 ? -d[1] : d[1]);
+    const uint32_t a2 = (uint32_t)(d[2] < 0 ? -d[2] : d[2]);
+    const uint32_t N = a0 > a1 ? (a0 > a2 ? a0 : a2) : (a1 > a2 ? a1 : a2);
+    // Dominant axis m (first of the maximal ones); minor axes a < b.
+    const uint32_t m = a0 == N ? 0u : (a1 == N ? 1u : 2u);
+    const uint32_t aa = m == 0 ? a1 : a0, ab = m == 2 ? a1 : a2;
+    const int32_t da = m == 0 ? d[1] : d[0], db = m == 2 ? d[1] : d[2], dm = m == 0 ? d[0] : (m == 1 ? d[1] : d[2]);
+    const uint32_t nega = da < 0, negb = db < 0, negm = dm < 0;
     const uint32_t two_n = 2u * N;
     uint32_t qa = 0, ra = 0, qb = 0, rb = 0;
     if (N > 0) {
         const float rcp = __builtin_amdgcn_rcpf((float)two_n);
-        divmod_rcp(2u * k0 * aa + N - nega, two_n, rcp, qa, ra);
-        divmod_rcp(2u * k0 * ab + N - negb, two_n, rcp, qb, rb);
+        divmod_rcp(2u * __umul24(klo, aa) + N - nega, two_n, rcp, qa, ra);
+        divmod_rcp(2u * __umul24(klo, ab) + N - negb, two_n, rcp, qb, rb);
     }
-    // Bit index of voxel k0 inside the brick; each stride's sign is the
-    // direction of its axis.
-    const int32_t sgn_m = sm < 0 ? -1 : 1;
-    int32_t idx = (pm + sgn_m * (int32_t)k0 - om) * (sm < 0 ? -sm : sm) +
-                  (pa + (nega ? -(int32_t)qa : (int32_t)qa) - oa) * (sa < 0 ? -sa : sa) +
-                  (pb + (negb ? -(int32_t)qb : (int32_t)qb) - ob) * (sb < 0 ? -sb : sb);
+    // Voxel at klo, relative to the brick origin.
+    const int32_t vm = negm ? -(int32_t)klo : (int32_t)klo;
+    const int32_t va = nega ? -(int32_t)qa : (int32_t)qa, vb = negb ? -(int32_t)qb : (int32_t)qb;
+    const int32_t x = p0[0] - org[0] + (m == 0 ? vm : va);
+    const int32_t y = p0[1] - org[1] + (m == 1 ? vm : (m == 0 ? va : vb));
+    const int32_t z = p0[2] - org[2] + (m == 2 ? vm : vb);
+    u32x4 g;
+    g.x = ((ra + 32768u - two_n) & 0xFFFFu) | ((rb + 32768u - two_n) << 16);
+    g.y = (2u * aa) | ((2u * ab) << 16);
+    g.z = two_n | ((len - 1u) << 16) | (m << 25) | (negm << 27) | (nega << 28) | (negb << 29);
+    g.w = (uint32_t)(x + (y << LGX) + (z << (LGX + LGY)));
+    return g;
+}
+
+// Sets the bits of chunk j (voxels klo + j*kChunk ... , at most kChunk of
+// them; exactly kChunk when kFull) of the piece with digest g.
+//
+// The dominant axis moves by one voxel per step.  Adding 2a to a minor
+// axis' biased half sets its bit 15 exactly when that coordinate advances.
+// An arithmetic shift turns those bits into 0 / -1 halves, which subtract 2N
+// from their halves in one packed multiply-add and add the axes' signed
+// strides to the bit index in one packed dot product (with the strides
+// stored negated).  Needs 2N <= 32768.  A chunk after the first starts from
+// the piece's state advanced by j*kChunk steps: one division per minor axis.
+template <bool kFull, int kChunk, int LGX, int LGY>
+__device__ __forceinline__ void run_chunk(uint32_t* brick, const u32x4& g, uint32_t j) {
+    const uint32_t two_n = g.z & 0xFFFFu;
+    const uint32_t len = ((g.z >> 16) & 0x1FFu) + 1u;
+    const uint32_t m = (g.z >> 25) & 3u;
+    const uint32_t negm = (g.z >> 27) & 1u, nega = (g.z >> 28) & 1u, negb = (g.z >> 29) & 1u;
+    // Strides are powers of two: log2 of the dominant axis' and of the
+    // minor axes' (a < b) strides.
+    const uint32_t shm = m == 0 ? 0u : (m == 1 ? (uint32_t)LGX : (uint32_t)(LGX + LGY));
+    const uint32_t sha = m == 0 ? (uint32_t)LGX : 0u, shb = m == 2 ? (uint32_t)LGX : (uint32_t)(LGX + LGY);
+    // The state advanced by koff steps (koff = 0 for the first chunk leaves it
+    // unchanged): the minor remainders and coordinates by one division each.
+    const uint32_t koff = j * (uint32_t)kChunk;
+    // Scalars first: this compiler's __builtin_bit_cast of a vector element
+    // (g.y) reads the vector's first element instead.
+    const uint32_t gx = g.x, gy = g.y;
+    const u16x2 E0 = __builtin_bit_cast(u16x2, gx);
+    const u16x2 T = __builtin_bit_cast(u16x2, gy);
+    const uint32_t y = two_n | (two_n == 0u);  // a single-voxel piece has N = 0
+    const float rcp = __builtin_amdgcn_rcpf((float)y);
+    uint32_t qa, ra, qb, rb;
+    divmod_rcp((uint32_t)E0.x + two_n - 32768u + __umul24(koff, (uint32_t)T.x), y, rcp, qa, ra);
+    divmod_rcp((uint32_t)E0.y + two_n - 32768u + __umul24(koff, (uint32_t)T.y), y, rcp, qb, rb);
     u16x2 E = {(uint16_t)(ra + 32768u - two_n), (uint16_t)(rb + 32768u - two_n)};
-    const u16x2 T = {(uint16_t)(2u * aa), (uint16_t)(2u * ab)};
+    const int32_t dm = (int32_t)(koff << shm), dqa = (int32_t)(qa << sha), dqb = (int32_t)(qb << shb);
+    int32_t idx = (int32_t)g.w + (negm ? -dm : dm) + (nega ? -dqa : dqa) + (negb ? -dqb : dqb);
+    const int32_t sm = negm ? -(1 << shm) : (1 << shm);
+    const int32_t sa = 1 << sha, sb = 1 << shb;
     const u16x2 N2 = {(uint16_t)two_n, (uint16_t)two_n};
-    const i16x2 S = {(int16_t)(-sa), (int16_t)(-sb)};
+    const i16x2 S = {(int16_t)(nega ? sa : -sa), (int16_t)(negb ? sb : -sb)};
     const i16x2 k15 = {15, 15};
     if constexpr (kFull) {
 #pragma unroll 8
@@ -573,10 +606,11 @@ __device__ __forceinline__ void set_chunk(uint32_t* brick, const u32x4& rec, uin
             idx = __builtin_amdgcn_sdot2(C, S, idx, false) + sm;
         }
     } else {
-        for (int k = 0; k < len; ++k) {
+        const int n = (int)(len - koff < (uint32_t)kChunk ? len - koff : (uint32_t)kChunk);
+        for (int k = 0; k < n; ++k) {
             atomicOr(&brick[(uint32_t)idx >> 5], 1u << ((uint32_t)idx & 31u));
             E = E + T;
-            const i16x2 C = __builtin_bit_cast(i16x2, E) >> k15;  // -1 where the axis advances
+            const i16x2 C = __builtin_bit_cast(i16x2, E) >> k15;
             E = E + __builtin_bit_cast(u16x2, C) * N2;
             idx = __builtin_amdgcn_sdot2(C, S, idx, false) + sm;
         }
@@ -697,6 +731,10 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
             gbase = __builtin_amdgcn_readfirstlane(gbase);
             rec_n = (gbase + lane < p_hi) ? recv[gbase + lane] : (u32x4){0u, 0u, 0u, 0u};
 
+            // This lane's piece as a stepping state (read by the lanes that
+            // run its chunks).
+            const u32x4 dg = digest_piece<LGX, LGY>(rec, org);
+
             // Chunks of this lane's piece: its full chunks, then its one
             // partial chunk (if any).  The wave's table lists all full
             // chunks first, then the partial ones in four length classes,
@@ -732,17 +770,14 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
                 const uint32_t c = q + lane;
                 const uint32_t e = c < tt ? my_ent[c] : 0u;
                 const int src = (int)((e & 63u) << 2);
-                u32x4 r;
-                r.x = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)rec.x);
-                r.y = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)rec.y);
-                r.z = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)rec.z);
-                r.w = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)rec.w);
-                const uint32_t k0 = (r.w & 0xFFFFu) + (e >> 6) * kChunk;
+                const u32x4 g = {(uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.x),
+                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.y),
+                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.z),
+                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.w)};
                 if (q + kWave <= tf) {
-                    set_chunk<true, kChunk, LGX, LGY>(brick, r, k0, kChunk, org);
+                    run_chunk<true, kChunk, LGX, LGY>(brick, g, e >> 6);
                 } else if (c < tt) {
-                    const uint32_t left = (r.w >> 16) - k0 + 1u;
-                    set_chunk<false, kChunk, LGX, LGY>(brick, r, k0, (int)(left < kChunk ? left : kChunk), org);
+                    run_chunk<false, kChunk, LGX, LGY>(brick, g, e >> 6);
                 }
             }
             // The table is rewritten by the next group.
