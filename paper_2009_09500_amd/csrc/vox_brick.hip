@@ -495,31 +495,56 @@ struct BrickShape {
     static constexpr int kMaxLg = LGX > LGY ? (LGX > LGZ ? LGX : LGZ) : (LGY > LGZ ? LGY : LGZ);
 };
 
-// floor(x / y) and remainder for x < 2^31, 1 <= y < 2^16 and quotients
+// floor(x / y) and remainder for x < 2^31, 2 <= y < 2^16 and quotients
 // below 2^15, from a hardware reciprocal estimate corrected in integers
-// (exact).  The estimate's relative error is below 2^-21 (x and y are exact
-// or rounded once in float, the reciprocal is within one ulp), so x * rcp is
-// within 2^15 * 2^-21 of x / y and its floor within one of the quotient.
-__device__ __forceinline__ void divmod_rcp(uint32_t x, uint32_t y, float rcp, uint32_t& q, uint32_t& r) {
-    uint32_t qq = (uint32_t)((float)x * rcp);
-    int32_t rr = (int32_t)(x - __umul24(qq, y));
-    if (rr < 0) { --qq; rr += (int32_t)y; }
-    if (rr >= (int32_t)y) { ++qq; rr -= (int32_t)y; }
+// (exact).  rcp_down(y) is the reciprocal (within one ulp) scaled by
+// 1 - 2^-20: x (rounded once in float) times it is below x / y by a relative
+// 2^-20 +- 2^-22, so its integer part is the quotient or one less (the
+// quotient is below 2^15, so the shortfall stays below one), and one
+// upward correction makes it exact.
+__device__ __forceinline__ float rcp_down(uint32_t y) {
+    return __builtin_amdgcn_rcpf((float)y) * (1.0f - 0x1p-20f);
+}
+
+__device__ __forceinline__ void divmod_down(uint32_t x, uint32_t y, float rcpd, uint32_t& q, uint32_t& r) {
+    uint32_t qq = (uint32_t)((float)x * rcpd);
+    uint32_t rr = x - __umul24(qq, y);
+    if (rr >= y) {
+        ++qq;
+        rr -= y;
+    }
     q = qq;
-    r = (uint32_t)rr;
+    r = rr;
 }
 
 // Stepping state of a piece at its first voxel, made once per piece by the
 // lane that loaded its record and read by the lanes that run its chunks
-// (16 bytes, like the record):
-//   x: E0, the two minor axes' error terms as biased 16-bit halves
+// (five words):
+//   e: E0, the two minor axes' error terms as biased 16-bit halves
 //      u = r - 2N + 32768 (r the remainder of eq. (3)'s division at k = klo)
-//   y: T, the halves' increments 2a
-//   z: 2N | (len - 1) << 16 | m << 25 | neg_m << 27 | neg_a << 28 | neg_b << 29
-//      (m the dominant axis, a and b the other two in axis order)
-//   w: bit index of the voxel at k = klo inside the brick
-template <int LGX, int LGY>
-__device__ __forceinline__ u32x4 digest_piece(const u32x4& rec, const int32_t org[3]) {
+//   t: T, the halves' increments 2a
+//   s: S, the minor axes' signed strides in the brick, negated, as 16-bit
+//      halves (minor axes a < b in axis order)
+//   v: the dominant axis' signed stride (low half) | 2N << 16 (2 when N = 0)
+//   w: bit index of the voxel at k = klo inside the brick | (len - 1) << kIdxBits
+struct Digest {
+    uint32_t e, t, s, v, w;
+};
+
+template <int LGX, int LGY, int LGZ>
+struct DigestBits {
+    static constexpr int kIdxBits = LGX + LGY + LGZ;
+    static constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
+    // Strides up to 2^(LGX+LGY) as signed 16-bit halves; lengths up to the
+    // brick's largest side above the bit index.
+    static_assert(LGX + LGY <= 14, "strides must fit signed 16-bit halves");
+    static_assert(kIdxBits + (LGX > LGY ? (LGX > LGZ ? LGX : LGZ) : (LGY > LGZ ? LGY : LGZ)) <= 32,
+                  "bit index and length share a word");
+};
+
+template <int LGX, int LGY, int LGZ>
+__device__ __forceinline__ Digest digest_piece(const u32x4& rec, const int32_t org[3]) {
+    using DB = DigestBits<LGX, LGY, LGZ>;
     // Record words: x0|y0<<16, z0|dx<<16, dy|dz<<16, klo|khi<<16.
     const int32_t p0[3] = {(int32_t)(rec.x & 0xFFFFu), (int32_t)(rec.x >> 16), (int32_t)(rec.y & 0xFFFFu)};
     const int32_t d[3] = {(int32_t)(int16_t)(rec.y >> 16), (int32_t)(int16_t)(rec.z & 0xFFFFu),
@@ -534,12 +559,14 @@ __device__ __forceinline__ u32x4 digest_piece(const u32x4& rec, const int32_t or
     const uint32_t aa = m == 0 ? a1 : a0, ab = m == 2 ? a1 : a2;
     const int32_t da = m == 0 ? d[1] : d[0], db = m == 2 ? d[1] : d[2], dm = m == 0 ? d[0] : (m == 1 ? d[1] : d[2]);
     const uint32_t nega = da < 0, negb = db < 0, negm = dm < 0;
-    const uint32_t two_n = 2u * N;
+    // A single-voxel piece (N = 0) is given 2N = 2: its minor axes never
+    // advance (a = b = 0), and every division below stays defined.
+    const uint32_t two_n = N > 0 ? 2u * N : 2u;
     uint32_t qa = 0, ra = 0, qb = 0, rb = 0;
     if (N > 0) {
-        const float rcp = __builtin_amdgcn_rcpf((float)two_n);
-        divmod_rcp(2u * __umul24(klo, aa) + N - nega, two_n, rcp, qa, ra);
-        divmod_rcp(2u * __umul24(klo, ab) + N - negb, two_n, rcp, qb, rb);
+        const float rcpd = rcp_down(two_n);
+        divmod_down(2u * __umul24(klo, aa) + N - nega, two_n, rcpd, qa, ra);
+        divmod_down(2u * __umul24(klo, ab) + N - negb, two_n, rcpd, qb, rb);
     }
     // Voxel at klo, relative to the brick origin.
     const int32_t vm = negm ? -(int32_t)klo : (int32_t)klo;
@@ -547,11 +574,18 @@ __device__ __forceinline__ u32x4 digest_piece(const u32x4& rec, const int32_t or
     const int32_t x = p0[0] - org[0] + (m == 0 ? vm : va);
     const int32_t y = p0[1] - org[1] + (m == 1 ? vm : (m == 0 ? va : vb));
     const int32_t z = p0[2] - org[2] + (m == 2 ? vm : vb);
-    u32x4 g;
-    g.x = ((ra + 32768u - two_n) & 0xFFFFu) | ((rb + 32768u - two_n) << 16);
-    g.y = (2u * aa) | ((2u * ab) << 16);
-    g.z = two_n | ((len - 1u) << 16) | (m << 25) | (negm << 27) | (nega << 28) | (negb << 29);
-    g.w = (uint32_t)(x + (y << LGX) + (z << (LGX + LGY)));
+    // Strides are powers of two: log2 of the dominant axis' and of the
+    // minor axes' strides.
+    const uint32_t shm = m == 0 ? 0u : (m == 1 ? (uint32_t)LGX : (uint32_t)(LGX + LGY));
+    const uint32_t sha = m == 0 ? (uint32_t)LGX : 0u, shb = m == 2 ? (uint32_t)LGX : (uint32_t)(LGX + LGY);
+    const int32_t sm = negm ? -(1 << shm) : (1 << shm);
+    const int32_t sa = nega ? (1 << sha) : -(1 << sha), sb = negb ? (1 << shb) : -(1 << shb);
+    Digest g;
+    g.e = ((ra + 32768u - two_n) & 0xFFFFu) | ((rb + 32768u - two_n) << 16);
+    g.t = (2u * aa) | ((2u * ab) << 16);
+    g.s = ((uint32_t)sa & 0xFFFFu) | ((uint32_t)sb << 16);
+    g.v = ((uint32_t)sm & 0xFFFFu) | (two_n << 16);
+    g.w = (uint32_t)(x + (y << LGX) + (z << (LGX + LGY))) | ((len - 1u) << DB::kIdxBits);
     return g;
 }
 
@@ -560,41 +594,36 @@ __device__ __forceinline__ u32x4 digest_piece(const u32x4& rec, const int32_t or
 //
 // The dominant axis moves by one voxel per step.  Adding 2a to a minor
 // axis' biased half sets its bit 15 exactly when that coordinate advances.
-// An arithmetic shift turns those bits into 0 / -1 halves, which subtract 2N
-// from their halves in one packed multiply-add and add the axes' signed
-// strides to the bit index in one packed dot product (with the strides
-// stored negated).  Needs 2N <= 32768.  A chunk after the first starts from
-// the piece's state advanced by j*kChunk steps: one division per minor axis.
-template <bool kFull, int kChunk, int LGX, int LGY>
-__device__ __forceinline__ void run_chunk(uint32_t* brick, const u32x4& g, uint32_t j) {
-    const uint32_t two_n = g.z & 0xFFFFu;
-    const uint32_t len = ((g.z >> 16) & 0x1FFu) + 1u;
-    const uint32_t m = (g.z >> 25) & 3u;
-    const uint32_t negm = (g.z >> 27) & 1u, nega = (g.z >> 28) & 1u, negb = (g.z >> 29) & 1u;
-    // Strides are powers of two: log2 of the dominant axis' and of the
-    // minor axes' (a < b) strides.
-    const uint32_t shm = m == 0 ? 0u : (m == 1 ? (uint32_t)LGX : (uint32_t)(LGX + LGY));
-    const uint32_t sha = m == 0 ? (uint32_t)LGX : 0u, shb = m == 2 ? (uint32_t)LGX : (uint32_t)(LGX + LGY);
-    // The state advanced by koff steps (koff = 0 for the first chunk leaves it
-    // unchanged): the minor remainders and coordinates by one division each.
+// A packed arithmetic shift turns those bits into 0 / -1 halves, which
+// subtract 2N from their halves in one packed multiply-add and add the axes'
+// signed strides to the bit index in one packed dot product (with the
+// strides stored negated).  Needs 2N <= 32768.  A chunk starts from the
+// piece's state advanced by koff = j*kChunk steps: one division per minor
+// axis gives the remainders and the numbers of advances Q, and the bit index
+// moves by koff dominant strides and Q minor ones (one more dot product,
+// with -Q against the negated strides).
+template <bool kFull, int kChunk, int LGX, int LGY, int LGZ>
+__device__ __forceinline__ void run_chunk(uint32_t* brick, const Digest& g, uint32_t j) {
+    using DB = DigestBits<LGX, LGY, LGZ>;
+    const uint32_t two_n = g.v >> 16;
+    const int32_t sm = (int32_t)(int16_t)(g.v & 0xFFFFu);
     const uint32_t koff = j * (uint32_t)kChunk;
-    // Scalars first: this compiler's __builtin_bit_cast of a vector element
-    // (g.y) reads the vector's first element instead.
-    const uint32_t gx = g.x, gy = g.y;
-    const u16x2 E0 = __builtin_bit_cast(u16x2, gx);
-    const u16x2 T = __builtin_bit_cast(u16x2, gy);
-    const uint32_t y = two_n | (two_n == 0u);  // a single-voxel piece has N = 0
-    const float rcp = __builtin_amdgcn_rcpf((float)y);
+    // Scalars first: this compiler's __builtin_bit_cast of a vector or
+    // struct element can read the wrong element.
+    const uint32_t ge = g.e, gt = g.t, gs = g.s;
+    const u16x2 E0 = __builtin_bit_cast(u16x2, ge);
+    const u16x2 T = __builtin_bit_cast(u16x2, gt);
+    const i16x2 S = __builtin_bit_cast(i16x2, gs);
+    const float rcpd = rcp_down(two_n);
     uint32_t qa, ra, qb, rb;
-    divmod_rcp((uint32_t)E0.x + two_n - 32768u + __umul24(koff, (uint32_t)T.x), y, rcp, qa, ra);
-    divmod_rcp((uint32_t)E0.y + two_n - 32768u + __umul24(koff, (uint32_t)T.y), y, rcp, qb, rb);
+    divmod_down((uint32_t)E0.x + two_n - 32768u + __umul24(koff, (uint32_t)T.x), two_n, rcpd, qa, ra);
+    divmod_down((uint32_t)E0.y + two_n - 32768u + __umul24(koff, (uint32_t)T.y), two_n, rcpd, qb, rb);
     u16x2 E = {(uint16_t)(ra + 32768u - two_n), (uint16_t)(rb + 32768u - two_n)};
-    const int32_t dm = (int32_t)(koff << shm), dqa = (int32_t)(qa << sha), dqb = (int32_t)(qb << shb);
-    int32_t idx = (int32_t)g.w + (negm ? -dm : dm) + (nega ? -dqa : dqa) + (negb ? -dqb : dqb);
-    const int32_t sm = negm ? -(1 << shm) : (1 << shm);
-    const int32_t sa = 1 << sha, sb = 1 << shb;
+    const u16x2 Q = {(uint16_t)qa, (uint16_t)qb};
+    const u16x2 Z = {0, 0};
+    int32_t idx = __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, Z - Q), S,
+                                         (int32_t)(g.w & DB::kIdxMask) + (int32_t)koff * sm, false);
     const u16x2 N2 = {(uint16_t)two_n, (uint16_t)two_n};
-    const i16x2 S = {(int16_t)(nega ? sa : -sa), (int16_t)(negb ? sb : -sb)};
     const i16x2 k15 = {15, 15};
     if constexpr (kFull) {
 #pragma unroll 8
@@ -606,6 +635,7 @@ __device__ __forceinline__ void run_chunk(uint32_t* brick, const u32x4& g, uint3
             idx = __builtin_amdgcn_sdot2(C, S, idx, false) + sm;
         }
     } else {
+        const uint32_t len = (g.w >> DB::kIdxBits) + 1u;
         const int n = (int)(len - koff < (uint32_t)kChunk ? len - koff : (uint32_t)kChunk);
         for (int k = 0; k < n; ++k) {
             atomicOr(&brick[(uint32_t)idx >> 5], 1u << ((uint32_t)idx & 31u));
@@ -733,7 +763,7 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
 
             // This lane's piece as a stepping state (read by the lanes that
             // run its chunks).
-            const u32x4 dg = digest_piece<LGX, LGY>(rec, org);
+            const Digest dg = digest_piece<LGX, LGY, LGZ>(rec, org);
 
             // Chunks of this lane's piece: its full chunks, then its one
             // partial chunk (if any).  The wave's table lists all full
@@ -770,14 +800,15 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
                 const uint32_t c = q + lane;
                 const uint32_t e = c < tt ? my_ent[c] : 0u;
                 const int src = (int)((e & 63u) << 2);
-                const u32x4 g = {(uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.x),
-                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.y),
-                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.z),
-                                 (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.w)};
+                const Digest g = {(uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.e),
+                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.t),
+                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.s),
+                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.v),
+                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.w)};
                 if (q + kWave <= tf) {
-                    run_chunk<true, kChunk, LGX, LGY>(brick, g, e >> 6);
+                    run_chunk<true, kChunk, LGX, LGY, LGZ>(brick, g, e >> 6);
                 } else if (c < tt) {
-                    run_chunk<false, kChunk, LGX, LGY>(brick, g, e >> 6);
+                    run_chunk<false, kChunk, LGX, LGY, LGZ>(brick, g, e >> 6);
                 }
             }
             // The table is rewritten by the next group.
