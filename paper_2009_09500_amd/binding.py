@@ -86,6 +86,11 @@ def load(path: str | None = None):
     if not os.path.exists(p):
         raise RuntimeError("libvox.so not found at %s: build it with "
                            "`python -m paper_2009_09500_amd.build`" % p)
+    # torch first: its HIP libraries ask for the HIP runtime by its bare file
+    # name, libvox.so by its versioned soname.  Loaded in this order, libvox.so
+    # binds to torch's runtime; the other way round the process would hold two
+    # HIP runtimes, and the second to touch the GPU finds no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(p)
     P, i64, i32, u32, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                             ctypes.c_uint32, ctypes.c_size_t)

@@ -647,6 +647,12 @@ __device__ __forceinline__ void run_chunk(uint32_t* brick, const Digest& g, uint
     }
 }
 
+// A piece record, read once: a non-temporal load, so that the stream of
+// records does not push the volume's partly written lines out of the L2.
+__device__ __forceinline__ u32x4 load_stream(const u32x4* p) {
+    return __builtin_nontemporal_load(p);
+}
+
 // Launch shape of the fill kernel per brick shape: threads, voxels per chunk
 // and workgroups per CU.  A 128 KiB brick takes a whole CU (one workgroup of
 // 1024 threads); 64 KiB bricks run two workgroups of 512 threads per CU, so
@@ -658,6 +664,7 @@ struct FillCfg {
     static constexpr int kChunk = 32;
     static constexpr int kWgsPerCu = kBig ? 1 : 2;
 };
+constexpr int kSets = 2;  // piece records per lane in a wave group
 
 // Persistent fill.  Workgroups take bricks from the brick queues (work
 // stealing: bricks differ a lot in work).  Inside a brick the waves work
@@ -676,10 +683,19 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
     constexpr int kWaves = kBlock / kWave;
     constexpr int kMaxChunks = ((1 << Shape::kMaxLg) + kChunk - 1) / kChunk;  // per piece
     constexpr int kUpr = Shape::kBXw / 4;  // 16-byte units per brick row
-    static_assert(kWave * kMaxChunks <= 65536 && kWave <= 64, "chunk entries: lane in 6 bits");
+    constexpr int kGroup = kWave * kSets;  // records per wave group
+    // Chunk table entries per wave: all chunks of a group when the LDS left
+    // by the brick holds them, else a multiple of 64 below that (a group
+    // with more chunks runs its two record sets one after the other).
+    constexpr int kLdsWg = 163840 / Cfg::kWgsPerCu;
+    constexpr int kEntFit = ((kLdsWg - (int)Shape::kBytes - 64) / (2 * kWaves)) / kWave * kWave;
+    constexpr int kEntCap = kGroup * kMaxChunks < kEntFit ? kGroup * kMaxChunks : kEntFit;
+    constexpr bool kSplit = kEntCap < kGroup * kMaxChunks;
+    static_assert(kWave == 64 && kSets == 2 && kMaxChunks <= 512, "chunk entries: lane | set << 6 | j << 7");
+    static_assert(kEntCap >= kWave * kMaxChunks, "one record set's chunks always fit the table");
     // The brick first, so its addresses need no base offset.
     __shared__ __align__(16) uint32_t brick[Shape::kWords];
-    __shared__ uint16_t ent[kWaves][kWave * kMaxChunks];  // per-wave chunk tables
+    __shared__ uint16_t ent[kWaves][kEntCap];  // per-wave chunk tables
     __shared__ uint32_t cursor_s;
     __shared__ uint32_t next_s[3];
 
@@ -744,77 +760,111 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
         // (The brick is zero and cursor_s = p_lo: set before the barrier that
         // ended the previous brick.)
 
-        // This wave's groups of 64 records; the next group is claimed and
-        // loaded before the current one runs.
+        // This wave's groups of 128 records (two per lane: sets 0 and 1); the
+        // next group is claimed and loaded before the current one runs.
         uint32_t gbase = 0;
-        if (lane == 0) gbase = atomicAdd(&cursor_s, (uint32_t)kWave);
+        if (lane == 0) gbase = atomicAdd(&cursor_s, (uint32_t)kGroup);
         gbase = __builtin_amdgcn_readfirstlane(gbase);
-        u32x4 rec_n = (gbase + lane < p_hi) ? recv[gbase + lane] : (u32x4){0u, 0u, 0u, 0u};
+        u32x4 rn0 = (gbase + lane < p_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
+        u32x4 rn1 = (gbase + kWave + lane < p_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
         while (gbase < p_hi) {
-            const uint32_t i = gbase + lane;
-            const u32x4 rec = rec_n;
-            const uint32_t len = i < p_hi ? (rec.w >> 16) - (rec.w & 0xFFFFu) + 1u : 0u;
-            // rec has arrived (len is made from it); the next group's load is
-            // issued only now, so no later wait for rec waits for it too.
-            asm volatile("" ::"v"(len) : "memory");
-            if (lane == 0) gbase = atomicAdd(&cursor_s, (uint32_t)kWave);
+            const u32x4 r0 = rn0, r1 = rn1;
+            const uint32_t len0 = gbase + lane < p_hi ? (r0.w >> 16) - (r0.w & 0xFFFFu) + 1u : 0u;
+            const uint32_t len1 = gbase + kWave + lane < p_hi ? (r1.w >> 16) - (r1.w & 0xFFFFu) + 1u : 0u;
+            // The records have arrived (len0/len1 are made from them); the next
+            // group's loads are issued only now, so no later wait for these
+            // records waits for them too.
+            asm volatile("" ::"v"(len0), "v"(len1) : "memory");
+            if (lane == 0) gbase = atomicAdd(&cursor_s, (uint32_t)kGroup);
             gbase = __builtin_amdgcn_readfirstlane(gbase);
-            rec_n = (gbase + lane < p_hi) ? recv[gbase + lane] : (u32x4){0u, 0u, 0u, 0u};
+            rn0 = (gbase + lane < p_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
+            rn1 = (gbase + kWave + lane < p_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
 
-            // This lane's piece as a stepping state (read by the lanes that
-            // run its chunks).
-            const Digest dg = digest_piece<LGX, LGY, LGZ>(rec, org);
+            // This lane's pieces as stepping states (read by the lanes that
+            // run their chunks).
+            const Digest d0 = digest_piece<LGX, LGY, LGZ>(r0, org);
+            const Digest d1 = digest_piece<LGX, LGY, LGZ>(r1, org);
+            const uint32_t nf0 = len0 / kChunk, pl0 = len0 % kChunk;
+            const uint32_t nf1 = len1 / kChunk, pl1 = len1 % kChunk;
+            // Length class of a partial chunk: 3 (longest) ... 0, or 4 (none).
+            const uint32_t k0 = pl0 == 0 ? 4u : pl0 * 4u / kChunk, k1 = pl1 == 0 ? 4u : pl1 * 4u / kChunk;
 
-            // Chunks of this lane's piece: its full chunks, then its one
-            // partial chunk (if any).  The wave's table lists all full
-            // chunks first, then the partial ones in four length classes,
-            // longest first, so that most rounds run chunks of one length.
-            // Two packed DPP scans count all five lists (full chunks: at most
-            // 64 * kMaxChunks; each class: at most 64).
-            const uint32_t nfull = len / kChunk, pl = len % kChunk;
-            const uint32_t c3 = pl >= 3 * kChunk / 4, c2 = pl >= kChunk / 2 && pl < 3 * kChunk / 4;
-            const uint32_t c1 = pl >= kChunk / 4 && pl < kChunk / 2, c0 = pl > 0 && pl < kChunk / 4;
-            const uint32_t ia = wave_inclusive_sum_dpp(nfull | (c3 << 16));
-            const uint32_t ib = wave_inclusive_sum_dpp(c2 | (c1 << 10) | (c0 << 20));
-            const uint32_t ta = __builtin_amdgcn_readlane(ia, kWave - 1);
-            const uint32_t tb = __builtin_amdgcn_readlane(ib, kWave - 1);
-            const uint32_t tf = ta & 0xFFFFu;                      // full chunks
-            const uint32_t o2 = tf + (ta >> 16);                   // start of class 2
-            const uint32_t o1 = o2 + (tb & 0x3FFu);
-            const uint32_t o0 = o1 + ((tb >> 10) & 0x3FFu);
-            const uint32_t tt = o0 + (tb >> 20);
-            for (uint32_t j = 0; j < nfull; ++j) my_ent[(ia & 0xFFFFu) - nfull + j] = (uint16_t)(lane | (j << 6));
-            if (pl) {
-                const uint32_t pos = c3   ? tf + (ia >> 16) - 1u
-                                     : c2 ? o2 + (ib & 0x3FFu) - 1u
-                                     : c1 ? o1 + ((ib >> 10) & 0x3FFu) - 1u
-                                          : o0 + (ib >> 20) - 1u;
-                my_ent[pos] = (uint16_t)(lane | (nfull << 6));
-            }
-            // Make the table writes visible to the wave's own reads below.
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-            for (uint32_t q = 0; q < tt; q += kWave) {
-                const uint32_t c = q + lane;
-                const uint32_t e = c < tt ? my_ent[c] : 0u;
-                const int src = (int)((e & 63u) << 2);
-                const Digest g = {(uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.e),
-                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.t),
-                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.s),
-                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.v),
-                                  (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)dg.w)};
-                if (q + kWave <= tf) {
-                    run_chunk<true, kChunk, LGX, LGY, LGZ>(brick, g, e >> 6);
-                } else if (c < tt) {
-                    run_chunk<false, kChunk, LGX, LGY, LGZ>(brick, g, e >> 6);
+            // Chunks of this lane's pieces: their full chunks, then their
+            // partial chunks.  The wave's table lists all full chunks first,
+            // then the partial ones in four length classes, longest first, so
+            // that most rounds run chunks of one length.  Two packed DPP scans
+            // count all five lists.  Sets 0 and 1 share one table, or take
+            // turns when their chunks overflow it.
+            uint32_t sets = 3u;
+            for (;;) {
+                const uint32_t u0 = sets & 1u, u1 = sets >> 1;
+                const uint32_t f0 = u0 ? nf0 : 0u, f1 = u1 ? nf1 : 0u;
+                const uint32_t q0 = u0 ? k0 : 4u, q1 = u1 ? k1 : 4u;
+                const uint32_t c3 = (q0 == 3u) + (q1 == 3u), c2 = (q0 == 2u) + (q1 == 2u);
+                const uint32_t c1 = (q0 == 1u) + (q1 == 1u), c0 = (q0 == 0u) + (q1 == 0u);
+                const uint32_t ia = wave_inclusive_sum_dpp((f0 + f1) | (c3 << 16));
+                const uint32_t ib = wave_inclusive_sum_dpp(c2 | (c1 << 10) | (c0 << 20));
+                const uint32_t ta = __builtin_amdgcn_readlane(ia, kWave - 1);
+                const uint32_t tb = __builtin_amdgcn_readlane(ib, kWave - 1);
+                const uint32_t tf = ta & 0xFFFFu;                      // full chunks
+                const uint32_t o2 = tf + (ta >> 16);                   // start of class 2
+                const uint32_t o1 = o2 + (tb & 0x3FFu);
+                const uint32_t o0 = o1 + ((tb >> 10) & 0x3FFu);
+                const uint32_t tt = o0 + (tb >> 20);
+                if (kSplit && tt > (uint32_t)kEntCap) {
+                    sets = 1u;  // set 0 now, set 1 next
+                    continue;
                 }
+                {
+                    const uint32_t fb = (ia & 0xFFFFu) - f0 - f1;
+                    for (uint32_t j = 0; j < f0; ++j) my_ent[fb + j] = (uint16_t)(lane | (j << 7));
+                    for (uint32_t j = 0; j < f1; ++j) my_ent[fb + f0 + j] = (uint16_t)(lane | 64u | (j << 7));
+                    // End of this lane's run in each class list.
+                    const uint32_t e3 = tf + (ia >> 16), e2 = o2 + (ib & 0x3FFu);
+                    const uint32_t e1 = o1 + ((ib >> 10) & 0x3FFu), e0 = o0 + (ib >> 20);
+                    if (q0 < 4u) {
+                        const uint32_t pos = q0 == 3u ? e3 - c3 : q0 == 2u ? e2 - c2 : q0 == 1u ? e1 - c1 : e0 - c0;
+                        my_ent[pos] = (uint16_t)(lane | (nf0 << 7));
+                    }
+                    if (q1 < 4u) {
+                        const uint32_t pos = q1 == 3u ? e3 - 1u : q1 == 2u ? e2 - 1u : q1 == 1u ? e1 - 1u : e0 - 1u;
+                        my_ent[pos] = (uint16_t)(lane | 64u | (nf1 << 7));
+                    }
+                }
+                // Make the table writes visible to the wave's own reads below.
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+                for (uint32_t q = 0; q < tt; q += kWave) {
+                    const uint32_t c = q + lane;
+                    const uint32_t e = c < tt ? my_ent[c] : 0u;
+                    const int src = (int)((e & 63u) << 2);
+                    const bool s1 = (e & 64u) != 0u;
+                    const uint32_t ge0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.e);
+                    const uint32_t ge1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.e);
+                    const uint32_t gt0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.t);
+                    const uint32_t gt1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.t);
+                    const uint32_t gs0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.s);
+                    const uint32_t gs1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.s);
+                    const uint32_t gv0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.v);
+                    const uint32_t gv1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.v);
+                    const uint32_t gw0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.w);
+                    const uint32_t gw1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.w);
+                    const Digest g = {s1 ? ge1 : ge0, s1 ? gt1 : gt0, s1 ? gs1 : gs0, s1 ? gv1 : gv0, s1 ? gw1 : gw0};
+                    if (q + kWave <= tf) {
+                        run_chunk<true, kChunk, LGX, LGY, LGZ>(brick, g, e >> 7);
+                    } else if (c < tt) {
+                        run_chunk<false, kChunk, LGX, LGY, LGZ>(brick, g, e >> 7);
+                    }
+                }
+                // The table is rewritten by the next pass or group.
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (sets != 1u) break;
+                sets = 2u;
             }
-            // The table is rewritten by the next group.
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         // Hand over the next brick (read by all after the barrier).
         if (threadIdx.x == 0) {

@@ -135,6 +135,25 @@ def test_every_brick_shape(lg):
         binding.vox_set_tuning(None)
 
 
+@pytest.mark.parametrize("lg", [(8, 6, 5), (8, 6, 6)])
+def test_full_length_pieces(lg):
+    """Pieces as long as the brick is wide: a fill group's chunks overflow its
+    table, so its two record sets run one after the other."""
+    binding.vox_set_tuning(lg)
+    try:
+        dims = (512, 64, 64)
+        rng = np.random.default_rng(21)
+        n = 4096
+        y0 = rng.integers(3, 61, n)
+        z0 = rng.integers(3, 61, n)
+        segs = np.stack([np.zeros(n, np.int64), y0, z0, np.full(n, 511), y0 + rng.integers(-3, 4, n),
+                         z0 + rng.integers(-3, 4, n)], 1).astype(np.int32)
+        segs[::2] = segs[::2][:, [3, 4, 5, 0, 1, 2]]  # both directions
+        assert_grid(segs, dims)
+    finally:
+        binding.vox_set_tuning(None)
+
+
 def test_unsupported_shape_rejected():
     with pytest.raises(binding.VoxError):
         binding.vox_set_tuning((9, 9, 9))
