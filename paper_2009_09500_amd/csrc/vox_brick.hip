@@ -208,6 +208,8 @@ struct StagedSeg {
 };
 
 constexpr int kStage = 4096;      // segments staged per round
+constexpr int kStageBig = 8192;   // ... by the histogram when its counters leave room
+constexpr uint32_t kBigStageBricks = 8192;  // bricks per scene up to which they do
 constexpr int kOrderBins = 64;
 
 // Staged segments ordered by their number of bricks, longest walks first, so
@@ -215,9 +217,10 @@ constexpr int kOrderBins = 64;
 // start together and finish together.  The count used is
 // 1 + sum_a |brick_a(P1) - brick_a(P0)| (exact unless two axes cross at the
 // same k), clamped to the last bucket.
+template <int kN>
 struct Stage {
-    StagedSeg seg[kStage];
-    uint16_t order[kStage];
+    StagedSeg seg[kN];
+    uint16_t order[kN];
     uint32_t bins[kOrderBins];  // bucket sizes, then bucket cursors
     uint32_t nvalid;
 };
@@ -235,8 +238,9 @@ __device__ __forceinline__ uint32_t order_bin(const StagedSeg& g, const BrickGeo
 // Loads segments [base, base + cnt) into the stage (all threads of the
 // block), writes counts, flags out-of-volume segments, and builds the order
 // of the in-volume ones.
+template <int kN>
 __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs, int64_t base, uint32_t cnt,
-                                               const BrickGeom& bg, Stage& st, int32_t* __restrict__ counts,
+                                               const BrickGeom& bg, Stage<kN>& st, int32_t* __restrict__ counts,
                                                bool& bad) {
     if (threadIdx.x < kOrderBins) st.bins[threadIdx.x] = 0;
     lds_barrier();
@@ -280,7 +284,8 @@ __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs,
     }
     lds_barrier();
 }
-static_assert(kStage / kHistBlock <= 32, "one validity bit per staged segment and thread");
+static_assert(kStage / kHistBlock <= 32 && kStageBig / kHistBlock <= 32 && kStageBig <= 65536,
+              "one validity bit per staged segment and thread; 16-bit order entries");
 
 struct WalkState {
     AxisCross c[3];
@@ -309,8 +314,8 @@ __device__ __forceinline__ void walk_init(WalkState& w, const StagedSeg& g, cons
 // and steps all of them one brick at a time until the wave's last segment
 // ends.  emit(brick id, klo, khi, staged index) per piece, [klo, khi] being
 // the segment's k-window inside the brick.
-template <typename Emit>
-__device__ __forceinline__ void walk_ordered(const Stage& st, const BrickGeom& bg, Emit emit) {
+template <int kN, typename Emit>
+__device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeom& bg, Emit emit) {
     const uint32_t lane = __lane_id();
     const uint32_t nvalid = st.nvalid;
     for (uint32_t base = threadIdx.x - lane; base < nvalid; base += kHistBlock) {
@@ -341,10 +346,11 @@ __device__ __forceinline__ void walk_ordered(const Stage& st, const BrickGeom& b
     }
 }
 
+template <int kN>
 __global__ __launch_bounds__(kHistBlock) void k_brick_hist(const uint8_t* __restrict__ table,
                                                            uint8_t* __restrict__ work) {
     extern __shared__ uint32_t lh[];
-    __shared__ Stage st;
+    __shared__ Stage<kN> st;
     const TableView tv = table_view(table);
     const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
     const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
@@ -357,8 +363,8 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_hist(const uint8_t* __rest
     int64_t lo, hi;
     seg_range(sc.n, (int)g, (int)sc.rows, lo, hi);
     bool bad = false;
-    for (int64_t base = lo; base < hi; base += kStage) {
-        const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
+    for (int64_t base = lo; base < hi; base += kN) {
+        const uint32_t cnt = (uint32_t)(hi - base < kN ? hi - base : kN);
         stage_segments(sc.segs, base, cnt, bg, st, sc.counts, bad);
         walk_ordered(st, bg, [&](uint32_t b, uint32_t, uint32_t, uint32_t) { atomicAdd(&lh[b], 1u); });
         lds_barrier();
@@ -449,7 +455,7 @@ __global__ __launch_bounds__(kBaseBlock) void k_brick_base(const uint8_t* __rest
 __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(const uint8_t* __restrict__ table,
                                                               uint8_t* __restrict__ work) {
     extern __shared__ uint32_t cur[];
-    __shared__ Stage st;
+    __shared__ Stage<kStage> st;
     const TableView tv = table_view(table);
     const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
     const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
@@ -1023,15 +1029,18 @@ hipError_t launch_bricks(const void* d_table, const BrickLaunch& L, const BrickT
     const uint8_t* table = one ? work + kWorkTable : static_cast<const uint8_t*>(d_table);
     hipError_t e;
     {
-        // The histogram kernels may use up to 64 KiB of dynamic LDS.
+        // The histogram kernels may use up to 64 KiB of dynamic LDS (the
+        // histogram with big stages: what its stage leaves).
         static hipError_t attr = [] {
-            const void* ks[2] = {(const void*)k_brick_hist, (const void*)k_brick_scatter};
+            const void* ks[2] = {(const void*)k_brick_hist<kStage>, (const void*)k_brick_scatter};
             for (const void* k : ks) {
                 hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    (int)(kMaxBricks * sizeof(uint32_t)));
                 if (r != hipSuccess) return r;
             }
-            return hipSuccess;
+            return hipFuncSetAttribute((const void*)k_brick_hist<kStageBig>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kBigStageBricks * sizeof(uint32_t)));
         }();
         if (attr != hipSuccess) return attr;
     }
@@ -1049,7 +1058,10 @@ hipError_t launch_bricks(const void* d_table, const BrickLaunch& L, const BrickT
     const size_t hist_lds = (size_t)L.max_nb * sizeof(uint32_t);
     {
         KernelTimer t("brick_hist", stream);
-        k_brick_hist<<<L.rows, kHistBlock, hist_lds, stream>>>(table, work);
+        if (L.max_nb <= kBigStageBricks)
+            k_brick_hist<kStageBig><<<L.rows, kHistBlock, hist_lds, stream>>>(table, work);
+        else
+            k_brick_hist<kStage><<<L.rows, kHistBlock, hist_lds, stream>>>(table, work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {

@@ -154,6 +154,17 @@ def test_full_length_pieces(lg):
         binding.vox_set_tuning(None)
 
 
+def test_more_bricks_than_big_stages():
+    """A volume of more than 8192 bricks: its histogram stages 4096 segments
+    per round (the big stages leave too little LDS for its counters)."""
+    binding.vox_set_tuning((7, 6, 6))
+    try:
+        dims = (2048, 2048, 1088)             # 16 x 32 x 17 = 8704 bricks
+        assert_grid(random_in(dims, 20_000, 23), dims)
+    finally:
+        binding.vox_set_tuning(None)
+
+
 def test_unsupported_shape_rejected():
     with pytest.raises(binding.VoxError):
         binding.vox_set_tuning((9, 9, 9))
