@@ -501,28 +501,6 @@ struct BrickShape {
     static constexpr int kMaxLg = LGX > LGY ? (LGX > LGZ ? LGX : LGZ) : (LGY > LGZ ? LGY : LGZ);
 };
 
-// floor(x / y) and remainder for x < 2^31, 2 <= y < 2^16 and quotients
-// below 2^15, from a hardware reciprocal estimate corrected in integers
-// (exact).  rcp_down(y) is the reciprocal (within one ulp) scaled by
-// 1 - 2^-20: x (rounded once in float) times it is below x / y by a relative
-// 2^-20 +- 2^-22, so its integer part is the quotient or one less (the
-// quotient is below 2^15, so the shortfall stays below one), and one
-// upward correction makes it exact.
-__device__ __forceinline__ float rcp_down(uint32_t y) {
-    return __builtin_amdgcn_rcpf((float)y) * (1.0f - 0x1p-20f);
-}
-
-__device__ __forceinline__ void divmod_down(uint32_t x, uint32_t y, float rcpd, uint32_t& q, uint32_t& r) {
-    uint32_t qq = (uint32_t)((float)x * rcpd);
-    uint32_t rr = x - __umul24(qq, y);
-    if (rr >= y) {
-        ++qq;
-        rr -= y;
-    }
-    q = qq;
-    r = rr;
-}
-
 // Stepping state of a piece at its first voxel, made once per piece by the
 // lane that loaded its record and read by the lanes that run its chunks
 // (five words):

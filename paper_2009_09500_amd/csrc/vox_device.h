@@ -65,28 +65,56 @@ __device__ __forceinline__ bool in_int16(const Seg& s) {
 // to the numerator; as 2a <= 2N the quotient grows by at most one:
 //   r += 2a;  if (r >= 2N) { r -= 2N; ++q; }
 // This is Bresenham's error term; it reproduces the division exactly.
+// floor(x / y) and remainder for x < 2^31, 2 <= y < 2^16 and quotients
+// below 2^15, from a hardware reciprocal estimate corrected in integers
+// (exact).  rcp_down(y) is the reciprocal (within one ulp) scaled by
+// 1 - 2^-20: x (rounded once in float) times it is below x / y by a relative
+// 2^-20 +- 2^-22, so its integer part is the quotient or one less (the
+// quotient is below 2^15, so the shortfall stays below one), and one
+// upward correction makes it exact.
+__device__ __forceinline__ float rcp_down(uint32_t y) {
+    return __builtin_amdgcn_rcpf((float)y) * (1.0f - 0x1p-20f);
+}
+
+__device__ __forceinline__ void divmod_down(uint32_t x, uint32_t y, float rcpd, uint32_t& q, uint32_t& r) {
+    uint32_t qq = (uint32_t)((float)x * rcpd);
+    uint32_t rr = x - __umul24(qq, y);
+    if (rr >= y) {
+        ++qq;
+        rr -= y;
+    }
+    q = qq;
+    r = rr;
+}
+
 struct AxisStep {
     uint32_t q, r, two_a;
 };
 
-// Quotient and remainder of (2 k a + N - neg) / 2N for N >= 1.  32-bit when
-// the numerator fits (N <= 32767, as for every int16 coordinate pair except
-// the extreme ones), else 64-bit.
-__device__ __forceinline__ AxisStep axis_init(uint32_t a, uint32_t neg, uint32_t N, uint32_t k) {
-    AxisStep st;
-    st.two_a = 2u * a;
-    uint32_t two_n = 2u * N;
+// Quotients and remainders of (2 k a + N - neg) / 2N, per axis, for N >= 1
+// and k <= N.  Up to N = 32767 the numerators stay below 2^31 and the
+// quotients at most a < 2^15, so one reciprocal serves all three axes
+// (divmod_down); beyond that, 64-bit divisions.
+__device__ __forceinline__ void axis_init3(const uint32_t a[3], const uint32_t neg[3], uint32_t N, uint32_t k,
+                                           AxisStep st[3]) {
+    const uint32_t two_n = 2u * N;
     if (N <= 32767u) {
-        uint32_t num = 2u * k * a + N - neg;
-        st.q = num / two_n;
-        st.r = num - st.q * two_n;
+        const float rcpd = rcp_down(two_n);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            st[ax].two_a = 2u * a[ax];
+            divmod_down(2u * k * a[ax] + N - neg[ax], two_n, rcpd, st[ax].q, st[ax].r);
+        }
     } else {
-        uint64_t num = 2ull * k * a + N - neg;
-        uint64_t q = num / two_n;
-        st.q = (uint32_t)q;
-        st.r = (uint32_t)(num - q * two_n);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            st[ax].two_a = 2u * a[ax];
+            const uint64_t num = 2ull * k * a[ax] + N - neg[ax];
+            const uint64_t q = num / two_n;
+            st[ax].q = (uint32_t)q;
+            st[ax].r = (uint32_t)(num - q * two_n);
+        }
     }
-    return st;
 }
 
 __device__ __forceinline__ void axis_step(AxisStep& st, uint32_t two_n) {

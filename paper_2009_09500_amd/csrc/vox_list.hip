@@ -197,8 +197,7 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) st[ax] = AxisStep{0u, 0u, 0u};
         } else {
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) st[ax] = axis_init(a[ax], neg[ax], N, k);
+            axis_init3(a, neg, N, k, st);
         }
         uint32_t two_n = 2u * N;
         int16_t out[kListPerThread * 3];
