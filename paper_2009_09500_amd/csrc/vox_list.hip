@@ -136,9 +136,15 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     const int32_t* __restrict__ tile_seg, int16_t* __restrict__ voxels,
     const int64_t* __restrict__ total_p, const int32_t* __restrict__ status) {
     constexpr int kMaxSegs = (int)kListTile + 1;
-    __shared__ PackedSeg sseg[kMaxSegs];
+    constexpr int kSegWords = (int)(kMaxSegs * sizeof(PackedSeg) / 4);
+    constexpr int kStageWords = (int)(kListTile * 3 / 2);
+    // The staged segments and the output stage share LDS (the segments are
+    // dead once every lane has its voxels): 16 KiB a block, 8 blocks a CU.
+    __shared__ __align__(16) uint32_t lds_raw[kSegWords > kStageWords ? kSegWords : kStageWords];
     __shared__ int32_t srel[kMaxSegs + 1];
-    __shared__ uint32_t stage[kListTile * 3 / 2];
+    PackedSeg* sseg = reinterpret_cast<PackedSeg*>(lds_raw);
+    uint32_t* stage = lds_raw;
+    static_assert(sizeof(PackedSeg) == 12 && (kMaxSegs * sizeof(PackedSeg)) % 4 == 0, "packed segments");
 
     if (*status != 0) return;
     const int64_t total = *total_p;
@@ -172,6 +178,7 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 
     const int first = threadIdx.x * kListPerThread;  // tile-relative voxel
     const int count = (int)(j1 - j0);
+    int16_t out[kListPerThread * 3];
     if (first < count) {
         // Segment of the first voxel: largest s with srel[s] <= first.
         int lo = 0, hi = nseg - 1;
@@ -200,7 +207,6 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
             axis_init3(a, neg, N, k, st);
         }
         uint32_t two_n = 2u * N;
-        int16_t out[kListPerThread * 3];
 #pragma unroll
         for (int v = 0; v < kListPerThread; ++v) {
             const int j = first + v;
@@ -232,6 +238,9 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
                 axis_step(st[ax], two_n);
             }
         }
+    }
+    __syncthreads();  // the staged segments are dead from here
+    if (first < count) {
         // Stage: lane t owns 3*P int16 = 3*P/2 words at word 3*P/2*t.
         uint32_t* dst = stage + (kListPerThread * 3 / 2) * threadIdx.x;
 #pragma unroll
