@@ -637,6 +637,18 @@ __device__ __forceinline__ u32x4 load_stream(const u32x4* p) {
     return __builtin_nontemporal_load(p);
 }
 
+// A brick's records [lo, hi) in four quarters, one per SIMD of the CU.
+constexpr int kQuarters = 4;
+
+__device__ __forceinline__ uint32_t quarter_bound(uint32_t lo, uint32_t hi, uint32_t k) {
+    return lo + (uint32_t)(((uint64_t)(hi - lo) * k) / kQuarters);
+}
+
+__device__ __forceinline__ void set_quarters(uint32_t* cursors, uint32_t lo, uint32_t hi) {
+#pragma unroll
+    for (uint32_t k = 0; k < (uint32_t)kQuarters; ++k) cursors[k] = quarter_bound(lo, hi, k);
+}
+
 // Launch shape of the fill kernel per brick shape: threads, voxels per chunk
 // and workgroups per CU.  A 128 KiB brick takes a whole CU (one workgroup of
 // 1024 threads); 64 KiB bricks run two workgroups of 512 threads per CU, so
@@ -680,7 +692,7 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
     // The brick first, so its addresses need no base offset.
     __shared__ __align__(16) uint32_t brick[Shape::kWords];
     __shared__ uint16_t ent[kWaves][kEntCap];  // per-wave chunk tables
-    __shared__ uint32_t cursor_s;
+    __shared__ uint32_t cursor_s[kQuarters];  // per-SIMD record cursors of the brick
     __shared__ uint32_t next_s[3];
 
     const TableView tv = table_view(table);
@@ -701,7 +713,7 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
         next_s[0] = nb;
         next_s[1] = nb < NB ? bin_base[nb] : 0u;
         next_s[2] = nb < NB ? bin_base[nb + 1] : 0u;
-        cursor_s = next_s[1];
+        set_quarters(cursor_s, next_s[1], next_s[2]);
     }
     {
         u32x4* b4 = reinterpret_cast<u32x4*>(brick);
@@ -741,28 +753,33 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
                 ext[ax] = e < (1 << lgs[ax]) ? e : (1 << lgs[ax]);
             }
         }
-        // (The brick is zero and cursor_s = p_lo: set before the barrier that
+        // (The brick is zero and the cursors set: done before the barrier that
         // ended the previous brick.)
 
-        // This wave's groups of 128 records (two per lane: sets 0 and 1); the
-        // next group is claimed and loaded before the current one runs.
+        // This wave's groups of 128 records (two per lane: sets 0 and 1),
+        // taken from its SIMD's quarter of the brick's records (waves w and
+        // w + 4k share a SIMD), so the four SIMDs get even shares of the
+        // brick's work; the next group is claimed and loaded before the
+        // current one runs.
+        const uint32_t qu = wave % kQuarters;
+        const uint32_t q_hi = quarter_bound(p_lo, p_hi, qu + 1u);
         uint32_t gbase = 0;
-        if (lane == 0) gbase = atomicAdd(&cursor_s, (uint32_t)kGroup);
+        if (lane == 0) gbase = atomicAdd(&cursor_s[qu], (uint32_t)kGroup);
         gbase = __builtin_amdgcn_readfirstlane(gbase);
-        u32x4 rn0 = (gbase + lane < p_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
-        u32x4 rn1 = (gbase + kWave + lane < p_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
-        while (gbase < p_hi) {
+        u32x4 rn0 = (gbase + lane < q_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
+        u32x4 rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
+        while (gbase < q_hi) {
             const u32x4 r0 = rn0, r1 = rn1;
-            const uint32_t len0 = gbase + lane < p_hi ? (r0.w >> 16) - (r0.w & 0xFFFFu) + 1u : 0u;
-            const uint32_t len1 = gbase + kWave + lane < p_hi ? (r1.w >> 16) - (r1.w & 0xFFFFu) + 1u : 0u;
+            const uint32_t len0 = gbase + lane < q_hi ? (r0.w >> 16) - (r0.w & 0xFFFFu) + 1u : 0u;
+            const uint32_t len1 = gbase + kWave + lane < q_hi ? (r1.w >> 16) - (r1.w & 0xFFFFu) + 1u : 0u;
             // The records have arrived (len0/len1 are made from them); the next
             // group's loads are issued only now, so no later wait for these
             // records waits for them too.
             asm volatile("" ::"v"(len0), "v"(len1) : "memory");
-            if (lane == 0) gbase = atomicAdd(&cursor_s, (uint32_t)kGroup);
+            if (lane == 0) gbase = atomicAdd(&cursor_s[qu], (uint32_t)kGroup);
             gbase = __builtin_amdgcn_readfirstlane(gbase);
-            rn0 = (gbase + lane < p_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
-            rn1 = (gbase + kWave + lane < p_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
+            rn0 = (gbase + lane < q_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
+            rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
 
             // This lane's pieces as stepping states (read by the lanes that
             // run their chunks).
@@ -905,7 +922,7 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
         b = next_s[0];
         p_lo = next_s[1];
         p_hi = next_s[2];
-        if (threadIdx.x == 0) cursor_s = p_lo;
+        if (threadIdx.x == 0) set_quarters(cursor_s, p_lo, p_hi);
         lds_barrier();
     }
 }
