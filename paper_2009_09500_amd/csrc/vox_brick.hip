@@ -665,11 +665,12 @@ constexpr int kSets = 2;  // piece records per lane in a wave group
 // Persistent fill.  Workgroups take bricks from the brick queues (work
 // stealing: bricks differ a lot in work).  Inside a brick the waves work
 // independently, with no workgroup barrier until the brick is done: a wave
-// takes the next 64 piece records (one per lane), cuts them into chunks of at
-// most kChunk voxels, lists the chunks in its own LDS table (full chunks
-// first) and runs them in rounds of 64, one chunk per lane, reading each
-// chunk's record from the owning lane with ds_bpermute.  The next 64 records
-// are loaded while the current ones run.
+// takes the next 128 piece records of its SIMD's quarter of the brick (two
+// per lane), turns them into digests, cuts the pieces into chunks of at most
+// kChunk voxels, lists the chunks in its own LDS table (full chunks first)
+// and runs them in rounds of 64, one chunk per lane, reading each chunk's
+// digest from the owning lane with ds_bpermute.  The next 128 records are
+// loaded while the current ones run.
 template <int LGX, int LGY, int LGZ>
 __global__ __launch_bounds__((FillCfg<LGX, LGY, LGZ>::kBlock), (FillCfg<LGX, LGY, LGZ>::kWgsPerCu))
 void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work) {
