@@ -882,10 +882,37 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
         const int rows = ext[1] * ext[2];
         // Whole 16-byte units when the volume's rows hold whole brick rows.
         const bool vec = Shape::kBXw % 4 == 0 && (bg.dim[0] & ((1 << LGX) - 1)) == 0;
-        if (vec) {
+        const bool full_y = ext[1] == (1 << LGY);  // rows per slab a power of two
+        if (vec && full_y) {
+            // 16-byte units, kUpr per row, rows full width and full slabs:
+            // a thread's units share their row in the slab and their part of
+            // the row, and step by a fixed number of slabs (kBlock units are
+            // a whole number of slabs in every compiled shape).
+            constexpr int kRowsPerStep = kBlock / kUpr;
+            static_assert(kBlock % kUpr == 0 && kRowsPerStep % (1 << LGY) == 0, "whole slabs per step");
+            constexpr int kSlabsPerStep = kRowsPerStep >> LGY;
+            const int units = rows * kUpr;
+            const int part = (int)threadIdx.x % kUpr, r0 = (int)threadIdx.x / kUpr;
+            const int y = r0 & ((1 << LGY) - 1), z0 = r0 >> LGY;
+            u32x4* src = reinterpret_cast<u32x4*>(
+                &brick[(((uint32_t)z0 << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + 4u * part]);
+            global_u32x4* dst = (global_u32x4*)(
+                grid + ((int64_t)(org[2] + z0) * bg.dim[1] + (org[1] + y)) * row_words + (org[0] >> 5) + 4 * part);
+            const int64_t dst_step = (int64_t)kSlabsPerStep * bg.dim[1] * row_words / 4;  // in 16-byte units
+            for (int t = threadIdx.x; t < units; t += kBlock) {
+                const u32x4 v = *src;
+                *src = (u32x4){0u, 0u, 0u, 0u};  // zero for the next brick
+                if (clear) {
+                    *dst = v;
+                } else {
+                    *dst = *dst | v;
+                }
+                src += kBlock;
+                dst += dst_step;
+            }
+        } else if (vec) {
             // 16-byte units, kUpr per row, rows full width.
             const int units = rows * kUpr;
-            const bool full_y = ext[1] == (1 << LGY);  // rows per slab a power of two
             for (int t = threadIdx.x; t < units; t += kBlock) {
                 const int part = t % kUpr, r = t / kUpr;
                 const int y = full_y ? (r & ((1 << LGY) - 1)) : r % ext[1];
