@@ -327,8 +327,9 @@ def main():
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X and has "
-              "no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X and has "
+              "no multi-GPU path (sharding is described, not implemented); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
