@@ -322,26 +322,26 @@ __device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeo
         const uint32_t i = base + lane;
         bool active = i < nvalid;
         uint32_t j = 0;
-        WalkState w;
+        WalkState w = {};
         if (active) {
             j = st.order[i];
             walk_init(w, st.seg[j], bg);
         }
         while (__ballot(active)) {
-            if (active) {
-                uint32_t km = w.c[0].kn < w.c[1].kn ? w.c[0].kn : w.c[1].kn;
-                km = km < w.c[2].kn ? km : w.c[2].kn;
-                emit((uint32_t)((w.c[2].b * bg.nb[1] + w.c[1].b) * bg.nb[0] + w.c[0].b), w.klo,
-                     km == kNever ? w.N : km - 1u, j);
-                if (km == kNever) {
-                    active = false;
-                } else {
+            uint32_t km = w.c[0].kn < w.c[1].kn ? w.c[0].kn : w.c[1].kn;
+            km = km < w.c[2].kn ? km : w.c[2].kn;
+            // Brick ids and counts stay below 2^24: 24-bit multiplies.
+            if (active)
+                emit(__umul24(__umul24((uint32_t)w.c[2].b, (uint32_t)bg.nb[1]) + (uint32_t)w.c[1].b,
+                              (uint32_t)bg.nb[0]) +
+                         (uint32_t)w.c[0].b,
+                     w.klo, km == kNever ? w.N : km - 1u, j);
+            // The rest with selects only (lanes step different segments).
+            const bool go = active && km != kNever;
 #pragma unroll
-                    for (int ax = 0; ax < 3; ++ax)
-                        if (w.c[ax].kn == km) cross_step(w.c[ax]);
-                    w.klo = km;
-                }
-            }
+            for (int ax = 0; ax < 3; ++ax) cross_advance(w.c[ax], go && w.c[ax].kn == km);
+            w.klo = go ? km : w.klo;
+            active = go;
         }
     }
 }

@@ -93,17 +93,21 @@ __host__ __device__ __forceinline__ void cross_init(AxisCross& c, int32_t p0, in
     divmod_u64(2ull * N * B, c.D, c.Q, c.R);
 }
 
-// Advances an axis whose crossing c.kn has just happened.
-__host__ __device__ __forceinline__ void cross_step(AxisCross& c) {
-    c.b += c.dir;
-    if (c.b == c.bend) {
-        c.kn = kNever;
-        return;
-    }
+// Advances an axis if `hit` (its crossing c.kn has just happened), written
+// with selects only so that a wave stepping many segments does not branch.
+__host__ __device__ __forceinline__ void cross_advance(AxisCross& c, bool hit) {
+    const int32_t nb = c.b + c.dir;
+    const bool last = nb == c.bend;
     const uint32_t carry = c.sl < c.R ? 1u : 0u;
-    c.kn += c.Q + carry;
-    c.sl = c.sl + (carry ? c.D : 0u) - c.R;
+    const uint32_t kn = last ? kNever : c.kn + c.Q + carry;
+    const uint32_t sl = last ? c.sl : c.sl + (carry ? c.D : 0u) - c.R;
+    c.b = hit ? nb : c.b;
+    c.kn = hit ? kn : c.kn;
+    c.sl = hit ? sl : c.sl;
 }
+
+// Advances an axis whose crossing c.kn has just happened.
+__host__ __device__ __forceinline__ void cross_step(AxisCross& c) { cross_advance(c, true); }
 
 struct SegAxes {
     int32_t p0[3];
@@ -143,9 +147,7 @@ __host__ __device__ __forceinline__ void walk_bricks(const SegAxes& s, const Bri
         emit((uint32_t)((c[2].b * bg.nb[1] + c[1].b) * bg.nb[0] + c[0].b), klo, km == kNever ? s.N : km - 1u);
         if (km == kNever) break;
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            if (c[ax].kn == km) cross_step(c[ax]);
-        }
+        for (int ax = 0; ax < 3; ++ax) cross_advance(c[ax], c[ax].kn == km);
         klo = km;
     }
 }
