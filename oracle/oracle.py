@@ -5,6 +5,8 @@ benchmark's CPU-baseline leg use this module to compute the expected output of
 the parametric voxelization (arXiv 2009.09500, Section 3, eq. (2)-(3) and the
 algorithm of Fig. 3, with N = max|d_a| and round-half-up voxel rounding).  The
 product path never imports it.  It shares no code with the HIP library.
+The `*_euclid` functions state the paper's literal variant with the
+Euclidean N of eq. (1) (N = int(|E - S|), consecutive duplicates removed).
 
 The C source is compiled with gcc into oracle/liboracle.so by `build()`
 (called by the package build step and on first use).  `Oracle(path)` wraps
@@ -71,6 +73,18 @@ class Oracle:
         lib.vox_oracle_list.restype = i64
         lib.vox_oracle_grid.argtypes = [P, i64, i32, i32, i32, P, ctypes.c_int]
         lib.vox_oracle_grid.restype = i64
+        lib.vox_oracle_length_euclid.argtypes = [P]
+        lib.vox_oracle_length_euclid.restype = i64
+        lib.vox_oracle_sample_euclid.argtypes = [P, i64, P]
+        lib.vox_oracle_sample_euclid.restype = None
+        lib.vox_oracle_counts_euclid.argtypes = [P, i64, P]
+        lib.vox_oracle_counts_euclid.restype = None
+        lib.vox_oracle_offsets_euclid.argtypes = [P, i64, P]
+        lib.vox_oracle_offsets_euclid.restype = i64
+        lib.vox_oracle_list_euclid.argtypes = [P, i64, P, i64]
+        lib.vox_oracle_list_euclid.restype = i64
+        lib.vox_oracle_grid_euclid.argtypes = [P, i64, i32, i32, i32, P, ctypes.c_int]
+        lib.vox_oracle_grid_euclid.restype = i64
         self._lib = lib
         self.path = path
 
@@ -124,6 +138,58 @@ class Oracle:
             raise ValueError("end point outside the volume")
         return out
 
+    # Euclidean-length variant (eq. (1): N = int(|E - S|), consecutive
+    # duplicates removed).
+
+    def length_euclid(self, seg) -> int:
+        s = _segs(np.asarray(seg).reshape(1, 6))
+        return int(self._lib.vox_oracle_length_euclid(_ptr(s)))
+
+    def sample_euclid(self, seg, k: int) -> tuple:
+        """Voxel of sample k (0 <= k <= N_e), before duplicates are removed."""
+        s = _segs(np.asarray(seg).reshape(1, 6))
+        out = np.empty(3, dtype=np.int64)
+        self._lib.vox_oracle_sample_euclid(_ptr(s), int(k), _ptr(out))
+        return tuple(int(v) for v in out)
+
+    def counts_euclid(self, segs) -> np.ndarray:
+        s = _segs(segs)
+        out = np.empty(s.shape[0], dtype=np.int32)
+        self._lib.vox_oracle_counts_euclid(_ptr(s), s.shape[0], _ptr(out))
+        return out
+
+    def offsets_euclid(self, segs) -> np.ndarray:
+        s = _segs(segs)
+        out = np.empty(s.shape[0] + 1, dtype=np.int64)
+        self._lib.vox_oracle_offsets_euclid(_ptr(s), s.shape[0], _ptr(out))
+        return out
+
+    def voxel_list_euclid(self, segs) -> np.ndarray:
+        s = _segs(segs)
+        total = int(self.offsets_euclid(s)[-1])
+        out = np.empty((max(total, 0), 3), dtype=np.int16)
+        got = self._lib.vox_oracle_list_euclid(_ptr(s), s.shape[0], _ptr(out), total)
+        if got < 0:
+            raise ValueError("end point outside the int16 range")
+        return out
+
+    def grid_euclid(self, segs, dims, base=None) -> np.ndarray:
+        s = _segs(segs)
+        dx, dy, dz = (int(v) for v in dims)
+        nwords = (dx * dy * dz + 31) // 32
+        if base is None:
+            out = np.empty(nwords, dtype=np.uint32)
+            clear = 1
+        else:
+            out = np.array(base, dtype=np.uint32, copy=True).reshape(-1)
+            if out.size != nwords:
+                raise ValueError("base has the wrong size")
+            clear = 0
+        got = self._lib.vox_oracle_grid_euclid(_ptr(s), s.shape[0], dx, dy, dz, _ptr(out), clear)
+        if got < 0:
+            raise ValueError("end point outside the volume")
+        return out
+
 
 _default = None
 
@@ -156,3 +222,19 @@ def voxel_list(segs):
 
 def grid(segs, dims, base=None):
     return default().grid(segs, dims, base)
+
+
+def counts_euclid(segs):
+    return default().counts_euclid(segs)
+
+
+def offsets_euclid(segs):
+    return default().offsets_euclid(segs)
+
+
+def voxel_list_euclid(segs):
+    return default().voxel_list_euclid(segs)
+
+
+def grid_euclid(segs, dims, base=None):
+    return default().grid_euclid(segs, dims, base)
