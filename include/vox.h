@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define VOX_ABI_VERSION 2
+#define VOX_ABI_VERSION 3
 
 /* One segment: start point (x0,y0,z0) = S, end point (x1,y1,z1) = E.
  * Arrays of segments are dense, 24 bytes per segment, 4-byte aligned. */
@@ -65,6 +65,10 @@ typedef enum vox_status {
 /* Grid flag: zero the whole bit-volume before setting voxels.  Without it
  * the voxels are ORed into the volume's current contents. */
 #define VOX_GRID_CLEAR 1u
+/* Grid flag: the paper's literal length of eq. (1), N = int(|E - S|) (see
+ * vox_segments_to_list_euclid), instead of max |d_a|.  Such calls take the
+ * thread-per-segment path (no LDS bricks). */
+#define VOX_GRID_EUCLID 2u
 
 /* ---------------------------------------------------------------- lists */
 
@@ -97,6 +101,19 @@ vox_status vox_segments_to_list(const vox_segment *d_segs, int64_t n,
                                 int64_t capacity, int64_t *h_total,
                                 void *d_work, size_t work_bytes, void *stream);
 
+/* The same lists with the paper's literal length of eq. (1): N_i =
+ * int(|E - S|) (the integer square root of dx^2 + dy^2 + dz^2), samples
+ * S + k (E - S) / N_i for k = 0..N_i (eq. (2)-(3)) each mapped to the voxel
+ * containing it (round half up, as above), and a sample that falls in the
+ * voxel of the sample before it dropped (with this N two samples can share
+ * a voxel).  d_offsets[i] counts the voxels kept; arguments, workspace size
+ * (vox_list_workspace_bytes), ownership and errors as for
+ * vox_segments_to_list.  One thread walks each segment's samples. */
+vox_status vox_segments_to_list_euclid(const vox_segment *d_segs, int64_t n,
+                                       int64_t *d_offsets, int16_t *d_voxels,
+                                       int64_t capacity, int64_t *h_total,
+                                       void *d_work, size_t work_bytes, void *stream);
+
 /* ----------------------------------------------------------------- grids */
 
 /* Workspace bytes for vox_segments_to_grid with n segments and the given
@@ -113,8 +130,10 @@ size_t vox_grid_workspace_bytes(int64_t n, int32_t dim_x, int32_t dim_y, int32_t
  *   d_grid     [ceil(dim_x*dim_y*dim_z / 32)] uint32, device, in/out.
  *              Voxel (x,y,z) is bit b = (z*dim_y + y)*dim_x + x, stored in
  *              word b / 32 at bit b % 32 (least significant bit first).
- *   d_counts   optional [n] int32 out, device: N_i + 1.
- *   flags      VOX_GRID_CLEAR or 0.
+ *   d_counts   optional [n] int32 out, device: N_i + 1 (with
+ *              VOX_GRID_EUCLID: the voxels kept, 0 for a segment outside the
+ *              volume).
+ *   flags      VOX_GRID_CLEAR and/or VOX_GRID_EUCLID, or 0.
  *   d_work     workspace, >= vox_grid_workspace_bytes(...) bytes, 256-byte
  *              aligned.
  *

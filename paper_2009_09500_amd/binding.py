@@ -28,6 +28,7 @@ VOX_ERR_DEVICE = 4
 VOX_ERR_WORKSPACE = 5
 VOX_ERR_BATCH_MISMATCH = 6
 VOX_GRID_CLEAR = 1
+VOX_GRID_EUCLID = 2
 
 _lib = None
 
@@ -104,6 +105,8 @@ def load(path: str | None = None):
     lib.vox_list_workspace_bytes.restype = sz
     lib.vox_segments_to_list.argtypes = [P, i64, P, P, i64, P, P, sz, P]
     lib.vox_segments_to_list.restype = ctypes.c_int
+    lib.vox_segments_to_list_euclid.argtypes = [P, i64, P, P, i64, P, P, sz, P]
+    lib.vox_segments_to_list_euclid.restype = ctypes.c_int
     lib.vox_grid_workspace_bytes.argtypes = [i64, i32, i32, i32]
     lib.vox_grid_workspace_bytes.restype = sz
     lib.vox_segments_to_grid.argtypes = [P, i64, i32, i32, i32, P, P, u32, P, sz, P]
@@ -178,14 +181,16 @@ def vox_grid_workspace_bytes(n: int, dims) -> int:
 
 
 def vox_segments_to_list(segs, offsets, voxels, capacity: int, work, want_total: bool = False,
-                         stream=None):
-    """Calls vox_segments_to_list; returns the total if want_total."""
+                         stream=None, euclid: bool = False):
+    """Calls vox_segments_to_list (vox_segments_to_list_euclid if euclid);
+    returns the total if want_total."""
     lib = load()
     _check_segs(segs)
     total = ctypes.c_int64(-1)
-    st = lib.vox_segments_to_list(_ptr(segs), segs.shape[0], _ptr(offsets), _ptr(voxels),
-                                  int(capacity), ctypes.byref(total) if want_total else None,
-                                  _ptr(work), work.numel() * work.element_size(), _stream(stream))
+    fn = lib.vox_segments_to_list_euclid if euclid else lib.vox_segments_to_list
+    st = fn(_ptr(segs), segs.shape[0], _ptr(offsets), _ptr(voxels),
+            int(capacity), ctypes.byref(total) if want_total else None,
+            _ptr(work), work.numel() * work.element_size(), _stream(stream))
     if want_total and st in (VOX_ERR_CAPACITY, VOX_ERR_OUT_OF_RANGE):
         raise VoxError(st, lib.vox_last_error().decode())
     _check(lib, st)
@@ -304,18 +309,19 @@ def workspace(nbytes: int, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def segments_to_list(segs, stream=None):
+def segments_to_list(segs, stream=None, euclid: bool = False):
     """(offsets int64 [n+1], voxels int16 [total, 3]) for a device segment
-    tensor; two library calls (size query, then generation)."""
+    tensor; two library calls (size query, then generation).  euclid: the
+    paper's eq. (1) length (vox_segments_to_list_euclid)."""
     import torch
     _check_segs(segs)
     n = segs.shape[0]
     offsets = torch.empty(n + 1, dtype=torch.int64, device=segs.device)
     work = workspace(vox_list_workspace_bytes(n, 0), segs.device)
-    total = vox_segments_to_list(segs, offsets, None, 0, work, want_total=True, stream=stream)
+    total = vox_segments_to_list(segs, offsets, None, 0, work, want_total=True, stream=stream, euclid=euclid)
     voxels = torch.empty((max(total, 1), 3), dtype=torch.int16, device=segs.device)
     work = workspace(vox_list_workspace_bytes(n, total), segs.device)
-    vox_segments_to_list(segs, offsets, voxels, total, work, stream=stream)
+    vox_segments_to_list(segs, offsets, voxels, total, work, stream=stream, euclid=euclid)
     return offsets, voxels[:total]
 
 
@@ -324,15 +330,16 @@ def grid_words(dims) -> int:
     return (dx * dy * dz + 31) // 32
 
 
-def segments_to_grid(segs, dims, grid=None, want_counts: bool = False, stream=None):
+def segments_to_grid(segs, dims, grid=None, want_counts: bool = False, stream=None, euclid: bool = False):
     """Packed uint32 bit-volume (as int32 storage) of the segments; a new
-    cleared volume unless `grid` is given (then ORed into it)."""
+    cleared volume unless `grid` is given (then ORed into it).  euclid: the
+    paper's eq. (1) length (VOX_GRID_EUCLID)."""
     import torch
     _check_segs(segs)
-    flags = 0
+    flags = VOX_GRID_EUCLID if euclid else 0
     if grid is None:
         grid = torch.empty(grid_words(dims), dtype=torch.int32, device=segs.device)
-        flags = VOX_GRID_CLEAR
+        flags |= VOX_GRID_CLEAR
     counts = torch.empty(segs.shape[0], dtype=torch.int32, device=segs.device) if want_counts else None
     work = workspace(vox_grid_workspace_bytes(segs.shape[0], dims), segs.device)
     vox_segments_to_grid(segs, dims, grid, counts, flags, work, stream=stream)

@@ -104,9 +104,9 @@ size_t vox_list_workspace_bytes(int64_t n, int64_t capacity) {
     return vox::list_workspace_bytes(n, capacity);
 }
 
-vox_status vox_segments_to_list(const vox_segment* d_segs, int64_t n, int64_t* d_offsets,
-                                int16_t* d_voxels, int64_t capacity, int64_t* h_total,
-                                void* d_work, size_t work_bytes, void* stream) {
+static vox_status segments_to_list(const vox_segment* d_segs, int64_t n, int64_t* d_offsets,
+                                   int16_t* d_voxels, int64_t capacity, int64_t* h_total,
+                                   void* d_work, size_t work_bytes, void* stream, bool euclid) {
     if (n < 0) return fail(VOX_ERR_INVALID_ARGUMENT, "n must be >= 0");
     if (n > (int64_t(1) << 31) - 2) return fail(VOX_ERR_INVALID_ARGUMENT, "n must be < 2^31 - 1");
     if (n > 0 && d_segs == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "d_segs is NULL");
@@ -129,10 +129,11 @@ vox_status vox_segments_to_list(const vox_segment* d_segs, int64_t n, int64_t* d
     const bool a8 = aligned(d_segs, 8);
     vox::ListWork w = vox::list_workspace(d_work, n, cap);
     hipError_t e;
-    if ((e = vox::launch_list_count(segs, n, a8, w, s)) != hipSuccess) return device_fail(e, "count");
+    if ((e = vox::launch_list_count(segs, n, a8, w, s, euclid)) != hipSuccess) return device_fail(e, "count");
     if ((e = vox::launch_list_scan(w, n, d_offsets, cap, want, s)) != hipSuccess)
         return device_fail(e, "scan");
-    if ((e = vox::launch_list_offsets(n, d_offsets, w, cap, want, s)) != hipSuccess)
+    // (The Euclidean lists are written per segment: no output tiles.)
+    if ((e = vox::launch_list_offsets(n, d_offsets, w, cap, want && !euclid, s)) != hipSuccess)
         return device_fail(e, "offsets");
 
     int64_t tiles = want ? (cap + vox::kListTile - 1) / vox::kListTile : 0;
@@ -158,11 +159,27 @@ vox_status vox_segments_to_list(const vox_segment* d_segs, int64_t n, int64_t* d
         }
     }
     if (tiles > 0) {
-        if ((e = vox::launch_list_voxels(segs, n, a8, d_offsets, w, d_voxels, cap, tiles, s)) !=
-            hipSuccess)
-            return device_fail(e, "voxels");
+        if (euclid)
+            e = vox::launch_list_voxels_euclid(segs, n, a8, d_offsets, w, d_voxels, s);
+        else
+            e = vox::launch_list_voxels(segs, n, a8, d_offsets, w, d_voxels, cap, tiles, s);
+        if (e != hipSuccess) return device_fail(e, "voxels");
     }
     return result == VOX_OK ? ok() : result;
+}
+
+vox_status vox_segments_to_list(const vox_segment* d_segs, int64_t n, int64_t* d_offsets,
+                                int16_t* d_voxels, int64_t capacity, int64_t* h_total,
+                                void* d_work, size_t work_bytes, void* stream) {
+    return segments_to_list(d_segs, n, d_offsets, d_voxels, capacity, h_total, d_work, work_bytes, stream,
+                            false);
+}
+
+vox_status vox_segments_to_list_euclid(const vox_segment* d_segs, int64_t n, int64_t* d_offsets,
+                                       int16_t* d_voxels, int64_t capacity, int64_t* h_total,
+                                       void* d_work, size_t work_bytes, void* stream) {
+    return segments_to_list(d_segs, n, d_offsets, d_voxels, capacity, h_total, d_work, work_bytes, stream,
+                            true);
 }
 
 size_t vox_grid_workspace_bytes(int64_t n, int32_t dim_x, int32_t dim_y, int32_t dim_z) {
@@ -183,7 +200,7 @@ vox_status vox_segments_to_grid(const vox_segment* d_segs, int64_t n, int32_t di
         return fail(VOX_ERR_INVALID_ARGUMENT, "d_grid NULL or not 16-byte aligned");
     if (d_counts && !aligned(d_counts, 4))
         return fail(VOX_ERR_INVALID_ARGUMENT, "d_counts not 4-byte aligned");
-    if (flags & ~VOX_GRID_CLEAR) return fail(VOX_ERR_INVALID_ARGUMENT, "unknown flag bits");
+    if (flags & ~(VOX_GRID_CLEAR | VOX_GRID_EUCLID)) return fail(VOX_ERR_INVALID_ARGUMENT, "unknown flag bits");
     if (d_work == nullptr || !aligned(d_work, vox::kAlign))
         return fail(VOX_ERR_WORKSPACE, "d_work NULL or not 256-byte aligned");
     const size_t need = vox::grid_workspace_bytes(n, dim_x, dim_y, dim_z);

@@ -46,6 +46,25 @@ __device__ __forceinline__ int64_t seg_length(const Seg& s) {
     return n;
 }
 
+// Euclidean length of the paper's eq. (1), N_e = int(|p1 - p0|): the integer
+// square root of dx^2 + dy^2 + dz^2.  For end points within 2^31 of each
+// other the sum stays below 2^64 (and below 2^53, where the double square
+// root is within one of the result, for every input the library accepts:
+// int16 lists, volumes up to 2^20 a side); the integer corrections make it
+// exact.
+__device__ __forceinline__ uint32_t euclid_length(const Seg& s) {
+    uint64_t ss = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t d = (int64_t)s.p1[a] - (int64_t)s.p0[a];
+        ss += (uint64_t)(d * d);
+    }
+    uint64_t r = (uint64_t)sqrt((double)ss);
+    while (r * r > ss) --r;
+    while ((r + 1) * (r + 1) <= ss) ++r;
+    return (uint32_t)r;
+}
+
 __device__ __forceinline__ bool in_int16(const Seg& s) {
     bool ok = true;
 #pragma unroll
@@ -122,6 +141,56 @@ __device__ __forceinline__ void axis_step(AxisStep& st, uint32_t two_n) {
     bool c = st.r >= two_n;
     st.r = c ? st.r - two_n : st.r;
     st.q += c ? 1u : 0u;
+}
+
+// The samples k = 0..N of a segment for an N that is at least every |d_a|
+// (the Chebyshev length, or the Euclidean one of eq. (1)): q_a(k) =
+// floor((2 k a + N - neg) / 2N), so sample k's voxel is p0 + sign * q.
+// Each step advances every axis by at most one, and reports whether any
+// did, i.e. whether sample k lies in another voxel than sample k - 1.
+struct SampleWalk {
+    AxisStep st[3];
+    uint32_t neg[3];
+    uint32_t two_n;
+};
+
+__device__ __forceinline__ SampleWalk sample_walk(const Seg& g, uint32_t N) {
+    SampleWalk w;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int32_t d = g.p1[a] - g.p0[a];
+        w.neg[a] = d < 0;
+        w.st[a].two_a = 2u * (uint32_t)(d < 0 ? -d : d);
+        w.st[a].q = 0u;
+        w.st[a].r = N ? N - w.neg[a] : 0u;
+    }
+    w.two_n = 2u * N;
+    return w;
+}
+
+__device__ __forceinline__ bool sample_step(SampleWalk& w) {
+    bool moved = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const uint32_t q = w.st[a].q;
+        axis_step(w.st[a], w.two_n);
+        moved |= w.st[a].q != q;
+    }
+    return moved;
+}
+
+__device__ __forceinline__ int32_t sample_coord(const SampleWalk& w, const Seg& g, int a) {
+    const int32_t q = (int32_t)w.st[a].q;
+    return g.p0[a] + (w.neg[a] ? -q : q);
+}
+
+// Voxels of segment g under the Euclidean length N (consecutive duplicates
+// removed): 1 + the number of steps that move.
+__device__ __forceinline__ uint32_t euclid_count(const Seg& g, uint32_t N) {
+    SampleWalk w = sample_walk(g, N);
+    uint32_t c = 1;
+    for (uint32_t k = 1; k <= N; ++k) c += sample_step(w) ? 1u : 0u;
+    return c;
 }
 
 // ------------------------------------------------------------ block scans

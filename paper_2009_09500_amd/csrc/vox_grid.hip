@@ -24,8 +24,9 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_clear(uint32_t* __restrict_
 }
 
 // Thread per segment: range check, count, then every voxel of eq. (3) by
-// exact stepping, each ORed into the grid.
-template <bool kAligned8>
+// exact stepping, each ORed into the grid.  kEuclid: N is the Euclidean
+// length of eq. (1) and the count is of the samples that start a new voxel.
+template <bool kAligned8, bool kEuclid>
 __global__ __launch_bounds__(kGridBlock) void k_grid_direct(const int32_t* __restrict__ segs, int64_t n,
                                                             int32_t dx, int32_t dy, int32_t dz,
                                                             uint32_t* __restrict__ grid,
@@ -34,40 +35,33 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_direct(const int32_t* __res
     const int64_t i = (int64_t)blockIdx.x * kGridBlock + threadIdx.x;
     if (i >= n) return;
     Seg g = load_seg<kAligned8>(segs, i);
-    const int64_t N64 = seg_length(g);
-    if (counts) counts[i] = (int32_t)(N64 + 1 > 0x7FFFFFFFll ? 0x7FFFFFFFll : N64 + 1);
     const int32_t dim[3] = {dx, dy, dz};
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         ok &= (g.p0[a] >= 0) & (g.p0[a] < dim[a]) & (g.p1[a] >= 0) & (g.p1[a] < dim[a]);
+    if (!kEuclid && counts) {
+        const int64_t N64 = seg_length(g);
+        counts[i] = (int32_t)(N64 + 1 > 0x7FFFFFFFll ? 0x7FFFFFFFll : N64 + 1);
+    }
     if (!ok) {
+        // (The Euclidean count of an out-of-volume segment is not walked.)
+        if (kEuclid && counts) counts[i] = 0;
         atomicOr(status, kStatusOutOfRange);
         return;
     }
-    const uint32_t N = (uint32_t)N64;  // < 2^20 inside the volume
-    uint32_t neg[3];
-    AxisStep st[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int32_t d = g.p1[a] - g.p0[a];
-        neg[a] = d < 0;
-        st[a].two_a = 2u * (uint32_t)(d < 0 ? -d : d);
-        st[a].q = 0u;
-        st[a].r = N ? N - neg[a] : 0u;
-    }
-    const uint32_t two_n = 2u * N;
+    // Inside the volume every side is below 2^20: N < 2^21.
+    const uint32_t N = kEuclid ? euclid_length(g) : (uint32_t)seg_length(g);
+    SampleWalk w = sample_walk(g, N);
+    uint32_t voxels = 1;
     for (uint32_t k = 0; k <= N; ++k) {
-        int64_t c[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            int32_t q = (int32_t)st[a].q;
-            c[a] = g.p0[a] + (neg[a] ? -q : q);
-            axis_step(st[a], two_n);
-        }
-        const uint64_t b = ((uint64_t)c[2] * (uint64_t)dy + (uint64_t)c[1]) * (uint64_t)dx + (uint64_t)c[0];
+        const uint64_t c[3] = {(uint64_t)sample_coord(w, g, 0), (uint64_t)sample_coord(w, g, 1),
+                               (uint64_t)sample_coord(w, g, 2)};
+        const uint64_t b = (c[2] * (uint64_t)dy + c[1]) * (uint64_t)dx + c[0];
         atomicOr(grid + (b >> 5), 1u << (uint32_t)(b & 31u));
+        if (k < N) voxels += sample_step(w) ? 1u : 0u;
     }
+    if (kEuclid && counts) counts[i] = (int32_t)voxels;
 }
 
 // The brick path serves volumes whose rows are whole words and whose piece
@@ -108,7 +102,8 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
     BrickGeom bg;
     // The brick path reads segments with 8-byte loads; arrays that are only
     // 4-byte aligned take the direct path.
-    if (aligned8 && use_bricks(n, dx, dy, dz, bg))
+    const bool euclid = (flags & 2u) != 0;  // VOX_GRID_EUCLID: the direct path only
+    if (!euclid && aligned8 && use_bricks(n, dx, dy, dz, bg))
         return launch_brick_grid(segs, n, bg, grid, counts, flags, w.status, w.bytes, stream);
     {
         KernelTimer timer("grid_init", stream);
@@ -128,11 +123,22 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
     }
     if (n == 0) return hipSuccess;
     dim3 gridDim((unsigned)((n + kGridBlock - 1) / kGridBlock));
-    KernelTimer timer("grid_direct", stream);
-    if (aligned8)
-        k_grid_direct<true><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts, w.status);
-    else
-        k_grid_direct<false><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts, w.status);
+    KernelTimer timer(euclid ? "grid_direct_euclid" : "grid_direct", stream);
+    if (euclid) {
+        if (aligned8)
+            k_grid_direct<true, true><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts,
+                                                                          w.status);
+        else
+            k_grid_direct<false, true><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts,
+                                                                           w.status);
+    } else {
+        if (aligned8)
+            k_grid_direct<true, false><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts,
+                                                                           w.status);
+        else
+            k_grid_direct<false, false><<<gridDim, kGridBlock, 0, stream>>>(segs, n, dx, dy, dz, grid, counts,
+                                                                            w.status);
+    }
     return hipGetLastError();
 }
 

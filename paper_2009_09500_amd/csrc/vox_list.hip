@@ -18,7 +18,9 @@ namespace vox {
 
 // ------------------------------------------------------------------ count
 
-template <bool kAligned8>
+// Voxel counts per segment (N + 1, or with the Euclidean N of eq. (1) the
+// samples that start a new voxel) and their block sums; out-of-range flags.
+template <bool kAligned8, bool kEuclid>
 __global__ __launch_bounds__(kCountBlock) void k_list_count(const int32_t* __restrict__ segs,
                                                             int64_t n, uint32_t* __restrict__ counts,
                                                             int64_t* __restrict__ block_sums,
@@ -32,8 +34,15 @@ __global__ __launch_bounds__(kCountBlock) void k_list_count(const int32_t* __res
         int64_t i = base + (int64_t)s * kCountBlock + threadIdx.x;
         if (i < n) {
             Seg g = load_seg<kAligned8>(segs, i);
-            int64_t c = seg_length(g) + 1;
-            flag |= in_int16(g) ? 0 : kStatusOutOfRange;
+            const bool inr = in_int16(g);
+            int64_t c;
+            if constexpr (kEuclid) {
+                // (An out-of-range segment writes nothing: no walk of it.)
+                c = inr ? (int64_t)euclid_count(g, euclid_length(g)) : 1;
+            } else {
+                c = seg_length(g) + 1;
+            }
+            flag |= inr ? 0 : kStatusOutOfRange;
             // Counts above 2^32 - 1 only arise from out-of-range input.
             counts[i] = c > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)c;
             sum += c > 0xFFFFFFFFll ? 0xFFFFFFFFll : c;
@@ -264,6 +273,35 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     for (int64_t c = tail0 / 2 + threadIdx.x; c < bytes / 2; c += kListBlock) dst16[c] = src16[c];
 }
 
+// Lists with the Euclidean N of eq. (1): a thread per segment walks its
+// samples and writes the voxel of every sample that starts a new one from
+// the segment's offset on.
+template <bool kAligned8>
+__global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
+    const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
+    int16_t* __restrict__ voxels, const int32_t* __restrict__ status) {
+    if (*status != 0) return;
+    const int64_t stride = (int64_t)gridDim.x * kCountBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kCountBlock + threadIdx.x; i < n; i += stride) {
+        const Seg g = load_seg<kAligned8>(segs, i);
+        const uint32_t N = euclid_length(g);
+        int16_t* out = voxels + 3 * offsets[i];
+        SampleWalk w = sample_walk(g, N);
+        out[0] = (int16_t)g.p0[0];
+        out[1] = (int16_t)g.p0[1];
+        out[2] = (int16_t)g.p0[2];
+        out += 3;
+        for (uint32_t k = 1; k <= N; ++k) {
+            if (sample_step(w)) {
+                out[0] = (int16_t)sample_coord(w, g, 0);
+                out[1] = (int16_t)sample_coord(w, g, 1);
+                out[2] = (int16_t)sample_coord(w, g, 2);
+                out += 3;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- host side
 
 size_t list_workspace_bytes(int64_t n, int64_t capacity) {
@@ -298,22 +336,25 @@ ListWork list_workspace(void* d_work, int64_t n, int64_t capacity) {
     return w;
 }
 
-hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
-                             hipStream_t stream) {
-    KernelTimer timer("list_count", stream);
-    if (n == 0) {
-        // One block that writes a zero sum and no flag.
-        if (aligned8)
-            k_list_count<true><<<1, kCountBlock, 0, stream>>>(segs, 0, w.counts, w.block_sums, w.block_flags);
-        else
-            k_list_count<false><<<1, kCountBlock, 0, stream>>>(segs, 0, w.counts, w.block_sums, w.block_flags);
-        return hipGetLastError();
-    }
-    dim3 grid((unsigned)w.nb);
+template <bool kEuclid>
+static void list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w, hipStream_t stream) {
+    // n == 0: one block that writes a zero sum and no flag.
+    dim3 grid(n == 0 ? 1u : (unsigned)w.nb);
     if (aligned8)
-        k_list_count<true><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums, w.block_flags);
+        k_list_count<true, kEuclid><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums,
+                                                                       w.block_flags);
     else
-        k_list_count<false><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums, w.block_flags);
+        k_list_count<false, kEuclid><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums,
+                                                                        w.block_flags);
+}
+
+hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
+                             hipStream_t stream, bool euclid) {
+    KernelTimer timer(euclid ? "list_count_euclid" : "list_count", stream);
+    if (euclid)
+        list_count<true>(segs, n, aligned8, w, stream);
+    else
+        list_count<false>(segs, n, aligned8, w, stream);
     return hipGetLastError();
 }
 
@@ -348,6 +389,21 @@ hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, con
     else
         k_list_voxels<false><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
                                                               w.total, w.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_voxels_euclid(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
+                                     const ListWork& w, int16_t* voxels, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + kCountBlock - 1) / kCountBlock;
+    if (blocks > 8192) blocks = 8192;
+    KernelTimer timer("list_voxels_euclid", stream);
+    if (aligned8)
+        k_list_voxels_euclid<true><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, offsets, voxels,
+                                                                                       w.status);
+    else
+        k_list_voxels_euclid<false><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, offsets, voxels,
+                                                                                        w.status);
     return hipGetLastError();
 }
 

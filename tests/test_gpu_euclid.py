@@ -1,0 +1,129 @@
+"""The paper's Euclidean-length variant (eq. (1): N = int(|E - S|),
+consecutive duplicates removed) on the GPU against the oracle's variant,
+element by element and word by word."""
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2009_09500_amd import binding, workloads
+from tests import pins
+from tests.gpu_helpers import canaries_intact, dev, grid_host, to_dev, to_host
+from tests.test_gpu_list import _prepared
+
+pytestmark = pytest.mark.gpu
+
+
+def assert_list(segs):
+    torch = pytest.importorskip("torch")
+    offs, vox = binding.segments_to_list(to_dev(segs), euclid=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(offs), oracle.offsets_euclid(segs))
+    exp = oracle.voxel_list_euclid(segs)
+    got = to_host(vox)
+    assert got.shape == exp.shape
+    if not np.array_equal(got, exp):
+        bad = np.argwhere(np.any(got != exp, axis=1))[:5, 0]
+        raise AssertionError("first mismatching voxels %s: got %s expected %s" % (
+            bad.tolist(), got[bad].tolist(), exp[bad].tolist()))
+
+
+def assert_grid(segs, dims, base=None):
+    s = to_dev(segs)
+    if base is None:
+        g, c = binding.segments_to_grid(s, dims, want_counts=True, euclid=True)
+    else:
+        g, c = binding.segments_to_grid(s, dims, grid=to_dev(base.view(np.int32)), want_counts=True,
+                                        euclid=True)
+    got = grid_host(g)
+    exp = oracle.grid_euclid(segs, dims, base=base)
+    if not np.array_equal(got, exp):
+        bad = np.flatnonzero(got != exp)
+        raise AssertionError("%d words differ, first %s" % (bad.size, bad[:5].tolist()))
+    assert np.array_equal(to_host(c), oracle.counts_euclid(segs))
+
+
+def test_list_exhaustive_small_cube():
+    assert_list(pins.exhaustive(-2, 2))
+
+
+def test_list_small_uniform():
+    assert_list(workloads.small_uniform()["segs"])
+
+
+def test_list_random_lengths_and_signs():
+    rng = np.random.default_rng(61)
+    p0 = rng.integers(-3000, 3000, (20_000, 3))
+    segs = np.concatenate([p0, p0 + rng.integers(-2500, 2501, (20_000, 3))], 1).astype(np.int32)
+    assert_list(segs)
+
+
+def test_list_extreme_int16():
+    segs = np.array([[-32768, -32768, -32768, 32767, 32767, 32767],
+                     [32767, -32768, 0, -32768, 32767, 5],
+                     [-32768, 0, 0, 32767, 1, 0],
+                     [7, 7, 7, 7, 7, 7]], np.int32)
+    assert_list(segs)
+
+
+def test_list_fixed_length_scaled():
+    assert_list(workloads.fixed_length(n=30_000)["segs"])
+
+
+def test_list_empty_and_points():
+    assert_list(np.zeros((0, 6), np.int32))
+    rng = np.random.default_rng(62)
+    p = rng.integers(-100, 100, (500, 3))
+    assert_list(np.concatenate([p, p], 1).astype(np.int32))
+
+
+def test_list_capacity_and_range_errors():
+    segs = workloads.small_uniform(n=300)["segs"]
+    total = int(oracle.offsets_euclid(segs)[-1])
+    s, offs, whole, vox, work = _prepared(segs, total - 1)
+    with pytest.raises(binding.VoxError) as e:
+        binding.vox_segments_to_list(s, offs, vox, total - 1, work, want_total=True, euclid=True)
+    assert e.value.status == binding.VOX_ERR_CAPACITY
+    assert np.all(to_host(whole) == 0x5A5A)
+    assert np.array_equal(to_host(offs), oracle.offsets_euclid(segs))
+    bad = segs.copy()
+    bad[11, 2] = -40000
+    s, offs, whole, vox, work = _prepared(bad, 10**6)
+    binding.vox_segments_to_list(s, offs, vox, 10**6, work, euclid=True)
+    assert binding.vox_read_status(work) == binding.VOX_ERR_OUT_OF_RANGE
+    assert np.all(to_host(whole) == 0x5A5A)
+    s, offs, whole, vox, work = _prepared(segs, total)
+    assert binding.vox_segments_to_list(s, offs, vox, total, work, want_total=True, euclid=True) == total
+    assert canaries_intact(whole, 64 * 8, 0x5A5A)
+
+
+def test_grid_small_uniform():
+    c = workloads.small_uniform(n=2000)
+    assert_grid(c["segs"], c["dims"])
+
+
+def test_grid_odd_volume_and_or_mode():
+    dims = (97, 33, 21)
+    rng = np.random.default_rng(63)
+    p = [np.stack([rng.integers(0, d, 3000) for d in dims], 1) for _ in range(2)]
+    segs = np.concatenate(p, 1).astype(np.int32)
+    assert_grid(segs, dims)
+    base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+    assert_grid(segs, dims, base=base)
+
+
+def test_grid_arbitrary_lengths():
+    c = workloads.arbitrary_length(n=20_000, volume=384)
+    assert_grid(c["segs"], c["dims"])
+
+
+def test_grid_out_of_volume_segment():
+    dims = (64, 64, 64)
+    segs = np.array([[0, 0, 0, 63, 40, 20], [1, 2, 3, 64, 5, 5], [5, 5, 5, 6, 60, 30]], np.int32)
+    s = to_dev(segs)
+    g = to_dev(np.zeros(binding.grid_words(dims), np.int32))
+    work = binding.workspace(binding.vox_grid_workspace_bytes(3, dims), dev())
+    binding.vox_segments_to_grid(s, dims, g, None, binding.VOX_GRID_CLEAR | binding.VOX_GRID_EUCLID, work)
+    assert binding.vox_read_status(work) == binding.VOX_ERR_OUT_OF_RANGE
+    ok = segs[[0, 2]]
+    assert np.array_equal(grid_host(g), oracle.grid_euclid(ok, dims))
