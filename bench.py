@@ -9,7 +9,9 @@ timed region is exactly K steps between HIP events on the launch stream,
 bracketed by device synchronisation.  Prints ONE JSON line.
 
 Also reported (in "extra"): the fixed-length list workload (1 048 576
-segments, 68 157 440 voxels), the small 1000-segment workload and a single
+segments, 68 157 440 voxels), the same lists and a 100 000-segment 512^3
+bit-volume with the paper's Euclidean length of eq. (1), the small
+1000-segment workload and a single
 segment alone (launch latency), each timed the same way; the 256-scene
 workload as plain calls, one batched launch sequence and a graph replay;
 and the serving loop on wireframe requests (saturation throughput, then a
@@ -113,19 +115,19 @@ def bench_grid(args, torch, binding, workloads, dev, stream):
     }
 
 
-def bench_list(args, torch, binding, workloads, dev, stream):
+def bench_list(args, torch, binding, workloads, dev, stream, euclid=False):
     c = workloads.fixed_length()
     segs = torch.from_numpy(c["segs"]).to(dev)
     n = segs.shape[0]
     offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
     work0 = binding.workspace(binding.vox_list_workspace_bytes(n, 0), dev)
     total = binding.vox_segments_to_list(segs, offsets, None, 0, work0, want_total=True,
-                                         stream=stream)
+                                         stream=stream, euclid=euclid)
     vox = torch.empty((total, 3), dtype=torch.int16, device=dev)
     work = binding.workspace(binding.vox_list_workspace_bytes(n, total), dev)
 
     def step():
-        binding.vox_segments_to_list(segs, offsets, vox, total, work, stream=stream)
+        binding.vox_segments_to_list(segs, offsets, vox, total, work, stream=stream, euclid=euclid)
 
     for _ in range(args.warmup):
         step()
@@ -137,16 +139,48 @@ def bench_list(args, torch, binding, workloads, dev, stream):
     prof = binding.vox_profile_records()
     binding.vox_profile_reset()
     algo = 24 * n + 8 * (n + 1) + 6 * total
-    kv = prof.get("list_voxels", (0.0, 1))
+    kv = prof.get("list_voxels_euclid" if euclid else "list_voxels", (0.0, 1))
     kv_ms = kv[0] / max(kv[1], 1)
     return {
-        "workload": "fixed-length 1048576 segments x 65 voxels -> int16 lists (seed 1002)",
+        "workload": ("fixed-length 1048576 segments (Chebyshev length 64) -> int16 lists with the "
+                     "Euclidean N of eq. (1), duplicates removed (seed 1002)" if euclid else
+                     "fixed-length 1048576 segments x 65 voxels -> int16 lists (seed 1002)"),
         "voxels": total, "ms_per_call": round(ms, 4),
         "voxels_per_s": total / (ms * 1e-3),
         "hbm_gbs_algorithmic": algo / (ms * 1e-3) / 1e9,
         "algorithmic_bytes": algo,
         "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
         "list_voxels_kernel_gbs": (6 * total) / (kv_ms * 1e-3) / 1e9 if kv_ms > 0 else None,
+    }
+
+
+def bench_grid_euclid(args, torch, binding, workloads, dev, stream):
+    """Bit-volume with the Euclidean N of eq. (1) (direct path): 100 000
+    arbitrary-length segments in a cleared 512^3 volume."""
+    c = workloads.arbitrary_length(n=100_000, volume=512)
+    segs = torch.from_numpy(c["segs"]).to(dev)
+    n = segs.shape[0]
+    dims = c["dims"]
+    grid = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev)
+    counts = torch.empty(n, dtype=torch.int32, device=dev)
+    work = binding.workspace(binding.vox_grid_workspace_bytes(n, dims), dev)
+    flags = binding.VOX_GRID_CLEAR | binding.VOX_GRID_EUCLID
+
+    def step():
+        binding.vox_segments_to_grid(segs, dims, grid, counts, flags, work, stream=stream)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    voxels = int(counts.sum().item())
+    reps = max(args.steps // 4, 3)
+    ms = _events_time(stream, step, reps) / reps
+    algo = 24 * n + 4 * n + grid.numel() * 4
+    return {
+        "workload": "arbitrary-length 100000 segments (seed 1003) -> cleared 512^3 bit-volume with the "
+                    "Euclidean N of eq. (1)",
+        "voxels": voxels, "ms_per_call": round(ms, 4), "voxels_per_s": voxels / (ms * 1e-3),
+        "hbm_gbs_algorithmic": algo / (ms * 1e-3) / 1e9, "algorithmic_bytes": algo,
     }
 
 
@@ -402,6 +436,8 @@ def main():
     if not args.no_extra:
         line["extra"] = {
             "list": bench_list(args, torch, binding, workloads, dev, stream),
+            "list_euclid": bench_list(args, torch, binding, workloads, dev, stream, euclid=True),
+            "grid_euclid": bench_grid_euclid(args, torch, binding, workloads, dev, stream),
             "small": bench_small(args, torch, binding, workloads, dev, stream),
             "batch": bench_batch(args, torch, binding, workloads, dev, stream),
         }

@@ -273,30 +273,73 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     for (int64_t c = tail0 / 2 + threadIdx.x; c < bytes / 2; c += kListBlock) dst16[c] = src16[c];
 }
 
-// Lists with the Euclidean N of eq. (1): a thread per segment walks its
-// samples and writes the voxel of every sample that starts a new one from
-// the segment's offset on.
+// Lists with the Euclidean N of eq. (1).  A wave per segment: the samples
+// k = 0..N are cut into 64 contiguous blocks, one per lane; each lane walks
+// its block from sample k0 - 1 (to compare its first sample with the one
+// before), counts the samples that start a new voxel, a wave prefix sum
+// places each lane's voxels, and a second walk writes them.  Consecutive
+// lanes write consecutive voxels, so the wave's stores stay together.
+__device__ __forceinline__ void store_voxel(int16_t* voxels, int64_t at, const SampleWalk& w, const Seg& g) {
+    int16_t* o = voxels + 3 * at;
+    o[0] = (int16_t)sample_coord(w, g, 0);
+    o[1] = (int16_t)sample_coord(w, g, 1);
+    o[2] = (int16_t)sample_coord(w, g, 2);
+}
+
 template <bool kAligned8>
 __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
     const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
     int16_t* __restrict__ voxels, const int32_t* __restrict__ status) {
     if (*status != 0) return;
-    const int64_t stride = (int64_t)gridDim.x * kCountBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kCountBlock + threadIdx.x; i < n; i += stride) {
+    const uint32_t lane = threadIdx.x % kWave;
+    const int64_t waves = (int64_t)gridDim.x * (kCountBlock / kWave);
+    for (int64_t i = (int64_t)blockIdx.x * (kCountBlock / kWave) + threadIdx.x / kWave; i < n; i += waves) {
         const Seg g = load_seg<kAligned8>(segs, i);
         const uint32_t N = euclid_length(g);
-        int16_t* out = voxels + 3 * offsets[i];
-        SampleWalk w = sample_walk(g, N);
-        out[0] = (int16_t)g.p0[0];
-        out[1] = (int16_t)g.p0[1];
-        out[2] = (int16_t)g.p0[2];
-        out += 3;
-        for (uint32_t k = 1; k <= N; ++k) {
+        const uint32_t samples = N + 1u;
+        const uint32_t per = (samples + kWave - 1) / kWave;
+        const uint32_t k0 = lane * per < samples ? lane * per : samples;
+        const uint32_t k1 = k0 + per < samples ? k0 + per : samples;
+        // The walk at sample k0 - 1 (lane 0: at sample 0, which is kept).
+        uint32_t a[3], neg[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int32_t d = g.p1[ax] - g.p0[ax];
+            neg[ax] = d < 0;
+            a[ax] = (uint32_t)(d < 0 ? -d : d);
+        }
+        SampleWalk w0;
+        if (N > 0) {
+            axis_init3(a, neg, N, k0 > 0 ? k0 - 1u : 0u, w0.st);
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) w0.st[ax] = AxisStep{0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) w0.neg[ax] = neg[ax];
+        w0.two_n = 2u * N;
+        // Sample 0 (lane 0's first) is always kept; every later sample is
+        // kept when the step to it moves.
+        const uint32_t kb = k0 == 0 ? 1u : k0;
+        // Pass 1: voxels this lane keeps.
+        uint32_t cnt = k0 == 0 ? 1u : 0u;
+        {
+            SampleWalk w = w0;
+            for (uint32_t k = kb; k < k1; ++k) cnt += sample_step(w) ? 1u : 0u;
+        }
+        const uint32_t incl = wave_inclusive_sum(cnt);
+        const int64_t base = offsets[i] + (int64_t)(incl - cnt);
+        // Pass 2: write them.
+        SampleWalk w = w0;
+        uint32_t pos = 0;
+        if (k0 == 0) {
+            store_voxel(voxels, base, w, g);
+            pos = 1;
+        }
+        for (uint32_t k = kb; k < k1; ++k) {
             if (sample_step(w)) {
-                out[0] = (int16_t)sample_coord(w, g, 0);
-                out[1] = (int16_t)sample_coord(w, g, 1);
-                out[2] = (int16_t)sample_coord(w, g, 2);
-                out += 3;
+                store_voxel(voxels, base + pos, w, g);
+                ++pos;
             }
         }
     }
@@ -395,8 +438,9 @@ hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, con
 hipError_t launch_list_voxels_euclid(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
                                      const ListWork& w, int16_t* voxels, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    int64_t blocks = (n + kCountBlock - 1) / kCountBlock;
-    if (blocks > 8192) blocks = 8192;
+    constexpr int kWavesPerBlock = kCountBlock / kWave;
+    int64_t blocks = (n + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 16384) blocks = 16384;
     KernelTimer timer("list_voxels_euclid", stream);
     if (aligned8)
         k_list_voxels_euclid<true><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, offsets, voxels,
