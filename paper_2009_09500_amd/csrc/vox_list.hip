@@ -273,74 +273,78 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     for (int64_t c = tail0 / 2 + threadIdx.x; c < bytes / 2; c += kListBlock) dst16[c] = src16[c];
 }
 
-// Lists with the Euclidean N of eq. (1).  A wave per segment: the samples
-// k = 0..N are cut into 64 contiguous blocks, one per lane; each lane walks
-// its block from sample k0 - 1 (to compare its first sample with the one
-// before), counts the samples that start a new voxel, a wave prefix sum
-// places each lane's voxels, and a second walk writes them.  Consecutive
-// lanes write consecutive voxels, so the wave's stores stay together.
-__device__ __forceinline__ void store_voxel(int16_t* voxels, int64_t at, const SampleWalk& w, const Seg& g) {
-    int16_t* o = voxels + 3 * at;
-    o[0] = (int16_t)sample_coord(w, g, 0);
-    o[1] = (int16_t)sample_coord(w, g, 1);
-    o[2] = (int16_t)sample_coord(w, g, 2);
-}
+// Lists with the Euclidean N of eq. (1).  A wave takes four segments, 16
+// lanes each; a segment's lanes take its samples k = 0..N 16 at a time.
+// With q_a(k), r_a(k) the quotient and remainder of (2 k a + N - neg) / 2N,
+// the step from k - 1 to k carries into q_a exactly when r_a(k) < 2a
+// (a <= N, so an axis moves by at most one), so each lane decides alone
+// whether its sample starts a new voxel; a ballot of those decisions places
+// the kept voxels, and consecutive lanes write consecutive voxels.
+constexpr int kEuclidLanes = 16;
 
 template <bool kAligned8>
 __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
     const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
     int16_t* __restrict__ voxels, const int32_t* __restrict__ status) {
     if (*status != 0) return;
+    constexpr int kSlots = kWave / kEuclidLanes;
     const uint32_t lane = threadIdx.x % kWave;
-    const int64_t waves = (int64_t)gridDim.x * (kCountBlock / kWave);
-    for (int64_t i = (int64_t)blockIdx.x * (kCountBlock / kWave) + threadIdx.x / kWave; i < n; i += waves) {
-        const Seg g = load_seg<kAligned8>(segs, i);
+    const uint32_t sub = lane % kEuclidLanes;
+    const uint32_t slot = lane / kEuclidLanes;
+    const uint64_t slot_bits = ((1ull << kEuclidLanes) - 1) << (kEuclidLanes * slot);
+    const int64_t step = (int64_t)gridDim.x * (kCountBlock / kWave) * kSlots;
+    for (int64_t i0 = ((int64_t)blockIdx.x * (kCountBlock / kWave) + threadIdx.x / kWave) * kSlots; i0 < n;
+         i0 += step) {
+        const int64_t i = i0 + slot;
+        const bool valid = i < n;
+        Seg g = {};
+        if (valid) g = load_seg<kAligned8>(segs, i);
         const uint32_t N = euclid_length(g);
-        const uint32_t samples = N + 1u;
-        const uint32_t per = (samples + kWave - 1) / kWave;
-        const uint32_t k0 = lane * per < samples ? lane * per : samples;
-        const uint32_t k1 = k0 + per < samples ? k0 + per : samples;
-        // The walk at sample k0 - 1 (lane 0: at sample 0, which is kept).
-        uint32_t a[3], neg[3];
+        const uint32_t two_n = 2u * N;
+        uint32_t two_a[3], num0[3];
+        bool neg[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             const int32_t d = g.p1[ax] - g.p0[ax];
             neg[ax] = d < 0;
-            a[ax] = (uint32_t)(d < 0 ? -d : d);
+            two_a[ax] = 2u * (uint32_t)(d < 0 ? -d : d);
+            num0[ax] = N - (neg[ax] ? 1u : 0u);
         }
-        SampleWalk w0;
-        if (N > 0) {
-            axis_init3(a, neg, N, k0 > 0 ? k0 - 1u : 0u, w0.st);
-        } else {
+        const float rcpd = rcp_down(two_n > 0 ? two_n : 1u);
+        int16_t* out = voxels + 3 * (valid ? offsets[i] : 0);
+        for (uint32_t c0 = 0; __ballot(valid && c0 <= N) != 0; c0 += kEuclidLanes) {
+            const uint32_t k = c0 + sub;
+            uint32_t q[3];
+            bool moved = k == 0;
+            if (N == 0) {
+                q[0] = q[1] = q[2] = 0;
+            } else if (N <= 32767u) {
+                // numerators below 2^31, quotients below 2^15
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) w0.st[ax] = AxisStep{0u, 0u, 0u};
-        }
+                for (int ax = 0; ax < 3; ++ax) {
+                    uint32_t r;
+                    divmod_down(__umul24(k, two_a[ax]) + num0[ax], two_n, rcpd, q[ax], r);
+                    moved |= r < two_a[ax];
+                }
+            } else {
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) w0.neg[ax] = neg[ax];
-        w0.two_n = 2u * N;
-        // Sample 0 (lane 0's first) is always kept; every later sample is
-        // kept when the step to it moves.
-        const uint32_t kb = k0 == 0 ? 1u : k0;
-        // Pass 1: voxels this lane keeps.
-        uint32_t cnt = k0 == 0 ? 1u : 0u;
-        {
-            SampleWalk w = w0;
-            for (uint32_t k = kb; k < k1; ++k) cnt += sample_step(w) ? 1u : 0u;
-        }
-        const uint32_t incl = wave_inclusive_sum(cnt);
-        const int64_t base = offsets[i] + (int64_t)(incl - cnt);
-        // Pass 2: write them.
-        SampleWalk w = w0;
-        uint32_t pos = 0;
-        if (k0 == 0) {
-            store_voxel(voxels, base, w, g);
-            pos = 1;
-        }
-        for (uint32_t k = kb; k < k1; ++k) {
-            if (sample_step(w)) {
-                store_voxel(voxels, base + pos, w, g);
-                ++pos;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const uint64_t num = (uint64_t)k * two_a[ax] + num0[ax];
+                    q[ax] = (uint32_t)(num / two_n);
+                    moved |= (uint32_t)(num - (uint64_t)q[ax] * two_n) < two_a[ax];
+                }
             }
+            const bool keep = valid && k <= N && moved;
+            const uint64_t m = __ballot(keep) & slot_bits;
+            if (keep) {
+                const uint32_t before = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                int16_t* o = out + 3 * before;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax)
+                    o[ax] = (int16_t)(g.p0[ax] + (neg[ax] ? -(int32_t)q[ax] : (int32_t)q[ax]));
+            }
+            out += 3 * __popcll(m);
         }
     }
 }
@@ -438,8 +442,8 @@ hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, con
 hipError_t launch_list_voxels_euclid(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
                                      const ListWork& w, int16_t* voxels, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    constexpr int kWavesPerBlock = kCountBlock / kWave;
-    int64_t blocks = (n + kWavesPerBlock - 1) / kWavesPerBlock;
+    constexpr int kSegsPerBlock = kCountBlock / kEuclidLanes;
+    int64_t blocks = (n + kSegsPerBlock - 1) / kSegsPerBlock;
     if (blocks > 16384) blocks = 16384;
     KernelTimer timer("list_voxels_euclid", stream);
     if (aligned8)
