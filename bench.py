@@ -174,13 +174,19 @@ def bench_grid_euclid(args, torch, binding, workloads, dev, stream):
     torch.cuda.synchronize()
     voxels = int(counts.sum().item())
     reps = max(args.steps // 4, 3)
+    binding.vox_profile_reset()
+    binding.vox_profile_enable(True)
     ms = _events_time(stream, step, reps) / reps
+    binding.vox_profile_enable(False)
+    prof = binding.vox_profile_records()
+    binding.vox_profile_reset()
     algo = 24 * n + 4 * n + grid.numel() * 4
     return {
         "workload": "arbitrary-length 100000 segments (seed 1003) -> cleared 512^3 bit-volume with the "
                     "Euclidean N of eq. (1)",
         "voxels": voxels, "ms_per_call": round(ms, 4), "voxels_per_s": voxels / (ms * 1e-3),
         "hbm_gbs_algorithmic": algo / (ms * 1e-3) / 1e9, "algorithmic_bytes": algo,
+        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
     }
 
 

@@ -184,6 +184,64 @@ __device__ __forceinline__ int32_t sample_coord(const SampleWalk& w, const Seg& 
     return g.p0[a] + (w.neg[a] ? -q : q);
 }
 
+// Sample k of a segment computed on its own, for lanes that each take one
+// sample: q_a(k) and r_a(k), the quotient and remainder of
+// (2 k a + N - neg) / 2N.  Because a <= N, the step from k - 1 to k moves
+// axis a (by one) exactly when it carries, that is when r_a(k) < 2a; at()
+// returns whether any axis moved (true at k = 0).  Up to N = 32767 the
+// numerators of k <= N stay below 2^31 and the quotients below 2^15, so one
+// reciprocal serves (divmod_down); beyond that, 64-bit divisions.  Lanes
+// with k > N get meaningless values.
+struct SampleAt {
+    uint32_t two_a[3], num0[3];
+    bool neg[3];
+    uint32_t N, two_n;
+    float rcpd;
+
+    __device__ __forceinline__ void init(const Seg& g, uint32_t n) {
+        N = n;
+        two_n = 2u * n;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int32_t d = g.p1[ax] - g.p0[ax];
+            neg[ax] = d < 0;
+            two_a[ax] = 2u * (uint32_t)(d < 0 ? -d : d);
+            num0[ax] = n - (neg[ax] ? 1u : 0u);
+        }
+        rcpd = rcp_down(two_n > 0 ? two_n : 1u);
+    }
+
+    __device__ __forceinline__ bool at(uint32_t k, uint32_t q[3]) const {
+        bool moved = k == 0;
+        if (N == 0) {
+            q[0] = q[1] = q[2] = 0;
+        } else if (N <= 32767u) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                uint32_t r;
+                divmod_down(__umul24(k, two_a[ax]) + num0[ax], two_n, rcpd, q[ax], r);
+                moved |= r < two_a[ax];
+            }
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const uint64_t num = (uint64_t)k * two_a[ax] + num0[ax];
+                q[ax] = (uint32_t)(num / two_n);
+                moved |= (uint32_t)(num - (uint64_t)q[ax] * two_n) < two_a[ax];
+            }
+        }
+        return moved;
+    }
+
+    __device__ __forceinline__ int32_t coord(const Seg& g, const uint32_t q[3], int ax) const {
+        return g.p0[ax] + (neg[ax] ? -(int32_t)q[ax] : (int32_t)q[ax]);
+    }
+};
+
+// Lanes per segment where a wave takes several segments at once, one sample
+// per lane (a power of two dividing 64).
+constexpr int kSampleLanes = 16;
+
 // Voxels of segment g under the Euclidean length N (consecutive duplicates
 // removed): 1 + the number of steps that move.
 __device__ __forceinline__ uint32_t euclid_count(const Seg& g, uint32_t N) {

@@ -23,45 +23,65 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_clear(uint32_t* __restrict_
         grid[i] = 0u;
 }
 
-// Thread per segment: range check, count, then every voxel of eq. (3) by
-// exact stepping, each ORed into the grid.  kEuclid: N is the Euclidean
-// length of eq. (1) and the count is of the samples that start a new voxel.
+// Four segments per wave, 16 lanes each; a segment's lanes take its samples
+// 16 at a time (SampleAt), and each lane whose sample starts a new voxel ORs
+// that voxel's bit into the grid.  Range check first: a segment with an end
+// point outside the volume sets the status and writes nothing.  Counts:
+// N + 1 for the Chebyshev N (also for a segment outside the volume), the
+// number of voxels after duplicate removal for the Euclidean N of eq. (1)
+// (0 outside the volume).
 template <bool kAligned8, bool kEuclid>
 __global__ __launch_bounds__(kGridBlock) void k_grid_direct(const int32_t* __restrict__ segs, int64_t n,
                                                             int32_t dx, int32_t dy, int32_t dz,
                                                             uint32_t* __restrict__ grid,
                                                             int32_t* __restrict__ counts,
                                                             int32_t* __restrict__ status) {
-    const int64_t i = (int64_t)blockIdx.x * kGridBlock + threadIdx.x;
-    if (i >= n) return;
-    Seg g = load_seg<kAligned8>(segs, i);
+    constexpr int kSlots = kWave / kSampleLanes;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t sub = lane % kSampleLanes;
+    const uint32_t slot = lane / kSampleLanes;
+    const uint64_t slot_bits = ((1ull << kSampleLanes) - 1) << (kSampleLanes * slot);
     const int32_t dim[3] = {dx, dy, dz};
-    bool ok = true;
+    const int64_t step = (int64_t)gridDim.x * (kGridBlock / kWave) * kSlots;
+    for (int64_t i0 = ((int64_t)blockIdx.x * (kGridBlock / kWave) + threadIdx.x / kWave) * kSlots; i0 < n;
+         i0 += step) {
+        const int64_t i = i0 + slot;
+        const bool valid = i < n;
+        Seg g = {};
+        if (valid) g = load_seg<kAligned8>(segs, i);
+        bool ok = valid;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-        ok &= (g.p0[a] >= 0) & (g.p0[a] < dim[a]) & (g.p1[a] >= 0) & (g.p1[a] < dim[a]);
-    if (!kEuclid && counts) {
-        const int64_t N64 = seg_length(g);
-        counts[i] = (int32_t)(N64 + 1 > 0x7FFFFFFFll ? 0x7FFFFFFFll : N64 + 1);
+        for (int a = 0; a < 3; ++a)
+            ok &= (g.p0[a] >= 0) & (g.p0[a] < dim[a]) & (g.p1[a] >= 0) & (g.p1[a] < dim[a]);
+        if (valid && sub == 0) {
+            if (!kEuclid && counts) {
+                const int64_t N64 = seg_length(g);
+                counts[i] = (int32_t)(N64 + 1 > 0x7FFFFFFFll ? 0x7FFFFFFFll : N64 + 1);
+            }
+            if (!ok) {
+                if (kEuclid && counts) counts[i] = 0;
+                atomicOr(status, kStatusOutOfRange);
+            }
+        }
+        if (!ok) g = Seg{};
+        // Inside the volume every side is below 2^20: N < 2^21.
+        SampleAt s;
+        s.init(g, kEuclid ? euclid_length(g) : (uint32_t)seg_length(g));
+        uint32_t kept = 0;
+        for (uint32_t c0 = 0; __ballot(ok && c0 <= s.N) != 0; c0 += kSampleLanes) {
+            const uint32_t k = c0 + sub;
+            uint32_t q[3];
+            const bool keep = s.at(k, q) && ok && k <= s.N;
+            if (keep) {
+                const uint64_t b = ((uint64_t)s.coord(g, q, 2) * (uint64_t)dy + (uint64_t)s.coord(g, q, 1)) *
+                                       (uint64_t)dx +
+                                   (uint64_t)s.coord(g, q, 0);
+                atomicOr(grid + (b >> 5), 1u << (uint32_t)(b & 31u));
+            }
+            if (kEuclid) kept += (uint32_t)__popcll(__ballot(keep) & slot_bits);
+        }
+        if (kEuclid && ok && sub == 0 && counts) counts[i] = (int32_t)kept;
     }
-    if (!ok) {
-        // (The Euclidean count of an out-of-volume segment is not walked.)
-        if (kEuclid && counts) counts[i] = 0;
-        atomicOr(status, kStatusOutOfRange);
-        return;
-    }
-    // Inside the volume every side is below 2^20: N < 2^21.
-    const uint32_t N = kEuclid ? euclid_length(g) : (uint32_t)seg_length(g);
-    SampleWalk w = sample_walk(g, N);
-    uint32_t voxels = 1;
-    for (uint32_t k = 0; k <= N; ++k) {
-        const uint64_t c[3] = {(uint64_t)sample_coord(w, g, 0), (uint64_t)sample_coord(w, g, 1),
-                               (uint64_t)sample_coord(w, g, 2)};
-        const uint64_t b = (c[2] * (uint64_t)dy + c[1]) * (uint64_t)dx + c[0];
-        atomicOr(grid + (b >> 5), 1u << (uint32_t)(b & 31u));
-        if (k < N) voxels += sample_step(w) ? 1u : 0u;
-    }
-    if (kEuclid && counts) counts[i] = (int32_t)voxels;
 }
 
 // The brick path serves volumes whose rows are whole words and whose piece
@@ -122,7 +142,10 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
         if (e != hipSuccess) return e;
     }
     if (n == 0) return hipSuccess;
-    dim3 gridDim((unsigned)((n + kGridBlock - 1) / kGridBlock));
+    constexpr int kSegsPerBlock = kGridBlock / kSampleLanes;
+    int64_t blocks = (n + kSegsPerBlock - 1) / kSegsPerBlock;
+    if (blocks > 16384) blocks = 16384;
+    dim3 gridDim((unsigned)blocks);
     KernelTimer timer(euclid ? "grid_direct_euclid" : "grid_direct", stream);
     if (euclid) {
         if (aligned8)

@@ -274,24 +274,20 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 }
 
 // Lists with the Euclidean N of eq. (1).  A wave takes four segments, 16
-// lanes each; a segment's lanes take its samples k = 0..N 16 at a time.
-// With q_a(k), r_a(k) the quotient and remainder of (2 k a + N - neg) / 2N,
-// the step from k - 1 to k carries into q_a exactly when r_a(k) < 2a
-// (a <= N, so an axis moves by at most one), so each lane decides alone
-// whether its sample starts a new voxel; a ballot of those decisions places
-// the kept voxels, and consecutive lanes write consecutive voxels.
-constexpr int kEuclidLanes = 16;
-
+// lanes each; a segment's lanes take its samples k = 0..N 16 at a time,
+// each deciding alone whether its sample starts a new voxel (SampleAt); a
+// ballot of those decisions places the kept voxels, and consecutive lanes
+// write consecutive voxels.
 template <bool kAligned8>
 __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
     const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
     int16_t* __restrict__ voxels, const int32_t* __restrict__ status) {
     if (*status != 0) return;
-    constexpr int kSlots = kWave / kEuclidLanes;
+    constexpr int kSlots = kWave / kSampleLanes;
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t sub = lane % kEuclidLanes;
-    const uint32_t slot = lane / kEuclidLanes;
-    const uint64_t slot_bits = ((1ull << kEuclidLanes) - 1) << (kEuclidLanes * slot);
+    const uint32_t sub = lane % kSampleLanes;
+    const uint32_t slot = lane / kSampleLanes;
+    const uint64_t slot_bits = ((1ull << kSampleLanes) - 1) << (kSampleLanes * slot);
     const int64_t step = (int64_t)gridDim.x * (kCountBlock / kWave) * kSlots;
     for (int64_t i0 = ((int64_t)blockIdx.x * (kCountBlock / kWave) + threadIdx.x / kWave) * kSlots; i0 < n;
          i0 += step) {
@@ -299,50 +295,20 @@ __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
         const bool valid = i < n;
         Seg g = {};
         if (valid) g = load_seg<kAligned8>(segs, i);
-        const uint32_t N = euclid_length(g);
-        const uint32_t two_n = 2u * N;
-        uint32_t two_a[3], num0[3];
-        bool neg[3];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const int32_t d = g.p1[ax] - g.p0[ax];
-            neg[ax] = d < 0;
-            two_a[ax] = 2u * (uint32_t)(d < 0 ? -d : d);
-            num0[ax] = N - (neg[ax] ? 1u : 0u);
-        }
-        const float rcpd = rcp_down(two_n > 0 ? two_n : 1u);
+        SampleAt s;
+        s.init(g, euclid_length(g));
         int16_t* out = voxels + 3 * (valid ? offsets[i] : 0);
-        for (uint32_t c0 = 0; __ballot(valid && c0 <= N) != 0; c0 += kEuclidLanes) {
+        for (uint32_t c0 = 0; __ballot(valid && c0 <= s.N) != 0; c0 += kSampleLanes) {
             const uint32_t k = c0 + sub;
             uint32_t q[3];
-            bool moved = k == 0;
-            if (N == 0) {
-                q[0] = q[1] = q[2] = 0;
-            } else if (N <= 32767u) {
-                // numerators below 2^31, quotients below 2^15
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    uint32_t r;
-                    divmod_down(__umul24(k, two_a[ax]) + num0[ax], two_n, rcpd, q[ax], r);
-                    moved |= r < two_a[ax];
-                }
-            } else {
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const uint64_t num = (uint64_t)k * two_a[ax] + num0[ax];
-                    q[ax] = (uint32_t)(num / two_n);
-                    moved |= (uint32_t)(num - (uint64_t)q[ax] * two_n) < two_a[ax];
-                }
-            }
-            const bool keep = valid && k <= N && moved;
+            const bool keep = s.at(k, q) && valid && k <= s.N;
             const uint64_t m = __ballot(keep) & slot_bits;
             if (keep) {
                 const uint32_t before = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 int16_t* o = out + 3 * before;
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax)
-                    o[ax] = (int16_t)(g.p0[ax] + (neg[ax] ? -(int32_t)q[ax] : (int32_t)q[ax]));
+                for (int ax = 0; ax < 3; ++ax) o[ax] = (int16_t)s.coord(g, q, ax);
             }
             out += 3 * __popcll(m);
         }
@@ -442,7 +408,7 @@ hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, con
 hipError_t launch_list_voxels_euclid(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
                                      const ListWork& w, int16_t* voxels, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    constexpr int kSegsPerBlock = kCountBlock / kEuclidLanes;
+    constexpr int kSegsPerBlock = kCountBlock / kSampleLanes;
     int64_t blocks = (n + kSegsPerBlock - 1) / kSegsPerBlock;
     if (blocks > 16384) blocks = 16384;
     KernelTimer timer("list_voxels_euclid", stream);
