@@ -71,6 +71,8 @@ class Oracle:
         lib.vox_oracle_offsets.restype = i64
         lib.vox_oracle_list.argtypes = [P, i64, P, i64]
         lib.vox_oracle_list.restype = i64
+        lib.vox_oracle_list32.argtypes = [P, i64, P, i64]
+        lib.vox_oracle_list32.restype = i64
         lib.vox_oracle_grid.argtypes = [P, i64, i32, i32, i32, P, ctypes.c_int]
         lib.vox_oracle_grid.restype = i64
         lib.vox_oracle_length_euclid.argtypes = [P]
@@ -117,6 +119,17 @@ class Oracle:
         got = self._lib.vox_oracle_list(_ptr(s), s.shape[0], _ptr(out), total)
         if got < 0:
             raise ValueError("end point outside the int16 range")
+        return out
+
+    def voxel_list32(self, segs) -> np.ndarray:
+        """int32 [total, 3]: the same lists with int32 coordinates, for
+        segments with every |P1_a - P0_a| < 2^30."""
+        s = _segs(segs)
+        total = int(self.offsets(s)[-1])
+        out = np.empty((max(total, 0), 3), dtype=np.int32)
+        got = self._lib.vox_oracle_list32(_ptr(s), s.shape[0], _ptr(out), total)
+        if got < 0:
+            raise ValueError("a segment spans 2^30 or more along an axis")
         return out
 
     def grid(self, segs, dims, base=None) -> np.ndarray:
@@ -218,6 +231,10 @@ def voxel(seg, k):
 
 def voxel_list(segs):
     return default().voxel_list(segs)
+
+
+def voxel_list32(segs):
+    return default().voxel_list32(segs)
 
 
 def grid(segs, dims, base=None):

@@ -124,6 +124,39 @@ int64_t vox_oracle_list(const int32_t *segs, int64_t n, int16_t *out, int64_t ca
     return total;
 }
 
+/* The same lists with int32 coordinates, for segments whose voxels leave
+ * the int16 range (the paper's longest single segments have 10^6 voxels,
+ * Section 5).  Domain: every |P1_a - P0_a| < 2^30.  Writes nothing and
+ * returns -1 if a segment is outside it or the total exceeds `capacity`
+ * voxels; otherwise returns the total. */
+int64_t vox_oracle_list32(const int32_t *segs, int64_t n, int32_t *out, int64_t capacity)
+{
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *s = segs + 6 * i;
+        for (int a = 0; a < 3; ++a)
+            if (abs64((int64_t)s[3 + a] - (int64_t)s[a]) >= ((int64_t)1 << 30))
+                return -1;
+        total += vox_oracle_length(s) + 1;
+    }
+    if (total > capacity)
+        return -1;
+    int64_t j = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *s = segs + 6 * i;
+        int64_t N = vox_oracle_length(s);
+        for (int64_t k = 0; k <= N; ++k) {
+            int64_t v[3];
+            vox_oracle_voxel(s, k, v);
+            out[3 * j + 0] = (int32_t)v[0];
+            out[3 * j + 1] = (int32_t)v[1];
+            out[3 * j + 2] = (int32_t)v[2];
+            ++j;
+        }
+    }
+    return total;
+}
+
 /* Packed occupancy bit-volume of dims dx*dy*dz: voxel (x,y,z) is bit
  * b = (z*dy + y)*dx + x, stored in 32-bit word b/32 at bit b%32 (LSB first).
  * With clear != 0 the volume starts empty, otherwise bits are ORed into the

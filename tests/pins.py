@@ -285,6 +285,62 @@ def check_closed_forms(o) -> str | None:
     return None
 
 
+def nearest_centre_at(seg, k: int) -> tuple:
+    """Voxel of sample k by exact rational arithmetic: the centre c nearest to
+    x = P0 + k d / N on each axis, ties to the larger c."""
+    p0 = [int(v) for v in seg[:3]]
+    p1 = [int(v) for v in seg[3:]]
+    N = _len(seg)
+    v = []
+    for a in range(3):
+        x = Fraction(p0[a]) if N == 0 else Fraction(p0[a]) + Fraction(k * (p1[a] - p0[a]), N)
+        f = x.numerator // x.denominator
+        best = None
+        for c in (f - 1, f, f + 1, f + 2):
+            dist = abs(Fraction(c) - x)
+            if best is None or dist < best[0] or (dist == best[0] and c > best[1]):
+                best = (dist, c)
+        v.append(best[1])
+    return tuple(v)
+
+
+def check_list32(o) -> str | None:
+    """int32 lists beyond the int16 range: closed forms of long axis and
+    diagonal segments far from the origin, a half-slope closed form, and
+    exact nearest-centre voxels at sampled k of random long segments with
+    end points near +-2^30."""
+    for p0, e, L in (((10 ** 9, -5, 7), (1, 0, 0), 10 ** 6), ((3, -(10 ** 9), 0), (0, -1, 0), 123457),
+                     ((-(2 ** 30), 2 ** 30, 40000), (1, -1, 1), 70001), ((0, 0, 2 ** 31 - 1), (0, 0, -1), 99999)):
+        p0, e = np.array(p0, np.int64), np.array(e, np.int64)
+        seg = np.concatenate([p0, p0 + L * e]).astype(np.int32)[None, :]
+        exp = p0[None, :] + np.arange(L + 1)[:, None] * e[None, :]
+        if not np.array_equal(o.voxel_list32(seg).astype(np.int64), exp):
+            return "list32 closed form %s" % seg.tolist()
+    # (0,0,0) -> (2m, m, 0): y_k = round_half_up(k / 2) = (k + 1) // 2.
+    m = 60000
+    got = o.voxel_list32(np.array([[0, 0, 0, 2 * m, m, 0]], np.int32)).astype(np.int64)
+    k = np.arange(2 * m + 1)
+    if not np.array_equal(got, np.stack([k, (k + 1) // 2, 0 * k], 1)):
+        return "list32 half-slope ties"
+    rng = np.random.default_rng(7)
+    p0 = rng.integers(-(2 ** 30), 2 ** 30, (6, 3))
+    d = rng.integers(-200000, 200001, (6, 3))
+    segs = np.concatenate([p0, p0 + d], 1).astype(np.int32)
+    got = o.voxel_list32(segs).astype(np.int64)
+    j = 0
+    for seg in segs:
+        N = _len(seg)
+        for kk in sorted({0, 1, N // 3, N // 2, N - 1, N} | set(rng.integers(0, N + 1, 40).tolist())):
+            if kk < 0 or kk > N:
+                continue
+            if tuple(got[j + kk]) != nearest_centre_at(seg, kk):
+                return "list32 sample %d of %s" % (kk, seg.tolist())
+        j += N + 1
+    if j != len(got):
+        return "list32 total"
+    return None
+
+
 def check_fp64(o, segs) -> str | None:
     """floor(P0 + k d / N + 1/2) in fp64 (exact for N < 2^20)."""
     segs = np.asarray(segs, dtype=np.int64)

@@ -34,6 +34,8 @@ MUTANTS = {
     "count without +1": ("counts[i] = (int32_t)(vox_oracle_length(segs + 6 * i) + 1);",
                          "counts[i] = (int32_t)(vox_oracle_length(segs + 6 * i));"),
     "grid keeps stale bits": ("if (clear)\n        memset", "if (!clear)\n        memset"),
+    "int32 list swaps axes": ("out[3 * j + 1] = (int32_t)v[1];", "out[3 * j + 1] = (int32_t)v[2];"),
+    "int32 list narrowed to int16": ("out[3 * j + 0] = (int32_t)v[0];", "out[3 * j + 0] = (int16_t)v[0];"),
 }
 
 
@@ -49,6 +51,7 @@ def _run_pins(o):
         lambda: pins.check_nearest_centre(o, ex),
         lambda: pins.check_invariants(o, rnd),
         lambda: pins.check_closed_forms(o),
+        lambda: pins.check_list32(o),
         lambda: pins.check_symmetries(o, rnd[:20]),
         lambda: pins.check_grid(o, np.array([[0, 0, 0, 36, 4, 2], [5, 4, 0, 20, 0, 2],
                                              [3, 1, 1, 3, 1, 1]], np.int32), (37, 5, 3)),
