@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define VOX_ABI_VERSION 3
+#define VOX_ABI_VERSION 4
 
 /* One segment: start point (x0,y0,z0) = S, end point (x1,y1,z1) = E.
  * Arrays of segments are dense, 24 bytes per segment, 4-byte aligned. */
@@ -67,7 +67,7 @@ typedef enum vox_status {
 #define VOX_GRID_CLEAR 1u
 /* Grid flag: the paper's literal length of eq. (1), N = int(|E - S|) (see
  * vox_segments_to_list_euclid), instead of max |d_a|.  Such calls take the
- * thread-per-segment path (no LDS bricks). */
+ * direct path (one device atomic per voxel, no LDS bricks). */
 #define VOX_GRID_EUCLID 2u
 
 /* ---------------------------------------------------------------- lists */
@@ -108,11 +108,24 @@ vox_status vox_segments_to_list(const vox_segment *d_segs, int64_t n,
  * voxel of the sample before it dropped (with this N two samples can share
  * a voxel).  d_offsets[i] counts the voxels kept; arguments, workspace size
  * (vox_list_workspace_bytes), ownership and errors as for
- * vox_segments_to_list.  One thread walks each segment's samples. */
+ * vox_segments_to_list.  Sixteen lanes share a segment's samples. */
 vox_status vox_segments_to_list_euclid(const vox_segment *d_segs, int64_t n,
                                        int64_t *d_offsets, int16_t *d_voxels,
                                        int64_t capacity, int64_t *h_total,
                                        void *d_work, size_t work_bytes, void *stream);
+
+/* The same lists as vox_segments_to_list with int32 coordinates, for
+ * segments whose voxels leave the int16 range (Section 5 times single
+ * segments of up to 10^6 voxels).  d_voxels is [capacity][3] int32, 16-byte
+ * aligned; every other argument, the workspace size
+ * (vox_list_workspace_bytes), ownership and the errors are those of
+ * vox_segments_to_list, except the range rule: every axis difference
+ * |P1_a - P0_a| must be below 2^30 (any int32 end points otherwise), else
+ * VOX_ERR_OUT_OF_RANGE (with h_total) and no voxel row is written. */
+vox_status vox_segments_to_list32(const vox_segment *d_segs, int64_t n,
+                                  int64_t *d_offsets, int32_t *d_voxels,
+                                  int64_t capacity, int64_t *h_total,
+                                  void *d_work, size_t work_bytes, void *stream);
 
 /* ----------------------------------------------------------------- grids */
 

@@ -107,6 +107,8 @@ def load(path: str | None = None):
     lib.vox_segments_to_list.restype = ctypes.c_int
     lib.vox_segments_to_list_euclid.argtypes = [P, i64, P, P, i64, P, P, sz, P]
     lib.vox_segments_to_list_euclid.restype = ctypes.c_int
+    lib.vox_segments_to_list32.argtypes = [P, i64, P, P, i64, P, P, sz, P]
+    lib.vox_segments_to_list32.restype = ctypes.c_int
     lib.vox_grid_workspace_bytes.argtypes = [i64, i32, i32, i32]
     lib.vox_grid_workspace_bytes.restype = sz
     lib.vox_segments_to_grid.argtypes = [P, i64, i32, i32, i32, P, P, u32, P, sz, P]
@@ -181,13 +183,16 @@ def vox_grid_workspace_bytes(n: int, dims) -> int:
 
 
 def vox_segments_to_list(segs, offsets, voxels, capacity: int, work, want_total: bool = False,
-                         stream=None, euclid: bool = False):
-    """Calls vox_segments_to_list (vox_segments_to_list_euclid if euclid);
-    returns the total if want_total."""
+                         stream=None, euclid: bool = False, wide: bool = False):
+    """Calls vox_segments_to_list (vox_segments_to_list_euclid if euclid,
+    vox_segments_to_list32 if wide); returns the total if want_total."""
     lib = load()
     _check_segs(segs)
+    if euclid and wide:
+        raise ValueError("the int32 lists use the Chebyshev length")
     total = ctypes.c_int64(-1)
-    fn = lib.vox_segments_to_list_euclid if euclid else lib.vox_segments_to_list
+    fn = (lib.vox_segments_to_list_euclid if euclid else
+          lib.vox_segments_to_list32 if wide else lib.vox_segments_to_list)
     st = fn(_ptr(segs), segs.shape[0], _ptr(offsets), _ptr(voxels),
             int(capacity), ctypes.byref(total) if want_total else None,
             _ptr(work), work.numel() * work.element_size(), _stream(stream))
@@ -309,19 +314,21 @@ def workspace(nbytes: int, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def segments_to_list(segs, stream=None, euclid: bool = False):
+def segments_to_list(segs, stream=None, euclid: bool = False, wide: bool = False):
     """(offsets int64 [n+1], voxels int16 [total, 3]) for a device segment
     tensor; two library calls (size query, then generation).  euclid: the
-    paper's eq. (1) length (vox_segments_to_list_euclid)."""
+    paper's eq. (1) length (vox_segments_to_list_euclid); wide: int32
+    coordinates (vox_segments_to_list32)."""
     import torch
     _check_segs(segs)
     n = segs.shape[0]
     offsets = torch.empty(n + 1, dtype=torch.int64, device=segs.device)
     work = workspace(vox_list_workspace_bytes(n, 0), segs.device)
-    total = vox_segments_to_list(segs, offsets, None, 0, work, want_total=True, stream=stream, euclid=euclid)
-    voxels = torch.empty((max(total, 1), 3), dtype=torch.int16, device=segs.device)
+    total = vox_segments_to_list(segs, offsets, None, 0, work, want_total=True, stream=stream, euclid=euclid,
+                                 wide=wide)
+    voxels = torch.empty((max(total, 1), 3), dtype=torch.int32 if wide else torch.int16, device=segs.device)
     work = workspace(vox_list_workspace_bytes(n, total), segs.device)
-    vox_segments_to_list(segs, offsets, voxels, total, work, stream=stream, euclid=euclid)
+    vox_segments_to_list(segs, offsets, voxels, total, work, stream=stream, euclid=euclid, wide=wide)
     return offsets, voxels[:total]
 
 

@@ -105,8 +105,9 @@ size_t vox_list_workspace_bytes(int64_t n, int64_t capacity) {
 }
 
 static vox_status segments_to_list(const vox_segment* d_segs, int64_t n, int64_t* d_offsets,
-                                   int16_t* d_voxels, int64_t capacity, int64_t* h_total,
-                                   void* d_work, size_t work_bytes, void* stream, bool euclid) {
+                                   void* d_voxels, int64_t capacity, int64_t* h_total,
+                                   void* d_work, size_t work_bytes, void* stream, vox::ListKind kind) {
+    const bool euclid = kind == vox::kListEuclid;
     if (n < 0) return fail(VOX_ERR_INVALID_ARGUMENT, "n must be >= 0");
     if (n > (int64_t(1) << 31) - 2) return fail(VOX_ERR_INVALID_ARGUMENT, "n must be < 2^31 - 1");
     if (n > 0 && d_segs == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "d_segs is NULL");
@@ -129,7 +130,7 @@ static vox_status segments_to_list(const vox_segment* d_segs, int64_t n, int64_t
     const bool a8 = aligned(d_segs, 8);
     vox::ListWork w = vox::list_workspace(d_work, n, cap);
     hipError_t e;
-    if ((e = vox::launch_list_count(segs, n, a8, w, s, euclid)) != hipSuccess) return device_fail(e, "count");
+    if ((e = vox::launch_list_count(segs, n, a8, w, s, kind)) != hipSuccess) return device_fail(e, "count");
     if ((e = vox::launch_list_scan(w, n, d_offsets, cap, want, s)) != hipSuccess)
         return device_fail(e, "scan");
     // (The Euclidean lists are written per segment: no output tiles.)
@@ -148,7 +149,9 @@ static vox_status segments_to_list(const vox_segment* d_segs, int64_t n, int64_t
         const int32_t st = (int32_t)(hdr[0] & 0xFFFFFFFF);
         *h_total = hdr[1];
         if (st & vox::kStatusOutOfRange) {
-            result = fail(VOX_ERR_OUT_OF_RANGE, "a segment end point lies outside the int16 range");
+            result = kind == vox::kListI32
+                         ? fail(VOX_ERR_OUT_OF_RANGE, "a segment spans 2^30 or more voxels along an axis")
+                         : fail(VOX_ERR_OUT_OF_RANGE, "a segment end point lies outside the int16 range");
             tiles = 0;
         } else if (st & vox::kStatusCapacity) {
             result = fail(VOX_ERR_CAPACITY, "total %lld voxels exceeds capacity %lld",
@@ -160,9 +163,12 @@ static vox_status segments_to_list(const vox_segment* d_segs, int64_t n, int64_t
     }
     if (tiles > 0) {
         if (euclid)
-            e = vox::launch_list_voxels_euclid(segs, n, a8, d_offsets, w, d_voxels, s);
+            e = vox::launch_list_voxels_euclid(segs, n, a8, d_offsets, w, static_cast<int16_t*>(d_voxels), s);
+        else if (kind == vox::kListI32)
+            e = vox::launch_list_voxels32(segs, n, a8, d_offsets, w, static_cast<int32_t*>(d_voxels), tiles, s);
         else
-            e = vox::launch_list_voxels(segs, n, a8, d_offsets, w, d_voxels, cap, tiles, s);
+            e = vox::launch_list_voxels(segs, n, a8, d_offsets, w, static_cast<int16_t*>(d_voxels), cap, tiles,
+                                        s);
         if (e != hipSuccess) return device_fail(e, "voxels");
     }
     return result == VOX_OK ? ok() : result;
@@ -172,14 +178,21 @@ vox_status vox_segments_to_list(const vox_segment* d_segs, int64_t n, int64_t* d
                                 int16_t* d_voxels, int64_t capacity, int64_t* h_total,
                                 void* d_work, size_t work_bytes, void* stream) {
     return segments_to_list(d_segs, n, d_offsets, d_voxels, capacity, h_total, d_work, work_bytes, stream,
-                            false);
+                            vox::kListI16);
+}
+
+vox_status vox_segments_to_list32(const vox_segment* d_segs, int64_t n, int64_t* d_offsets,
+                                  int32_t* d_voxels, int64_t capacity, int64_t* h_total,
+                                  void* d_work, size_t work_bytes, void* stream) {
+    return segments_to_list(d_segs, n, d_offsets, d_voxels, capacity, h_total, d_work, work_bytes, stream,
+                            vox::kListI32);
 }
 
 vox_status vox_segments_to_list_euclid(const vox_segment* d_segs, int64_t n, int64_t* d_offsets,
                                        int16_t* d_voxels, int64_t capacity, int64_t* h_total,
                                        void* d_work, size_t work_bytes, void* stream) {
     return segments_to_list(d_segs, n, d_offsets, d_voxels, capacity, h_total, d_work, work_bytes, stream,
-                            true);
+                            vox::kListEuclid);
 }
 
 size_t vox_grid_workspace_bytes(int64_t n, int32_t dim_x, int32_t dim_y, int32_t dim_z) {

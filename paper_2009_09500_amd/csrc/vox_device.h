@@ -74,6 +74,19 @@ __device__ __forceinline__ bool in_int16(const Seg& s) {
     return ok;
 }
 
+// Domain of the int32 lists: every |p1_a - p0_a| < 2^30, so N < 2^30 and the
+// stepping's remainders (below 2N) plus their increments (at most 2N) stay
+// below 2^32.
+__device__ __forceinline__ bool span_below_2p30(const Seg& s) {
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t d = (int64_t)s.p1[a] - (int64_t)s.p0[a];
+        ok &= (d < (int64_t(1) << 30)) & (d > -(int64_t(1) << 30));
+    }
+    return ok;
+}
+
 // Exact incremental evaluation of voxel k of a segment along one axis.
 //
 // With N the Chebyshev length, d = p1 - p0 and a = |d|, the coordinate is

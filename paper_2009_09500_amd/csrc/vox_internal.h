@@ -58,8 +58,12 @@ struct ListWork {
 size_t list_workspace_bytes(int64_t n, int64_t capacity);
 ListWork list_workspace(void* d_work, int64_t n, int64_t capacity);
 
+// The list forms: int16 coordinates with the Chebyshev N; int16 with the
+// Euclidean N of eq. (1); int32 coordinates with the Chebyshev N.
+enum ListKind { kListI16 = 0, kListEuclid = 1, kListI32 = 2 };
+
 hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
-                             hipStream_t stream, bool euclid);
+                             hipStream_t stream, ListKind kind);
 hipError_t launch_list_scan(const ListWork& w, int64_t n, int64_t* offsets, int64_t capacity,
                             bool want_voxels, hipStream_t stream);
 hipError_t launch_list_offsets(int64_t n, int64_t* offsets, const ListWork& w, int64_t capacity,
@@ -67,6 +71,8 @@ hipError_t launch_list_offsets(int64_t n, int64_t* offsets, const ListWork& w, i
 hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
                               const ListWork& w, int16_t* voxels, int64_t capacity,
                               int64_t tiles_to_launch, hipStream_t stream);
+hipError_t launch_list_voxels32(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
+                                const ListWork& w, int32_t* voxels, int64_t tiles_to_launch, hipStream_t stream);
 hipError_t launch_list_voxels_euclid(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
                                      const ListWork& w, int16_t* voxels, hipStream_t stream);
 

@@ -19,8 +19,10 @@ namespace vox {
 // ------------------------------------------------------------------ count
 
 // Voxel counts per segment (N + 1, or with the Euclidean N of eq. (1) the
-// samples that start a new voxel) and their block sums; out-of-range flags.
-template <bool kAligned8, bool kEuclid>
+// samples that start a new voxel) and their block sums; out-of-range flags
+// (int16 lists: a coordinate outside int16; int32 lists: an axis spanning
+// 2^30 or more).
+template <bool kAligned8, int kKind>
 __global__ __launch_bounds__(kCountBlock) void k_list_count(const int32_t* __restrict__ segs,
                                                             int64_t n, uint32_t* __restrict__ counts,
                                                             int64_t* __restrict__ block_sums,
@@ -34,9 +36,9 @@ __global__ __launch_bounds__(kCountBlock) void k_list_count(const int32_t* __res
         int64_t i = base + (int64_t)s * kCountBlock + threadIdx.x;
         if (i < n) {
             Seg g = load_seg<kAligned8>(segs, i);
-            const bool inr = in_int16(g);
+            const bool inr = kKind == kListI32 ? span_below_2p30(g) : in_int16(g);
             int64_t c;
-            if constexpr (kEuclid) {
+            if constexpr (kKind == kListEuclid) {
                 // (An out-of-range segment writes nothing: no walk of it.)
                 c = inr ? (int64_t)euclid_count(g, euclid_length(g)) : 1;
             } else {
@@ -134,26 +136,33 @@ __global__ __launch_bounds__(kCountBlock) void k_list_offsets(
 // relative to j0; lane t computes voxels j0 + t*P .. j0 + t*P + P - 1
 // (P = kListPerThread), stepping exactly from one voxel to the next and
 // moving to the following segment when the voxel index reaches its offset.
+template <typename T>
 struct PackedSeg {
-    int16_t p0[3];
-    int16_t p1[3];
+    T p0[3];
+    T p1[3];
 };
 
-template <bool kAligned8>
+// T = int16_t: coordinates in int16 (differences below 2^16); T = int32_t:
+// every axis difference below 2^30 (checked by the count kernel).
+template <bool kAligned8, typename T>
 __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
-    const int32_t* __restrict__ tile_seg, int16_t* __restrict__ voxels,
+    const int32_t* __restrict__ tile_seg, T* __restrict__ voxels,
     const int64_t* __restrict__ total_p, const int32_t* __restrict__ status) {
+    using PSeg = PackedSeg<T>;
     constexpr int kMaxSegs = (int)kListTile + 1;
-    constexpr int kSegWords = (int)(kMaxSegs * sizeof(PackedSeg) / 4);
-    constexpr int kStageWords = (int)(kListTile * 3 / 2);
+    constexpr int kSegWords = (int)(kMaxSegs * sizeof(PSeg) / 4);
+    constexpr int kVoxBytes = 3 * (int)sizeof(T);
+    constexpr int kLaneWords = kListPerThread * kVoxBytes / 4;  // a lane's staged voxels
+    constexpr int kStageWords = (int)kListTile * kVoxBytes / 4;
     // The staged segments and the output stage share LDS (the segments are
-    // dead once every lane has its voxels): 16 KiB a block, 8 blocks a CU.
+    // dead once every lane has its voxels): 16 KiB a block for int16 lists
+    // (8 blocks a CU), 28 KiB for int32 lists.
     __shared__ __align__(16) uint32_t lds_raw[kSegWords > kStageWords ? kSegWords : kStageWords];
     __shared__ int32_t srel[kMaxSegs + 1];
-    PackedSeg* sseg = reinterpret_cast<PackedSeg*>(lds_raw);
+    PSeg* sseg = reinterpret_cast<PSeg*>(lds_raw);
     uint32_t* stage = lds_raw;
-    static_assert(sizeof(PackedSeg) == 12 && (kMaxSegs * sizeof(PackedSeg)) % 4 == 0, "packed segments");
+    static_assert((kMaxSegs * sizeof(PSeg)) % 4 == 0 && (kListPerThread * kVoxBytes) % 4 == 0, "packing");
 
     if (*status != 0) return;
     const int64_t total = *total_p;
@@ -168,18 +177,18 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 
     for (int s = threadIdx.x; s < nseg; s += kListBlock) {
         Seg g = load_seg<kAligned8>(segs, (int64_t)s0 + s);
-        PackedSeg p;
+        PSeg p;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            p.p0[a] = (int16_t)g.p0[a];
-            p.p1[a] = (int16_t)g.p1[a];
+            p.p0[a] = (T)g.p0[a];
+            p.p1[a] = (T)g.p1[a];
         }
         sseg[s] = p;
     }
     for (int s = threadIdx.x; s <= nseg; s += kListBlock) {
         int64_t o = (int64_t)s0 + s <= n ? offsets[(int64_t)s0 + s] : total;
         int64_t rel = o - j0;
-        // A tile's own segments start within [-65535, kListTile].
+        // A tile's own segments start within [-(2^30 - 1), kListTile].
         rel = rel < -(1ll << 30) ? -(1ll << 30) : (rel > (1ll << 30) ? (1ll << 30) : rel);
         srel[s] = (int32_t)rel;
     }
@@ -187,7 +196,7 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 
     const int first = threadIdx.x * kListPerThread;  // tile-relative voxel
     const int count = (int)(j1 - j0);
-    int16_t out[kListPerThread * 3];
+    T out[kListPerThread * 3];
     if (first < count) {
         // Segment of the first voxel: largest s with srel[s] <= first.
         int lo = 0, hi = nseg - 1;
@@ -197,14 +206,16 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
         }
         int s = lo;
         int next = srel[s + 1];
-        PackedSeg p = sseg[s];
+        PSeg p = sseg[s];
         uint32_t neg[3], a[3];
         uint32_t N = 0;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            int32_t d = (int32_t)p.p1[ax] - (int32_t)p.p0[ax];
-            neg[ax] = d < 0;
-            a[ax] = (uint32_t)(d < 0 ? -d : d);
+            // (int32 end points: the difference is formed without overflow
+            // and is below 2^30 in magnitude.)
+            const uint32_t d = (uint32_t)p.p1[ax] - (uint32_t)p.p0[ax];
+            neg[ax] = (int32_t)d < 0;
+            a[ax] = (int32_t)d < 0 ? 0u - d : d;
             N = a[ax] > N ? a[ax] : N;
         }
         uint32_t k = (uint32_t)(first - srel[s]);
@@ -227,9 +238,9 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
                 N = 0;
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) {
-                    int32_t d = (int32_t)p.p1[ax] - (int32_t)p.p0[ax];
-                    neg[ax] = d < 0;
-                    a[ax] = (uint32_t)(d < 0 ? -d : d);
+                    const uint32_t d = (uint32_t)p.p1[ax] - (uint32_t)p.p0[ax];
+                    neg[ax] = (int32_t)d < 0;
+                    a[ax] = (int32_t)d < 0 ? 0u - d : d;
                     N = a[ax] > N ? a[ax] : N;
                 }
                 two_n = 2u * N;
@@ -243,25 +254,31 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 int32_t q = (int32_t)st[ax].q;
-                out[v * 3 + ax] = (int16_t)((int32_t)p.p0[ax] + (neg[ax] ? -q : q));
+                out[v * 3 + ax] = (T)((int32_t)p.p0[ax] + (neg[ax] ? -q : q));
                 axis_step(st[ax], two_n);
             }
         }
     }
     __syncthreads();  // the staged segments are dead from here
     if (first < count) {
-        // Stage: lane t owns 3*P int16 = 3*P/2 words at word 3*P/2*t.
-        uint32_t* dst = stage + (kListPerThread * 3 / 2) * threadIdx.x;
+        // Stage: lane t owns its 3*P coordinates, kLaneWords words at word
+        // kLaneWords*t.
+        uint32_t* dst = stage + kLaneWords * threadIdx.x;
+        if constexpr (sizeof(T) == 2) {
 #pragma unroll
-        for (int w = 0; w < kListPerThread * 3 / 2; ++w)
-            dst[w] = (uint32_t)(uint16_t)out[2 * w] | ((uint32_t)(uint16_t)out[2 * w + 1] << 16);
+            for (int w = 0; w < kLaneWords; ++w)
+                dst[w] = (uint32_t)(uint16_t)out[2 * w] | ((uint32_t)(uint16_t)out[2 * w + 1] << 16);
+        } else {
+#pragma unroll
+            for (int w = 0; w < kLaneWords; ++w) dst[w] = (uint32_t)out[w];
+        }
     }
     __syncthreads();
 
-    // Write the tile: bytes [6*j0, 6*j1).  j0 is a multiple of kListTile, so
-    // the start is 16-byte aligned whenever `voxels` is.
-    const int64_t bytes = 6 * (j1 - j0);
-    uint8_t* gbase = reinterpret_cast<uint8_t*>(voxels) + 6 * j0;
+    // Write the tile: bytes [B*j0, B*j1), B = 3*sizeof(T).  j0 is a multiple
+    // of kListTile, so the start is 16-byte aligned whenever `voxels` is.
+    const int64_t bytes = kVoxBytes * (j1 - j0);
+    uint8_t* gbase = reinterpret_cast<uint8_t*>(voxels) + kVoxBytes * j0;
     const int64_t n16 = bytes / 16;
     const uint4* src = reinterpret_cast<const uint4*>(stage);
     uint4* gdst = reinterpret_cast<uint4*>(gbase);
@@ -349,25 +366,28 @@ ListWork list_workspace(void* d_work, int64_t n, int64_t capacity) {
     return w;
 }
 
-template <bool kEuclid>
+template <int kKind>
 static void list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w, hipStream_t stream) {
     // n == 0: one block that writes a zero sum and no flag.
     dim3 grid(n == 0 ? 1u : (unsigned)w.nb);
     if (aligned8)
-        k_list_count<true, kEuclid><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums,
-                                                                       w.block_flags);
+        k_list_count<true, kKind><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums,
+                                                                     w.block_flags);
     else
-        k_list_count<false, kEuclid><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums,
-                                                                        w.block_flags);
+        k_list_count<false, kKind><<<grid, kCountBlock, 0, stream>>>(segs, n, w.counts, w.block_sums,
+                                                                      w.block_flags);
 }
 
 hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
-                             hipStream_t stream, bool euclid) {
-    KernelTimer timer(euclid ? "list_count_euclid" : "list_count", stream);
-    if (euclid)
-        list_count<true>(segs, n, aligned8, w, stream);
+                             hipStream_t stream, ListKind kind) {
+    KernelTimer timer(kind == kListEuclid ? "list_count_euclid" : (kind == kListI32 ? "list_count32" : "list_count"),
+                      stream);
+    if (kind == kListEuclid)
+        list_count<kListEuclid>(segs, n, aligned8, w, stream);
+    else if (kind == kListI32)
+        list_count<kListI32>(segs, n, aligned8, w, stream);
     else
-        list_count<false>(segs, n, aligned8, w, stream);
+        list_count<kListI16>(segs, n, aligned8, w, stream);
     return hipGetLastError();
 }
 
@@ -397,11 +417,25 @@ hipError_t launch_list_voxels(const int32_t* segs, int64_t n, bool aligned8, con
     dim3 grid((unsigned)tiles_to_launch);
     KernelTimer timer("list_voxels", stream);
     if (aligned8)
-        k_list_voxels<true><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
-                                                             w.total, w.status);
+        k_list_voxels<true, int16_t><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
+                                                                      w.total, w.status);
     else
-        k_list_voxels<false><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
-                                                              w.total, w.status);
+        k_list_voxels<false, int16_t><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
+                                                                       w.total, w.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_voxels32(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
+                                const ListWork& w, int32_t* voxels, int64_t tiles_to_launch, hipStream_t stream) {
+    if (n == 0 || tiles_to_launch <= 0) return hipSuccess;
+    dim3 grid((unsigned)tiles_to_launch);
+    KernelTimer timer("list_voxels32", stream);
+    if (aligned8)
+        k_list_voxels<true, int32_t><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
+                                                                      w.total, w.status);
+    else
+        k_list_voxels<false, int32_t><<<grid, kListBlock, 0, stream>>>(segs, n, offsets, w.tile_seg, voxels,
+                                                                       w.total, w.status);
     return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ SEED_ARBITRARY = 1003
 SEED_SCENES = 1004
 SEED_REQUEST0 = 1005
 
+SEED_PAPER = 1006
+
 N_SMALL = 1000
 N_FIXED = 1 << 20
 N_ARBITRARY = 1 << 22
@@ -98,6 +100,33 @@ def arbitrary_length(n: int = N_ARBITRARY, seed: int = SEED_ARBITRARY,
     d = np.rint(Lc[:, None] * v).astype(np.int64)
     segs = np.concatenate([start, start + d], axis=1).astype(np.int32)
     return {"segs": segs, "dims": (volume, volume, volume)}
+
+
+def paper_segments(lengths, seed: int = SEED_PAPER, start_bound: int = 1 << 29):
+    """The paper's experiment shapes (Section 5) with int32 coordinates: one
+    segment per entry of `lengths` (voxels per segment, >= 1), start uniform
+    in [-start_bound, start_bound)^3, direction uniform on the sphere,
+    end = start + rint((length - 1) * v), so segment i has exactly lengths[i]
+    voxels under the Chebyshev length.  Every axis difference stays below
+    2^30 for lengths up to 2^30."""
+    L = np.asarray(lengths, dtype=np.int64).reshape(-1)
+    rng = np.random.default_rng(seed)
+    start = rng.integers(-start_bound, start_bound, size=(L.size, 3))
+    v = _chebyshev_directions(rng, L.size)
+    d = np.rint((L[:, None] - 1) * v).astype(np.int64)
+    segs = np.concatenate([start, start + d], axis=1).astype(np.int32)
+    return {"segs": segs}
+
+
+def paper_arbitrary_lengths(n: int = 1024, total: int = 10 ** 9, seed: int = SEED_PAPER + 1):
+    """Experiment 3's lengths: n segments of arbitrary length totalling
+    `total` voxels: lengths uniform in [1, 2 total / n], rescaled to the
+    total, the rounding remainder on the last segment."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(1.0, 2.0 * total / n, size=n)
+    L = np.maximum(1, np.floor(w * (total / w.sum()))).astype(np.int64)
+    L[-1] += total - int(L.sum())
+    return L
 
 
 def scenes(n_scenes: int = N_SCENES, seed: int = SEED_SCENES,

@@ -68,3 +68,14 @@ def test_wireframe_request():
     assert s.min() >= 0 and s.max() <= 511
     assert 10_000 * 0.8 <= s.shape[0] <= 1_000_000 * 1.2
     assert s.shape[0] == 30 * q["frequency"] ** 2
+
+
+def test_paper_shapes():
+    L = workloads.paper_arbitrary_lengths()
+    assert L.size == 1024 and int(L.sum()) == 10 ** 9 and L.min() >= 1
+    segs = workloads.paper_segments(L)["segs"].astype(np.int64)
+    d = np.abs(segs[:, 3:] - segs[:, :3])
+    assert np.array_equal(d.max(axis=1) + 1, L)
+    assert d.max() < 2 ** 30
+    one = workloads.paper_segments([10 ** 6])["segs"].astype(np.int64)
+    assert np.abs(one[0, 3:] - one[0, :3]).max() == 10 ** 6 - 1
