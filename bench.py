@@ -10,7 +10,9 @@ bracketed by device synchronisation.  Prints ONE JSON line.
 
 Also reported (in "extra"): the fixed-length list workload (1 048 576
 segments, 68 157 440 voxels), the same lists and a 100 000-segment 512^3
-bit-volume with the paper's Euclidean length of eq. (1), the small
+bit-volume with the paper's Euclidean length of eq. (1), the paper's three
+experiment shapes as int32 lists (with and without the copy to the host),
+the small
 1000-segment workload and a single
 segment alone (launch latency), each timed the same way; the 256-scene
 workload as plain calls, one batched launch sequence and a graph replay;
@@ -188,6 +190,56 @@ def bench_grid_euclid(args, torch, binding, workloads, dev, stream):
         "hbm_gbs_algorithmic": algo / (ms * 1e-3) / 1e9, "algorithmic_bytes": algo,
         "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
     }
+
+
+def bench_paper(args, torch, binding, workloads, dev, stream):
+    """The paper's three experiment shapes (Section 5, Tables 2-4) as int32
+    lists: one segment of 10^3..10^6 voxels; 1024 segments of 20..200 000
+    voxels each; 1024 segments of arbitrary length totalling 10^9 voxels.
+    Each is timed on the device (inputs resident, the whole list call) and
+    again with the copy of the voxel rows into pinned host memory on the
+    same stream, the regime the paper's timings include."""
+
+    def run(segs_np, reps, copy_reps):
+        segs = torch.from_numpy(segs_np).to(dev)
+        n = segs.shape[0]
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        w0 = binding.workspace(binding.vox_list_workspace_bytes(n, 0), dev)
+        total = binding.vox_segments_to_list(segs, offsets, None, 0, w0, want_total=True, stream=stream,
+                                             wide=True)
+        vox = torch.empty((total, 3), dtype=torch.int32, device=dev)
+        work = binding.workspace(binding.vox_list_workspace_bytes(n, total), dev)
+        host = torch.empty((total, 3), dtype=torch.int32, pin_memory=True)
+
+        def gen():
+            binding.vox_segments_to_list(segs, offsets, vox, total, work, stream=stream, wide=True)
+
+        def gen_copy():
+            gen()
+            host.copy_(vox, non_blocking=True)
+
+        for _ in range(2):
+            gen()
+        ms = _events_time(stream, gen, reps) / reps
+        gen_copy()
+        ms_copy = _events_time(stream, gen_copy, copy_reps) / copy_reps
+        algo = 24 * n + 8 * (n + 1) + 12 * total
+        out = {"voxels": total, "ms_device": round(ms, 4), "voxels_per_s": total / (ms * 1e-3),
+               "hbm_gbs_algorithmic": algo / (ms * 1e-3) / 1e9,
+               "ms_with_d2h": round(ms_copy, 4), "voxels_per_s_with_d2h": total / (ms_copy * 1e-3),
+               "d2h_gbs": 12 * total / (max(ms_copy - ms, 1e-6) * 1e-3) / 1e9}
+        del segs, offsets, vox, work, host, w0
+        torch.cuda.empty_cache()
+        return out
+
+    res = {"output": "int32 xyz rows (vox_segments_to_list32)", "single_segment": {}, "fixed_1024": {}}
+    for L in (10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6):
+        res["single_segment"][str(L)] = run(workloads.paper_segments([L])["segs"], 20, 5)
+    for L in (20, 200, 2000, 20000, 200000):
+        res["fixed_1024"][str(L)] = run(workloads.paper_segments([L] * 1024, seed=90 + L)["segs"], 10, 3)
+    L = workloads.paper_arbitrary_lengths()
+    res["arbitrary_1024_total_1e9"] = run(workloads.paper_segments(L)["segs"], 5, 2)
+    return res
 
 
 def bench_small(args, torch, binding, workloads, dev, stream):
@@ -444,6 +496,7 @@ def main():
             "list": bench_list(args, torch, binding, workloads, dev, stream),
             "list_euclid": bench_list(args, torch, binding, workloads, dev, stream, euclid=True),
             "grid_euclid": bench_grid_euclid(args, torch, binding, workloads, dev, stream),
+            "paper_shapes": bench_paper(args, torch, binding, workloads, dev, stream),
             "small": bench_small(args, torch, binding, workloads, dev, stream),
             "batch": bench_batch(args, torch, binding, workloads, dev, stream),
         }
