@@ -407,6 +407,39 @@ def cpu_baseline(segs_np, dims, seconds_target=15.0):
     }
 
 
+def cpu_baseline_other(workloads):
+    """The oracle beside the other workloads of "extra", each on a bounded
+    sample (about a second or two): voxels per second on one core."""
+    from oracle import oracle
+    o = oracle.default()
+
+    def rate(fn, segs, voxels):
+        t = time.perf_counter()
+        fn(segs)
+        dt = time.perf_counter() - t
+        return {"voxels_per_s": voxels / dt, "seconds": round(dt, 3)}
+
+    out = {}
+    fixed_all = workloads.fixed_length()["segs"]
+    offs = o.offsets(fixed_all)
+    out["list"] = dict(rate(o.voxel_list, fixed_all, int(offs[-1])), sample="all 1048576 fixed-length segments")
+    fixed = fixed_all[:100_000]
+    offs = o.offsets_euclid(fixed)
+    out["list_euclid"] = dict(rate(o.voxel_list_euclid, fixed, int(offs[-1])),
+                              sample="first 100000 fixed-length segments, Euclidean N")
+    c = workloads.arbitrary_length(n=100_000, volume=512)
+    vox = int(np.sum(np.diff(o.offsets_euclid(c["segs"]))))
+    out["grid_euclid"] = dict(rate(lambda s: o.grid_euclid(s, c["dims"]), c["segs"], vox),
+                              sample="the 100000-segment 512^3 Euclidean grid workload, clear included")
+    one = workloads.paper_segments([10 ** 6])["segs"]
+    out["paper_single_segment_1e6"] = dict(rate(o.voxel_list32, one, 10 ** 6),
+                                           sample="the 10^6-voxel segment as int32 rows")
+    f = workloads.paper_segments([20000] * 1024, seed=90 + 20000)["segs"]
+    out["paper_fixed_1024x20000"] = dict(rate(o.voxel_list32, f, 1024 * 20000),
+                                         sample="1024 x 20000 voxels as int32 rows")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -504,6 +537,8 @@ def main():
             line["extra"]["serving"] = bench_serving(args, torch, binding, workloads, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(r["segs_np"], r["dims"])
+        if not args.no_extra:
+            line["cpu_baseline"]["other_workloads"] = cpu_baseline_other(workloads)
     print(json.dumps(line))
 
 
