@@ -41,6 +41,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# The paper's timings on its fastest GPU ("GTX 1070i" as printed) in ms,
+# copy to the host included (Section 5, Table 2: one segment of L voxels;
+# Table 3: 1024 segments of L voxels; Table 4: 1024 arbitrary segments
+# totalling 10^9 voxels).
+PAPER_GTX1070_MS = {
+    "single": {10 ** 3: 0.45, 10 ** 4: 0.51, 10 ** 5: 0.92, 10 ** 6: 3.65428571},
+    "fixed": {20: 0.42, 2000: 4.13, 20000: 43.85, 200000: 427.62},
+    "arbitrary": 4071.01,
+}
 METRIC = "voxels/sec + HBM GB/s (batched vs plain), p50/p99 scene latency"
 
 
@@ -235,10 +244,16 @@ def bench_paper(args, torch, binding, workloads, dev, stream):
     res = {"output": "int32 xyz rows (vox_segments_to_list32)", "single_segment": {}, "fixed_1024": {}}
     for L in (10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6):
         res["single_segment"][str(L)] = run(workloads.paper_segments([L])["segs"], 20, 5)
+        res["single_segment"][str(L)]["paper_ms_gtx1070"] = PAPER_GTX1070_MS["single"][L]
     for L in (20, 200, 2000, 20000, 200000):
         res["fixed_1024"][str(L)] = run(workloads.paper_segments([L] * 1024, seed=90 + L)["segs"], 10, 3)
+        res["fixed_1024"][str(L)]["paper_ms_gtx1070"] = PAPER_GTX1070_MS["fixed"].get(L)
     L = workloads.paper_arbitrary_lengths()
     res["arbitrary_1024_total_1e9"] = run(workloads.paper_segments(L)["segs"], 5, 2)
+    res["arbitrary_1024_total_1e9"]["paper_ms_gtx1070"] = PAPER_GTX1070_MS["arbitrary"]
+    res["paper_context"] = ("paper_ms_gtx1070: the paper's times on its fastest GPU ('GTX 1070i' as printed "
+                            "in Tables 2-4 of arXiv 2009.09500), which include the copy of the "
+                            "voxels to the host; compare with ms_with_d2h (null: length not in the tables)")
     return res
 
 

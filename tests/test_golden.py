@@ -46,3 +46,15 @@ def test_paper_table4_throughput_column():
             assert abs(d - p) > 0.1
         else:
             assert abs(d - p) <= 0.11
+
+
+def test_bench_quotes_the_paper_tables():
+    """The paper timings bench.py prints as context are the stored tables'."""
+    import bench
+    t = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+    col = t["devices"].index("GPU GTX 1070i")
+    for L, ms in bench.PAPER_GTX1070_MS["single"].items():
+        assert t["table2_single_segment_ms"][str(L)][col] == ms
+    for L, ms in bench.PAPER_GTX1070_MS["fixed"].items():
+        assert t["table3_1024_fixed_length_ms"][str(L)][col] == ms
+    assert t["table4_1024_arbitrary_1gvox"]["time_ms"][col] == bench.PAPER_GTX1070_MS["arbitrary"]
