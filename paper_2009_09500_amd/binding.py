@@ -186,10 +186,10 @@ def vox_segments_to_list(segs, offsets, voxels, capacity: int, work, want_total:
                          stream=None, euclid: bool = False, wide: bool = False):
     """Calls vox_segments_to_list (vox_segments_to_list_euclid if euclid,
     vox_segments_to_list32 if wide); returns the total if want_total."""
-    lib = load()
-    _check_segs(segs)
     if euclid and wide:
         raise ValueError("the int32 lists use the Chebyshev length")
+    lib = load()
+    _check_segs(segs)
     total = ctypes.c_int64(-1)
     fn = (lib.vox_segments_to_list_euclid if euclid else
           lib.vox_segments_to_list32 if wide else lib.vox_segments_to_list)

@@ -78,3 +78,22 @@ def test_host_argument_errors(lib):
     assert st == binding.VOX_ERR_INVALID_ARGUMENT            # grid misaligned
     st = lib.vox_segments_to_grid(fake, 5, 8, 8, 8, fake, None, 1, fake, 0, None)
     assert st == binding.VOX_ERR_WORKSPACE
+
+
+def test_list_variants_share_host_checks(lib):
+    """The Euclidean and int32 list entry points reject bad arguments on the
+    host, before any device work, as the int16 lists do."""
+    P = ctypes.c_void_p
+    fake = P(1 << 20)
+    for fn in (lib.vox_segments_to_list_euclid, lib.vox_segments_to_list32):
+        assert fn(fake, -1, fake, None, 0, None, fake, 1 << 20, None) == binding.VOX_ERR_INVALID_ARGUMENT
+        assert fn(None, 5, fake, None, 0, None, fake, 1 << 20, None) == binding.VOX_ERR_INVALID_ARGUMENT
+        assert fn(fake, 5, fake, P((1 << 20) + 8), 100, None, fake, 1 << 20, None) == \
+            binding.VOX_ERR_INVALID_ARGUMENT                 # voxels misaligned
+        assert fn(fake, 5, fake, None, 0, None, fake, 16, None) == binding.VOX_ERR_WORKSPACE
+
+
+def test_binding_rejects_euclid_with_int32(lib):
+    import pytest
+    with pytest.raises(ValueError, match="Chebyshev"):
+        binding.vox_segments_to_list(None, None, None, 0, None, euclid=True, wide=True)
