@@ -156,60 +156,26 @@ __device__ __forceinline__ void axis_step(AxisStep& st, uint32_t two_n) {
     st.q += c ? 1u : 0u;
 }
 
-// The samples k = 0..N of a segment for an N that is at least every |d_a|
-// (the Chebyshev length, or the Euclidean one of eq. (1)): q_a(k) =
-// floor((2 k a + N - neg) / 2N), so sample k's voxel is p0 + sign * q.
-// Each step advances every axis by at most one, and reports whether any
-// did, i.e. whether sample k lies in another voxel than sample k - 1.
-struct SampleWalk {
-    AxisStep st[3];
-    uint32_t neg[3];
-    uint32_t two_n;
-};
+// Lanes per segment where a wave takes several segments at once, one sample
+// per lane (a power of two dividing 64).
+constexpr int kSampleLanes = 16;
 
-__device__ __forceinline__ SampleWalk sample_walk(const Seg& g, uint32_t N) {
-    SampleWalk w;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int32_t d = g.p1[a] - g.p0[a];
-        w.neg[a] = d < 0;
-        w.st[a].two_a = 2u * (uint32_t)(d < 0 ? -d : d);
-        w.st[a].q = 0u;
-        w.st[a].r = N ? N - w.neg[a] : 0u;
-    }
-    w.two_n = 2u * N;
-    return w;
-}
-
-__device__ __forceinline__ bool sample_step(SampleWalk& w) {
-    bool moved = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const uint32_t q = w.st[a].q;
-        axis_step(w.st[a], w.two_n);
-        moved |= w.st[a].q != q;
-    }
-    return moved;
-}
-
-__device__ __forceinline__ int32_t sample_coord(const SampleWalk& w, const Seg& g, int a) {
-    const int32_t q = (int32_t)w.st[a].q;
-    return g.p0[a] + (w.neg[a] ? -q : q);
-}
-
-// Sample k of a segment computed on its own, for lanes that each take one
-// sample: q_a(k) and r_a(k), the quotient and remainder of
-// (2 k a + N - neg) / 2N.  Because a <= N, the step from k - 1 to k moves
-// axis a (by one) exactly when it carries, that is when r_a(k) < 2a; at()
-// returns whether any axis moved (true at k = 0).  Up to N = 32767 the
-// numerators of k <= N stay below 2^31 and the quotients below 2^15, so one
-// reciprocal serves (divmod_down); beyond that, 64-bit divisions.  Lanes
-// with k > N get meaningless values.
+// The samples of one segment as taken by one of its kSampleLanes lanes:
+// samples k, k + kSampleLanes, k + 2 kSampleLanes, ...  q_a and r_a are the
+// quotient and remainder of (2 k a + N - neg) / 2N.  Because a <= N, the
+// step from k - 1 to k moves axis a (by one) exactly when it carries, that is
+// when r_a(k) < 2a, so a lane knows on its own whether its sample starts a
+// new voxel.  start() divides once (one reciprocal for all three axes up to
+// N = 32767, where the numerators stay below 2^31 and the quotients below
+// 2^15; 64-bit divisions beyond); next() moves on by kSampleLanes samples
+// with the per-segment stride (dq, dr) = divmod(kSampleLanes * 2a, 2N), one
+// add and one correction per axis.  Both return whether the sample moved
+// (true at k = 0).  Samples past N get meaningless values.
 struct SampleAt {
-    uint32_t two_a[3], num0[3];
+    uint32_t two_a[3], num0[3], dq[3], dr[3];
+    uint32_t q[3], r[3];
     bool neg[3];
     uint32_t N, two_n;
-    float rcpd;
 
     __device__ __forceinline__ void init(const Seg& g, uint32_t n) {
         N = n;
@@ -221,48 +187,53 @@ struct SampleAt {
             two_a[ax] = 2u * (uint32_t)(d < 0 ? -d : d);
             num0[ax] = n - (neg[ax] ? 1u : 0u);
         }
-        rcpd = rcp_down(two_n > 0 ? two_n : 1u);
     }
 
-    __device__ __forceinline__ bool at(uint32_t k, uint32_t q[3]) const {
+    __device__ __forceinline__ bool start(uint32_t k) {
         bool moved = k == 0;
         if (N == 0) {
-            q[0] = q[1] = q[2] = 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) q[ax] = r[ax] = dq[ax] = dr[ax] = 0;
         } else if (N <= 32767u) {
+            const float rcpd = rcp_down(two_n);
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                uint32_t r;
-                divmod_down(__umul24(k, two_a[ax]) + num0[ax], two_n, rcpd, q[ax], r);
-                moved |= r < two_a[ax];
+                divmod_down(__umul24(k, two_a[ax]) + num0[ax], two_n, rcpd, q[ax], r[ax]);
+                divmod_down(kSampleLanes * two_a[ax], two_n, rcpd, dq[ax], dr[ax]);
+                moved |= r[ax] < two_a[ax];
             }
         } else {
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 const uint64_t num = (uint64_t)k * two_a[ax] + num0[ax];
                 q[ax] = (uint32_t)(num / two_n);
-                moved |= (uint32_t)(num - (uint64_t)q[ax] * two_n) < two_a[ax];
+                r[ax] = (uint32_t)(num - (uint64_t)q[ax] * two_n);
+                const uint32_t s = kSampleLanes * two_a[ax];
+                dq[ax] = s / two_n;
+                dr[ax] = s - dq[ax] * two_n;
+                moved |= r[ax] < two_a[ax];
             }
         }
         return moved;
     }
 
-    __device__ __forceinline__ int32_t coord(const Seg& g, const uint32_t q[3], int ax) const {
+    __device__ __forceinline__ bool next() {
+        bool moved = false;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const uint32_t t = r[ax] + dr[ax];
+            const bool c = t >= two_n;
+            r[ax] = c ? t - two_n : t;
+            q[ax] += dq[ax] + (c ? 1u : 0u);
+            moved |= r[ax] < two_a[ax];
+        }
+        return moved;
+    }
+
+    __device__ __forceinline__ int32_t coord(const Seg& g, int ax) const {
         return g.p0[ax] + (neg[ax] ? -(int32_t)q[ax] : (int32_t)q[ax]);
     }
 };
-
-// Lanes per segment where a wave takes several segments at once, one sample
-// per lane (a power of two dividing 64).
-constexpr int kSampleLanes = 16;
-
-// Voxels of segment g under the Euclidean length N (consecutive duplicates
-// removed): 1 + the number of steps that move.
-__device__ __forceinline__ uint32_t euclid_count(const Seg& g, uint32_t N) {
-    SampleWalk w = sample_walk(g, N);
-    uint32_t c = 1;
-    for (uint32_t k = 1; k <= N; ++k) c += sample_step(w) ? 1u : 0u;
-    return c;
-}
 
 // ------------------------------------------------------------ block scans
 

@@ -67,15 +67,15 @@ __global__ __launch_bounds__(kGridBlock) void k_grid_direct(const int32_t* __res
         // Inside the volume every side is below 2^20: N < 2^21.
         SampleAt s;
         s.init(g, kEuclid ? euclid_length(g) : (uint32_t)seg_length(g));
+        bool moved = s.start(sub);
         uint32_t kept = 0;
         for (uint32_t c0 = 0; __ballot(ok && c0 <= s.N) != 0; c0 += kSampleLanes) {
-            const uint32_t k = c0 + sub;
-            uint32_t q[3];
-            const bool keep = s.at(k, q) && ok && k <= s.N;
+            if (c0 != 0) moved = s.next();
+            const bool keep = moved && ok && c0 + sub <= s.N;
             if (keep) {
-                const uint64_t b = ((uint64_t)s.coord(g, q, 2) * (uint64_t)dy + (uint64_t)s.coord(g, q, 1)) *
+                const uint64_t b = ((uint64_t)s.coord(g, 2) * (uint64_t)dy + (uint64_t)s.coord(g, 1)) *
                                        (uint64_t)dx +
-                                   (uint64_t)s.coord(g, q, 0);
+                                   (uint64_t)s.coord(g, 0);
                 atomicOr(grid + (b >> 5), 1u << (uint32_t)(b & 31u));
             }
             if (kEuclid) kept += (uint32_t)__popcll(__ballot(keep) & slot_bits);

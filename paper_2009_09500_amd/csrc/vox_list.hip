@@ -18,6 +18,36 @@ namespace vox {
 
 // ------------------------------------------------------------------ count
 
+// Voxels of an int16-range segment under the Euclidean N of eq. (1)
+// (consecutive duplicates removed): 1 + the steps k - 1 -> k, k = 1..N,
+// that carry on some axis (r_a += 2a; a carry when r_a reaches 2N, which is
+// exactly when that axis moves, since a <= N).  One thread walks the
+// segment; a wave's segments have similar lengths in the workloads here.
+__device__ __forceinline__ uint32_t euclid_count(const Seg& g) {
+    const uint32_t N = euclid_length(g);
+    const uint32_t two_n = 2u * N;
+    uint32_t two_a[3], r[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int32_t d = g.p1[ax] - g.p0[ax];
+        two_a[ax] = 2u * (uint32_t)(d < 0 ? -d : d);
+        r[ax] = N - (d < 0 ? 1u : 0u);
+    }
+    uint32_t c = 1;
+    for (uint32_t k = 1; k <= N; ++k) {
+        bool moved = false;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const uint32_t t = r[ax] + two_a[ax];
+            const bool carry = t >= two_n;
+            r[ax] = carry ? t - two_n : t;
+            moved |= carry;
+        }
+        c += moved ? 1u : 0u;
+    }
+    return c;
+}
+
 // Voxel counts per segment (N + 1, or with the Euclidean N of eq. (1) the
 // samples that start a new voxel) and their block sums; out-of-range flags
 // (int16 lists: a coordinate outside int16; int32 lists: an axis spanning
@@ -40,7 +70,7 @@ __global__ __launch_bounds__(kCountBlock) void k_list_count(const int32_t* __res
             int64_t c;
             if constexpr (kKind == kListEuclid) {
                 // (An out-of-range segment writes nothing: no walk of it.)
-                c = inr ? (int64_t)euclid_count(g, euclid_length(g)) : 1;
+                c = inr ? (int64_t)euclid_count(g) : 1;
             } else {
                 c = seg_length(g) + 1;
             }
@@ -292,7 +322,8 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 
 // Lists with the Euclidean N of eq. (1).  A wave takes four segments, 16
 // lanes each; a segment's lanes take its samples k = 0..N 16 at a time,
-// each deciding alone whether its sample starts a new voxel (SampleAt); a
+// each stepping its own samples and deciding alone whether its sample starts
+// a new voxel (SampleAt); a
 // ballot of those decisions places the kept voxels, and consecutive lanes
 // write consecutive voxels.
 template <bool kAligned8>
@@ -314,18 +345,18 @@ __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
         if (valid) g = load_seg<kAligned8>(segs, i);
         SampleAt s;
         s.init(g, euclid_length(g));
+        bool moved = s.start(sub);
         int16_t* out = voxels + 3 * (valid ? offsets[i] : 0);
         for (uint32_t c0 = 0; __ballot(valid && c0 <= s.N) != 0; c0 += kSampleLanes) {
-            const uint32_t k = c0 + sub;
-            uint32_t q[3];
-            const bool keep = s.at(k, q) && valid && k <= s.N;
+            if (c0 != 0) moved = s.next();
+            const bool keep = moved && valid && c0 + sub <= s.N;
             const uint64_t m = __ballot(keep) & slot_bits;
             if (keep) {
                 const uint32_t before = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 int16_t* o = out + 3 * before;
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) o[ax] = (int16_t)s.coord(g, q, ax);
+                for (int ax = 0; ax < 3; ++ax) o[ax] = (int16_t)s.coord(g, ax);
             }
             out += 3 * __popcll(m);
         }
