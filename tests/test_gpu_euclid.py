@@ -127,3 +127,57 @@ def test_grid_out_of_volume_segment():
     assert binding.vox_read_status(work) == binding.VOX_ERR_OUT_OF_RANGE
     ok = segs[[0, 2]]
     assert np.array_equal(grid_host(g), oracle.grid_euclid(ok, dims))
+
+
+def test_list_full_fixed_length_sampled():
+    """The full 1 048 576-segment fixed-length set with the Euclidean N:
+    counts (offset differences) and voxels of 4 000 sampled segments against
+    the oracle, and the offsets' total against the sum of the counts."""
+    torch = pytest.importorskip("torch")
+    segs = workloads.fixed_length()["segs"]
+    offs, vox = binding.segments_to_list(to_dev(segs), euclid=True)
+    h_offs = to_host(offs)
+    counts = np.diff(h_offs)
+    assert counts.min() >= 65 and h_offs[0] == 0
+    rng = np.random.default_rng(64)
+    pick = np.sort(rng.choice(segs.shape[0], 4000, replace=False))
+    pick = np.concatenate([[0], pick, [segs.shape[0] - 1]])
+    assert np.array_equal(counts[pick], oracle.counts_euclid(segs[pick]))
+    rows = np.concatenate([np.arange(h_offs[i], h_offs[i + 1]) for i in pick])
+    got = to_host(vox.index_select(0, torch.from_numpy(rows).to(dev())))
+    assert np.array_equal(got, oracle.voxel_list_euclid(segs[pick]))
+
+
+def test_grid_full_arbitrary_length_sampled():
+    """The full 4 194 304-segment arbitrary-length set into a cleared 2048^3
+    volume with the Euclidean N: every voxel of 3 000 sampled segments (the
+    oracle's lists) is set, the counts of those segments match, and the
+    volume holds no more voxels than the counts add up to."""
+    torch = pytest.importorskip("torch")
+    c = workloads.arbitrary_length()
+    segs, dims = c["segs"], c["dims"]
+    g, counts = binding.segments_to_grid(to_dev(segs), dims, want_counts=True, euclid=True)
+    h_counts = to_host(counts)
+    rng = np.random.default_rng(65)
+    pick = np.sort(rng.choice(segs.shape[0], 3000, replace=False))
+    assert np.array_equal(h_counts[pick], oracle.counts_euclid(segs[pick]))
+    v = oracle.voxel_list_euclid(segs[pick]).astype(np.int64)
+    b = (v[:, 2] * dims[1] + v[:, 1]) * dims[0] + v[:, 0]
+    words = to_host(g.index_select(0, torch.from_numpy(b >> 5).to(dev()))).view(np.uint32)
+    assert np.all((words >> (b & 31).astype(np.uint32)) & 1)
+    set_bits = popcount_words(torch, g)
+    assert 0 < set_bits <= int(h_counts.astype(np.int64).sum())
+    del g
+    torch.cuda.empty_cache()
+
+
+def popcount_words(torch, g, chunk=1 << 25):
+    """Set bits of an int32 device tensor (SWAR popcount in int64, chunked)."""
+    total = 0
+    for i in range(0, g.numel(), chunk):
+        x = g[i:i + chunk].to(torch.int64) & 0xFFFFFFFF
+        x = x - ((x >> 1) & 0x55555555)
+        x = (x & 0x33333333) + ((x >> 2) & 0x33333333)
+        x = (x + (x >> 4)) & 0x0F0F0F0F
+        total += int(((x * 0x01010101) & 0xFFFFFFFF).__rshift__(24).sum().item())
+    return total
