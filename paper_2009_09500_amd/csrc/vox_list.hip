@@ -260,7 +260,9 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 #pragma unroll
         for (int v = 0; v < kListPerThread; ++v) {
             const int j = first + v;
-            if (j >= next && j < count) {
+            // (Never at v = 0: the search found the segment holding voxel
+            // `first`, and every segment has at least one voxel.)
+            if (v > 0 && j >= next && j < count) {
                 // First voxel of the following segment: k = 0.
                 ++s;
                 next = srel[s + 1];
