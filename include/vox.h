@@ -153,7 +153,12 @@ size_t vox_grid_workspace_bytes(int64_t n, int32_t dim_x, int32_t dim_y, int32_t
  * Device-checked: both end points of a segment must lie inside the volume
  * (then every voxel does, as each coordinate is rounded from a value between
  * two in-range integers).  A segment that fails sets VOX_ERR_OUT_OF_RANGE
- * and contributes no voxel; the others are still written. */
+ * and contributes no voxel; the others are still written.
+ *
+ * Calls with more than 16384 segments, 8-byte-aligned d_segs, the
+ * Chebyshev N, dim_x a multiple of 32 and every side at most 16384 (and a
+ * brick count within the library's limit) fill LDS bricks; the others take
+ * the direct path (one device atomic per voxel).  The output is the same. */
 vox_status vox_segments_to_grid(const vox_segment *d_segs, int64_t n,
                                 int32_t dim_x, int32_t dim_y, int32_t dim_z,
                                 uint32_t *d_grid, int32_t *d_counts, uint32_t flags,

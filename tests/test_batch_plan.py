@@ -118,10 +118,15 @@ def test_one_scene_table_has_no_lookup_arrays(lib):
 
 
 def test_plain_and_batch_workspace_agree(lib):
-    """A one-scene batch needs what the plain call on the same volume needs."""
-    for n, dims in ((1000, (256, 256, 256)), (10**6, (512, 512, 512)), (1, (64, 64, 32))):
+    """A one-scene batch needs what the plain call on the same volume needs
+    when the plain call takes the brick path (more than 16384 segments);
+    smaller plain calls take the direct path and need less."""
+    for n, dims in ((20000, (256, 256, 256)), (10**6, (512, 512, 512)), (16385, (64, 64, 32))):
         _, launch = plan(lib, [(n, dims, 1)])
         assert launch.work_bytes == lib.vox_grid_workspace_bytes(n, *dims)
+    for n, dims in ((1000, (256, 256, 256)), (16384, (512, 512, 512)), (1, (64, 64, 32))):
+        _, launch = plan(lib, [(n, dims, 1)])
+        assert 0 < lib.vox_grid_workspace_bytes(n, *dims) < launch.work_bytes
 
 
 def test_tuning_sets_batch_shape(lib):

@@ -143,7 +143,7 @@ def test_full_length_pieces(lg):
     try:
         dims = (512, 64, 64)
         rng = np.random.default_rng(21)
-        n = 4096
+        n = 20000  # above the direct path's segment limit
         y0 = rng.integers(3, 61, n)
         z0 = rng.integers(3, 61, n)
         segs = np.stack([np.zeros(n, np.int64), y0, z0, np.full(n, 511), y0 + rng.integers(-3, 4, n),
