@@ -104,7 +104,8 @@ def tune_grid(segs, dims, reps: int = 3, shapes=None, cache: TuneCache | None = 
     """Times each shape on (segs, dims) with a scratch volume, stores the
     fastest in the cache, sets it as the process-wide tuning and returns
     (shape, {shape: ms}).  `timer(shape) -> ms` replaces the GPU timing
-    (tests)."""
+    (tests).  Plain calls of at most 16384 segments take the direct path,
+    where the shape changes nothing: tune with more segments than that."""
     from . import binding
     shapes = list(shapes or SHAPES)
     cache = cache if cache is not None else TuneCache()
