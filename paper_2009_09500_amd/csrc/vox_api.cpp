@@ -130,12 +130,18 @@ static vox_status segments_to_list(const vox_segment* d_segs, int64_t n, int64_t
     const bool a8 = aligned(d_segs, 8);
     vox::ListWork w = vox::list_workspace(d_work, n, cap);
     hipError_t e;
-    if ((e = vox::launch_list_count(segs, n, a8, w, s, kind)) != hipSuccess) return device_fail(e, "count");
-    if ((e = vox::launch_list_scan(w, n, d_offsets, cap, want, s)) != hipSuccess)
-        return device_fail(e, "scan");
-    // (The Euclidean lists are written per segment: no output tiles.)
-    if ((e = vox::launch_list_offsets(n, d_offsets, w, cap, want && !euclid, s)) != hipSuccess)
-        return device_fail(e, "offsets");
+    if (n >= 1 && n <= vox::kSegsPerCountBlock) {
+        // One block counts, scans and places.
+        if ((e = vox::launch_list_one_block(segs, n, a8, w, d_offsets, cap, want, s, kind)) != hipSuccess)
+            return device_fail(e, "count");
+    } else {
+        if ((e = vox::launch_list_count(segs, n, a8, w, s, kind)) != hipSuccess) return device_fail(e, "count");
+        if ((e = vox::launch_list_scan(w, n, d_offsets, cap, want, s)) != hipSuccess)
+            return device_fail(e, "scan");
+        // (The Euclidean lists are written per segment: no output tiles.)
+        if ((e = vox::launch_list_offsets(n, d_offsets, w, cap, want && !euclid, s)) != hipSuccess)
+            return device_fail(e, "offsets");
+    }
 
     int64_t tiles = want ? (cap + vox::kListTile - 1) / vox::kListTile : 0;
     vox_status result = VOX_OK;

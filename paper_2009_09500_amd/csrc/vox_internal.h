@@ -64,6 +64,10 @@ enum ListKind { kListI16 = 0, kListEuclid = 1, kListI32 = 2 };
 
 hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
                              hipStream_t stream, ListKind kind);
+// Count, scan and offsets in one block, for 1 <= n <= kSegsPerCountBlock.
+hipError_t launch_list_one_block(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
+                                 int64_t* offsets, int64_t capacity, bool want_voxels, hipStream_t stream,
+                                 ListKind kind);
 hipError_t launch_list_scan(const ListWork& w, int64_t n, int64_t* offsets, int64_t capacity,
                             bool want_voxels, hipStream_t stream);
 hipError_t launch_list_offsets(int64_t n, int64_t* offsets, const ListWork& w, int64_t capacity,

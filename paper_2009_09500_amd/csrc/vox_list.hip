@@ -159,6 +159,73 @@ __global__ __launch_bounds__(kCountBlock) void k_list_offsets(
     }
 }
 
+// ---------------------------------------------------- one-block lists
+
+// Lists of at most kSegsPerCountBlock segments: the count, scan and offsets
+// kernels in one block (a call is then two launches with the voxel kernel).
+// Writes what those three write: counts, offsets[0..n], the total, the
+// status word (range flags, capacity) and the tile map.
+template <bool kAligned8, int kKind>
+__global__ __launch_bounds__(kCountBlock) void k_list_one_block(
+    const int32_t* __restrict__ segs, int64_t n, uint32_t* __restrict__ counts, int64_t* __restrict__ offsets,
+    int32_t* __restrict__ tile_seg, int64_t tile_limit, int64_t* __restrict__ total_p,
+    int32_t* __restrict__ status, int64_t capacity, int want_voxels) {
+    __shared__ int64_t lds[kCountBlock / kWave];
+    int64_t c[kCountPerThread];
+    int64_t flag = 0;
+#pragma unroll
+    for (int s = 0; s < kCountPerThread; ++s) {
+        const int64_t i = (int64_t)s * kCountBlock + threadIdx.x;
+        c[s] = 0;
+        if (i < n) {
+            Seg g = load_seg<kAligned8>(segs, i);
+            const bool inr = kKind == kListI32 ? span_below_2p30(g) : in_int16(g);
+            int64_t v;
+            if constexpr (kKind == kListEuclid) {
+                v = inr ? (int64_t)euclid_count(g) : 1;
+            } else {
+                v = seg_length(g) + 1;
+            }
+            flag |= inr ? 0 : kStatusOutOfRange;
+            c[s] = v > 0xFFFFFFFFll ? 0xFFFFFFFFll : v;
+            counts[i] = (uint32_t)c[s];
+        }
+    }
+    const int64_t flags = block_sum<kCountBlock>(flag, lds);
+    // Offsets, as the scan and offsets kernels would write them.
+    int64_t carry = 0;
+    int64_t off[kCountPerThread];
+#pragma unroll
+    for (int s = 0; s < kCountPerThread; ++s) {
+        int64_t sub;
+        off[s] = carry + block_exclusive_sum<kCountBlock>(c[s], lds, sub);
+        const int64_t i = (int64_t)s * kCountBlock + threadIdx.x;
+        if (i < n) offsets[i] = off[s];
+        carry += sub;
+    }
+    const int64_t tot = carry;
+    int32_t st = flags ? kStatusOutOfRange : 0;
+    if (want_voxels && tot > capacity) st |= kStatusCapacity;
+    if (threadIdx.x == 0) {
+        offsets[n] = tot;
+        *total_p = tot;
+        *status = st;
+    }
+    if (tile_limit > 0 && st == 0) {
+        const int64_t ntiles = tot < tile_limit * kListTile ? (tot + kListTile - 1) / kListTile : tile_limit;
+#pragma unroll
+        for (int s = 0; s < kCountPerThread; ++s) {
+            const int64_t i = (int64_t)s * kCountBlock + threadIdx.x;
+            if (i < n) {
+                const int64_t t0 = (off[s] + kListTile - 1) / kListTile;
+                int64_t t1 = (off[s] + c[s] - 1) / kListTile;  // inclusive
+                if (t1 >= ntiles) t1 = ntiles - 1;
+                for (int64_t t = t0; t <= t1; ++t) tile_seg[t] = (int32_t)i;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ voxel tiles
 
 // One tile = kListTile consecutive output voxels [j0, j1).  Its segments
@@ -421,6 +488,34 @@ hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, cons
         list_count<kListI32>(segs, n, aligned8, w, stream);
     else
         list_count<kListI16>(segs, n, aligned8, w, stream);
+    return hipGetLastError();
+}
+
+template <int kKind>
+static void list_one_block(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w, int64_t* offsets,
+                           int64_t capacity, bool want_voxels, hipStream_t stream) {
+    // (The Euclidean lists are written per segment: no output tiles.)
+    const int64_t tile_limit = want_voxels && kKind != kListEuclid ? (capacity + kListTile - 1) / kListTile : 0;
+    if (aligned8)
+        k_list_one_block<true, kKind><<<1, kCountBlock, 0, stream>>>(segs, n, w.counts, offsets, w.tile_seg,
+                                                                      tile_limit, w.total, w.status, capacity,
+                                                                      want_voxels ? 1 : 0);
+    else
+        k_list_one_block<false, kKind><<<1, kCountBlock, 0, stream>>>(segs, n, w.counts, offsets, w.tile_seg,
+                                                                       tile_limit, w.total, w.status, capacity,
+                                                                       want_voxels ? 1 : 0);
+}
+
+hipError_t launch_list_one_block(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
+                                 int64_t* offsets, int64_t capacity, bool want_voxels, hipStream_t stream,
+                                 ListKind kind) {
+    KernelTimer timer("list_one_block", stream);
+    if (kind == kListEuclid)
+        list_one_block<kListEuclid>(segs, n, aligned8, w, offsets, capacity, want_voxels, stream);
+    else if (kind == kListI32)
+        list_one_block<kListI32>(segs, n, aligned8, w, offsets, capacity, want_voxels, stream);
+    else
+        list_one_block<kListI16>(segs, n, aligned8, w, offsets, capacity, want_voxels, stream);
     return hipGetLastError();
 }
 
