@@ -13,7 +13,11 @@ __global__ void k_grid_init(int32_t* status) {
     if (threadIdx.x == 0) *status = 0;
 }
 
-__global__ __launch_bounds__(kGridBlock) void k_grid_clear(uint32_t* __restrict__ grid, int64_t nwords) {
+// Zeroes the volume and the status word (a cleared direct call is then two
+// launches).
+__global__ __launch_bounds__(kGridBlock) void k_grid_clear(uint32_t* __restrict__ grid, int64_t nwords,
+                                                           int32_t* __restrict__ status) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
     const int64_t stride = (int64_t)gridDim.x * kGridBlock;
     const int64_t n4 = nwords / 4;
     uint4* g4 = reinterpret_cast<uint4*>(grid);
@@ -133,22 +137,20 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
     const bool euclid = (flags & 2u) != 0;  // VOX_GRID_EUCLID: the direct path only
     if (!euclid && aligned8 && use_bricks(n, dx, dy, dz, bg))
         return launch_brick_grid(segs, n, bg, grid, counts, flags, w.status, w.bytes, stream);
-    {
-        KernelTimer timer("grid_init", stream);
-        k_grid_init<<<1, 64, 0, stream>>>(w.status);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
     const int64_t nwords = ((int64_t)dx * dy * dz + 31) / 32;
     if (flags & 1u) {
         int64_t blocks = (nwords / 4 + kGridBlock - 1) / kGridBlock;
         if (blocks > 8192) blocks = 8192;
         if (blocks < 1) blocks = 1;
         KernelTimer timer("grid_clear", stream);
-        k_grid_clear<<<dim3((unsigned)blocks), kGridBlock, 0, stream>>>(grid, nwords);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        k_grid_clear<<<dim3((unsigned)blocks), kGridBlock, 0, stream>>>(grid, nwords, w.status);
+    } else {
+        KernelTimer timer("grid_init", stream);
+        k_grid_init<<<1, 64, 0, stream>>>(w.status);
     }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     if (n == 0) return hipSuccess;
     constexpr int kSegsPerBlock = kGridBlock / kSampleLanes;
     int64_t blocks = (n + kSegsPerBlock - 1) / kSegsPerBlock;
