@@ -164,13 +164,14 @@ __global__ __launch_bounds__(kCountBlock) void k_list_offsets(
 // Lists of at most kSegsPerCountBlock segments: the count, scan and offsets
 // kernels in one block (a call is then two launches with the voxel kernel).
 // Writes what those three write: counts, offsets[0..n], the total, the
-// status word (range flags, capacity) and the tile map.
+// status word (range flags, capacity) and the tile map (here tile-parallel).
 template <bool kAligned8, int kKind>
 __global__ __launch_bounds__(kCountBlock) void k_list_one_block(
     const int32_t* __restrict__ segs, int64_t n, uint32_t* __restrict__ counts, int64_t* __restrict__ offsets,
     int32_t* __restrict__ tile_seg, int64_t tile_limit, int64_t* __restrict__ total_p,
     int32_t* __restrict__ status, int64_t capacity, int want_voxels) {
     __shared__ int64_t lds[kCountBlock / kWave];
+    __shared__ int64_t soff[kSegsPerCountBlock + 1];
     int64_t c[kCountPerThread];
     int64_t flag = 0;
 #pragma unroll
@@ -200,7 +201,10 @@ __global__ __launch_bounds__(kCountBlock) void k_list_one_block(
         int64_t sub;
         off[s] = carry + block_exclusive_sum<kCountBlock>(c[s], lds, sub);
         const int64_t i = (int64_t)s * kCountBlock + threadIdx.x;
-        if (i < n) offsets[i] = off[s];
+        if (i < n) {
+            offsets[i] = off[s];
+            soff[i] = off[s];
+        }
         carry += sub;
     }
     const int64_t tot = carry;
@@ -211,19 +215,44 @@ __global__ __launch_bounds__(kCountBlock) void k_list_one_block(
         *total_p = tot;
         *status = st;
     }
+    __syncthreads();  // soff complete
     if (tile_limit > 0 && st == 0) {
+        // Tile t starts in the segment holding voxel t * kListTile: the
+        // largest i with offsets[i] <= t * kListTile (every segment has at
+        // least one voxel, so the offsets increase strictly).  One tile per
+        // thread at a time, so one long segment spreads over the block.
         const int64_t ntiles = tot < tile_limit * kListTile ? (tot + kListTile - 1) / kListTile : tile_limit;
-#pragma unroll
-        for (int s = 0; s < kCountPerThread; ++s) {
-            const int64_t i = (int64_t)s * kCountBlock + threadIdx.x;
-            if (i < n) {
-                const int64_t t0 = (off[s] + kListTile - 1) / kListTile;
-                int64_t t1 = (off[s] + c[s] - 1) / kListTile;  // inclusive
-                if (t1 >= ntiles) t1 = ntiles - 1;
-                for (int64_t t = t0; t <= t1; ++t) tile_seg[t] = (int32_t)i;
+        for (int64_t t = threadIdx.x; t < ntiles; t += kCountBlock) {
+            const int64_t j = t * kListTile;
+            int lo = 0, hi = (int)n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (soff[mid] <= j) lo = mid; else hi = mid - 1;
             }
+            tile_seg[t] = lo;
         }
     }
+}
+
+// Tile map for many tiles, one thread per tile: tile t starts in the
+// segment holding voxel t * kListTile, the largest i with offsets[i] <=
+// t * kListTile (found by binary search over the n offsets).
+__global__ __launch_bounds__(kCountBlock) void k_list_tiles(const int64_t* __restrict__ offsets, int64_t n,
+                                                            int32_t* __restrict__ tile_seg, int64_t tile_limit,
+                                                            const int64_t* __restrict__ total_p,
+                                                            const int32_t* __restrict__ status) {
+    if (*status != 0) return;
+    const int64_t tot = *total_p;
+    const int64_t ntiles = tot < tile_limit * kListTile ? (tot + kListTile - 1) / kListTile : tile_limit;
+    const int64_t t = (int64_t)blockIdx.x * kCountBlock + threadIdx.x;
+    if (t >= ntiles) return;
+    const int64_t j = t * kListTile;
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (offsets[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    tile_seg[t] = (int32_t)lo;
 }
 
 // ------------------------------------------------------------ voxel tiles
@@ -491,11 +520,16 @@ hipError_t launch_list_count(const int32_t* segs, int64_t n, bool aligned8, cons
     return hipGetLastError();
 }
 
+// Tile maps up to this many tiles are written by the one-block kernel
+// itself; larger ones by k_list_tiles, one thread per tile.
+constexpr int64_t kOneBlockMaxTiles = 4096;
+
 template <int kKind>
 static void list_one_block(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w, int64_t* offsets,
                            int64_t capacity, bool want_voxels, hipStream_t stream) {
     // (The Euclidean lists are written per segment: no output tiles.)
-    const int64_t tile_limit = want_voxels && kKind != kListEuclid ? (capacity + kListTile - 1) / kListTile : 0;
+    const int64_t tiles = want_voxels && kKind != kListEuclid ? (capacity + kListTile - 1) / kListTile : 0;
+    const int64_t tile_limit = tiles <= kOneBlockMaxTiles ? tiles : 0;
     if (aligned8)
         k_list_one_block<true, kKind><<<1, kCountBlock, 0, stream>>>(segs, n, w.counts, offsets, w.tile_seg,
                                                                       tile_limit, w.total, w.status, capacity,
@@ -504,6 +538,9 @@ static void list_one_block(const int32_t* segs, int64_t n, bool aligned8, const 
         k_list_one_block<false, kKind><<<1, kCountBlock, 0, stream>>>(segs, n, w.counts, offsets, w.tile_seg,
                                                                        tile_limit, w.total, w.status, capacity,
                                                                        want_voxels ? 1 : 0);
+    if (tiles > kOneBlockMaxTiles)
+        k_list_tiles<<<dim3((unsigned)((tiles + kCountBlock - 1) / kCountBlock)), kCountBlock, 0, stream>>>(
+            offsets, n, w.tile_seg, tiles, w.total, w.status);
 }
 
 hipError_t launch_list_one_block(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
