@@ -169,3 +169,15 @@ def test_unsupported_shape_rejected():
     with pytest.raises(binding.VoxError):
         binding.vox_set_tuning((9, 9, 9))
     assert binding.vox_get_tuning() == (0, 0, 0)
+
+
+@pytest.mark.parametrize("n", [16384, 16385])
+def test_direct_brick_boundary(n):
+    """Plain calls of at most 16384 segments take the direct path, larger
+    ones the brick path: both sides, cleared and ORed into a volume."""
+    dims = (256, 128, 64)
+    segs = random_in(dims, n, 500 + n)
+    assert_grid(segs, dims)
+    rng = np.random.default_rng(n)
+    base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+    assert_grid(segs, dims, base=base)

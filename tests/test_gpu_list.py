@@ -148,3 +148,15 @@ def test_repeatable():
     a = run_list(segs)
     b = run_list(segs)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("n", [1023, 1024, 1025, 2048])
+def test_one_block_boundary(n):
+    """Lists of at most 1024 segments take the one-block count/scan/offsets
+    kernel, larger ones the three-kernel path: both sides of the boundary,
+    int16 and int32 lists, the latter with a tile map above 4096 tiles."""
+    assert_parity(workloads.arbitrary_length(n=n, seed=300 + n, volume=1024)["segs"])
+    long = workloads.paper_segments(np.full(n, 5000), seed=400 + n)["segs"]
+    offs, vox = binding.segments_to_list(to_dev(long), wide=True)
+    assert np.array_equal(to_host(offs), oracle.offsets(long))
+    assert np.array_equal(to_host(vox), oracle.voxel_list32(long))
