@@ -162,7 +162,20 @@ def bench_list(args, torch, binding, workloads, dev, stream, euclid=False):
         "algorithmic_bytes": algo,
         "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
         "list_voxels_kernel_gbs": (6 * total) / (kv_ms * 1e-3) / 1e9 if kv_ms > 0 else None,
+        # The voxel kernel against the HBM roofline: it writes 6 B a voxel and
+        # reads each segment (24 B) and its offset (8 B).
+        "roofline": _roofline("list_voxels_euclid" if euclid else "list_voxels",
+                              6 * total + 24 * n + 8 * (n + 1), kv_ms),
     }
+
+
+def _roofline(kernel, algo_bytes, avg_ms):
+    if avg_ms <= 0:
+        return None
+    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": algo_bytes,
+            "avg_launch_ms": avg_ms}
 
 
 def bench_grid_euclid(args, torch, binding, workloads, dev, stream):
@@ -235,6 +248,7 @@ def bench_paper(args, torch, binding, workloads, dev, stream):
         algo = 24 * n + 8 * (n + 1) + 12 * total
         out = {"voxels": total, "ms_device": round(ms, 4), "voxels_per_s": total / (ms * 1e-3),
                "hbm_gbs_algorithmic": algo / (ms * 1e-3) / 1e9,
+               "hbm_frac_algorithmic": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                "ms_with_d2h": round(ms_copy, 4), "voxels_per_s_with_d2h": total / (ms_copy * 1e-3),
                "d2h_gbs": 12 * total / (max(ms_copy - ms, 1e-6) * 1e-3) / 1e9}
         del segs, offsets, vox, work, host, w0
