@@ -192,3 +192,14 @@ def test_euclid_mutant_is_caught(name, tmp_path):
         if r is not None:
             fails.append(r)
     assert fails, "mutant %r passed every pin" % name
+
+
+def test_brute_force_beyond_32767():
+    """Euclidean lengths above 32767 (where the GPU kernels divide in 64 bits):
+    the whole list by exact rational arithmetic, for the int16 diagonal
+    (N = 113511) and two long skew segments."""
+    segs = np.array([[-32768, -32768, -32768, 32767, 32767, 32767],
+                     [32767, -30000, 5, -32768, 29999, -7],
+                     [-100, 20000, -32768, 150, -20000, 32767]], np.int32)
+    assert all(oracle.default().length_euclid(s) > 32767 for s in segs)
+    assert check_against_brute_force(oracle.default(), segs) is None
