@@ -567,10 +567,16 @@ hipError_t launch_list_scan(const ListWork& w, int64_t n, int64_t* offsets, int6
 hipError_t launch_list_offsets(int64_t n, int64_t* offsets, const ListWork& w, int64_t capacity,
                                bool want_voxels, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    int64_t tile_limit = want_voxels ? (capacity + kListTile - 1) / kListTile : 0;
+    const int64_t tiles = want_voxels ? (capacity + kListTile - 1) / kListTile : 0;
+    // Segments of more than four tiles on average: the tile map from
+    // k_list_tiles (one thread per tile) rather than one thread per segment.
+    const bool per_tile = tiles > 4 * n;
     KernelTimer timer("list_offsets", stream);
     k_list_offsets<<<dim3((unsigned)w.nb), kCountBlock, 0, stream>>>(
-        n, w.counts, w.block_sums, offsets, w.tile_seg, tile_limit, w.total, w.status);
+        n, w.counts, w.block_sums, offsets, w.tile_seg, per_tile ? 0 : tiles, w.total, w.status);
+    if (per_tile)
+        k_list_tiles<<<dim3((unsigned)((tiles + kCountBlock - 1) / kCountBlock)), kCountBlock, 0, stream>>>(
+            offsets, n, w.tile_seg, tiles, w.total, w.status);
     return hipGetLastError();
 }
 
