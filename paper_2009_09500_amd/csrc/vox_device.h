@@ -104,13 +104,28 @@ __device__ __forceinline__ bool span_below_2p30(const Seg& s) {
 // 2^-20 +- 2^-22, so its integer part is the quotient or one less (the
 // quotient is below 2^15, so the shortfall stays below one), and one
 // upward correction makes it exact.
-__device__ __forceinline__ float rcp_down(uint32_t y) {
-    return __builtin_amdgcn_rcpf((float)y) * (1.0f - 0x1p-20f);
+//
+// The scaling and the division are host+device so that a host program can
+// run them with the reciprocal estimate off by -1, 0 and +1 ulp (the
+// hardware's stated error), checking the exactness claim on the CPU.
+__host__ __device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul24(a, b);
+#else
+    return (a & 0xFFFFFFu) * (b & 0xFFFFFFu);
+#endif
 }
 
-__device__ __forceinline__ void divmod_down(uint32_t x, uint32_t y, float rcpd, uint32_t& q, uint32_t& r) {
+__host__ __device__ __forceinline__ float rcp_bias_down(float rcp) { return rcp * (1.0f - 0x1p-20f); }
+
+__device__ __forceinline__ float rcp_down(uint32_t y) {
+    return rcp_bias_down(__builtin_amdgcn_rcpf((float)y));
+}
+
+__host__ __device__ __forceinline__ void divmod_down(uint32_t x, uint32_t y, float rcpd, uint32_t& q,
+                                                     uint32_t& r) {
     uint32_t qq = (uint32_t)((float)x * rcpd);
-    uint32_t rr = x - __umul24(qq, y);
+    uint32_t rr = x - mul_u24(qq, y);
     if (rr >= y) {
         ++qq;
         rr -= y;
