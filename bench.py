@@ -93,6 +93,59 @@ def counter_traffic(kernel: str, workload: str, sources):
         return None
 
 
+def counter_fields(path: str, sources):
+    """{kernel: {column: value}} of a committed rocprofv3 counter summary
+    (profiles/*.txt), or None when there is none or the kernel sources
+    changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    rows, header, digest = {}, None, None
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        if line.startswith("source_digest:"):
+            digest = line.split(":", 1)[1].strip()
+            continue
+        parts = line.split()
+        if not parts:
+            continue
+        if parts[0] == "kernel":
+            header = parts[1:]
+            continue
+        if header and len(parts) >= len(header) + 1:
+            name = " ".join(parts[:len(parts) - len(header)])
+            try:
+                rows[name] = dict(zip(header, (float(v) for v in parts[-len(header):])))
+            except ValueError:
+                pass
+    if digest != source_digest(sources):
+        return None
+    return rows
+
+
+CUS = 256
+CLOCK_HZ = 2.4e9
+VALU_PEAK = CUS * CLOCK_HZ        # wave64 VALU instructions per second (one per CU per clock)
+
+
+def counter_bound(kernel: str, workload: str, sources, avg_ms: float, traffic):
+    """What bounds a kernel, from its committed SQ counters: the time its VALU
+    wave instructions need at the chip's issue rate (256 CUs x 2.4 GHz, one
+    wave64 instruction per CU per clock) against the time its HBM bytes (the
+    FETCH/WRITE counters) need at 8 TB/s."""
+    rows = counter_fields(os.path.join(ROOT, "profiles", "sq_%s_%s.txt" % (kernel, workload)), sources)
+    if not rows or traffic is None:
+        return None
+    row = next((v for k, v in rows.items() if "k_" + kernel in k), None)
+    if row is None or "INSTS_VALU" not in row:
+        return None
+    valu_ms = row["INSTS_VALU"] / VALU_PEAK * 1e3
+    hbm_ms = traffic / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"bound": "alu" if valu_ms > hbm_ms else "hbm", "valu_wave_instructions": row["INSTS_VALU"],
+            "valu_ms_at_peak_issue": valu_ms, "hbm_ms_at_peak": hbm_ms,
+            "valu_issue_frac": valu_ms / avg_ms if avg_ms > 0 else None}
+
+
 def bench_grid(args, torch, binding, workloads, dev, stream):
     c = workloads.arbitrary_length()
     segs_np = c["segs"]
@@ -324,13 +377,12 @@ def bench_batch(args, torch, binding, workloads, dev, stream):
         for s, x, g in zip(segs, sc, grids):
             binding.vox_segments_to_grid(s, x["dims"], g, None, clear, work, stream=stream)
 
-    table, launch = binding.vox_batch_plan([(s, x["dims"], g, None, clear)
-                                            for s, x, g in zip(segs, sc, grids)])
-    d_table = torch.from_numpy(table).to(dev)
-    bwork = binding.workspace(launch.work_bytes, dev)
+    d_scenes = torch.from_numpy(binding.scene_table([(s, x["dims"], g, None, clear)
+                                                     for s, x, g in zip(segs, sc, grids)])).to(dev)
+    bwork = binding.workspace(binding.batch_workspace_bytes(n, len(sc)), dev)
 
     def batched():
-        binding.vox_batch_scenes(d_table, launch, bwork, stream=stream)
+        binding.vox_batch_scenes(d_scenes, len(sc), n, bwork, stream=stream)
 
     for _ in range(2):
         plain()
@@ -340,7 +392,7 @@ def bench_batch(args, torch, binding, workloads, dev, stream):
     side = torch.cuda.Stream(device=dev)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=side):
-        binding.vox_batch_scenes(d_table, launch, bwork, stream=side)
+        binding.vox_batch_scenes(d_scenes, len(sc), n, bwork, stream=side)
     torch.cuda.synchronize()
     reps = max(args.steps // 4, 3)
     t_plain = _events_time(stream, plain, reps) / reps
@@ -364,35 +416,48 @@ def bench_batch(args, torch, binding, workloads, dev, stream):
         "speedup_batched_vs_plain": t_plain / t_batch,
         "speedup_graph_vs_plain": t_plain / t_graph,
         "batched_kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
-        "launch": launch.as_dict(),
+        "workspace_bytes": int(bwork.numel()),
+        "piece_records": binding.vox_read_batch_info(bwork, stream=stream)[0],
     }
 
 
-def bench_serving(args, torch, binding, workloads, dev, n_requests=1000, pool_size=24):
+def _wireframe_pool(n_requests, workers=16):
+    """Requests r = 0..n-1 of the serving stream (seeds 1005 + r), generated
+    in worker processes."""
+    import concurrent.futures as cf
+    from paper_2009_09500_amd import workloads
+    with cf.ProcessPoolExecutor(max_workers=min(workers, os.cpu_count() or 1)) as ex:
+        return list(ex.map(workloads.wireframe_request, range(n_requests), chunksize=8))
+
+
+def bench_serving(args, torch, binding, workloads, dev, n_requests=1000):
     """Wireframe requests into resident 512^3 grids: saturation throughput
-    (all requests at t=0), then Poisson arrivals at fractions of it."""
+    (all requests at t=0), then Poisson arrivals at fractions of it.  Request
+    r of every run is the icosphere of seed 1005 + r."""
     from paper_2009_09500_amd import serving
-    pool = [workloads.wireframe_request(r) for r in range(pool_size)]
+    pool = _wireframe_pool(n_requests)
     pinned = [torch.from_numpy(w["segs"]).pin_memory() for w in pool]
     dims = pool[0]["dims"]
-
     vox = [int((np.abs(w["segs"][:, 3:].astype(np.int64) - w["segs"][:, :3]).max(1) + 1).sum())
            for w in pool]
+    max_batch_segments, max_batch_scenes, n_slots = 2_000_000, 32, 48
+    ex = serving.GpuExecutor(dims, n_slots=n_slots, max_batch_segments=max_batch_segments,
+                             max_batch_scenes=max_batch_scenes, device=dev)
+    budget = ex.admission_budget()
 
     def requests(arrivals):
-        return [serving.Request(i, pool[i % pool_size]["segs"], dims, float(t),
-                                voxels=vox[i % pool_size], dev={"pinned": pinned[i % pool_size]})
+        return [serving.Request(i, pool[i]["segs"], dims, float(t), voxels=vox[i],
+                                dev={"pinned": pinned[i]})
                 for i, t in enumerate(arrivals)]
 
     def once(arrivals):
-        sched = serving.Scheduler(n_slots=48, budget_bytes=8 << 30, max_batch_segments=2_000_000,
-                                  max_batch_scenes=32)
+        sched = serving.Scheduler(n_slots=n_slots, budget_bytes=budget, max_batch_segments=max_batch_segments,
+                                  max_batch_scenes=max_batch_scenes)
         out = serving.run(requests(arrivals), ex, sched)
-        assert ex.status() == binding.VOX_OK
+        assert ex.status() == binding.VOX_OK and out["failed_requests"] == 0
         return out
 
-    ex = serving.GpuExecutor(dims, n_slots=48, device=dev)
-    once(np.zeros(pool_size))                                   # warm-up
+    once(np.zeros(min(24, n_requests)))                         # warm-up
     sat = once(np.zeros(n_requests))
     sweep = []
     for f in (0.25, 0.5, 0.75, 1.0, 1.25):
@@ -403,36 +468,79 @@ def bench_serving(args, torch, binding, workloads, dev, n_requests=1000, pool_si
         sweep.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})
     edges = [w["segs"].shape[0] for w in pool]
     return {
-        "workload": "wireframe requests: geodesic icospheres (seeds 1005+r, %d distinct, "
-                    "%d..%d edges) into resident 512^3 grids" % (pool_size, min(edges), max(edges)),
+        "workload": "wireframe requests: geodesic icospheres (request r: seed 1005+r, r < %d; "
+                    "%d..%d edges) into resident 512^3 grids" % (n_requests, min(edges), max(edges)),
         "requests_per_rate": n_requests,
+        "admission_budget_bytes": budget,
+        "batch_workspace_bytes": int(ex.work.numel()),
         "saturation": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sat.items()},
         "poisson_sweep": sweep,
     }
 
 
+def host_cpu() -> dict:
+    """CPU model and core counts of this host."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "logical_cpus": os.cpu_count()}
+
+
+class _one_core:
+    """Pins this process to one of its cores for the duration."""
+
+    def __enter__(self):
+        self.prev = None
+        try:
+            self.prev = os.sched_getaffinity(0)
+            core = sorted(self.prev)[-1]
+            os.sched_setaffinity(0, {core})
+            self.core = core
+        except (AttributeError, OSError):
+            self.core = None
+        return self
+
+    def __exit__(self, *exc):
+        if self.prev is not None:
+            os.sched_setaffinity(0, self.prev)
+
+
 def cpu_baseline(segs_np, dims, seconds_target=15.0):
-    """The oracle on the first segments of the workload (bounded sample)."""
+    """The oracle (gcc -O2 -march=native, single-threaded, pinned to one
+    core) on the first segments of the workload (bounded sample)."""
     from oracle import oracle
-    o = oracle.default()
-    # Calibrate on a small prefix, then run the sample once.
-    probe = segs_np[:20000]
-    t = time.perf_counter()
-    o.grid(probe, dims)
-    dt = time.perf_counter() - t
-    per_seg = max(dt / probe.shape[0], 1e-9)
-    m = int(min(segs_np.shape[0], max(50000, seconds_target / per_seg)))
-    sample = segs_np[:m]
-    vox = int((np.abs(sample[:, 3:].astype(np.int64) - sample[:, :3]).max(1) + 1).sum())
-    t = time.perf_counter()
-    o.grid(sample, dims)
-    dt = time.perf_counter() - t
+    o = oracle.native()
+    with _one_core() as pin:
+        # Calibrate on a small prefix, then run the sample once.
+        probe = segs_np[:20000]
+        t = time.perf_counter()
+        o.grid(probe, dims)
+        dt = time.perf_counter() - t
+        per_seg = max(dt / probe.shape[0], 1e-9)
+        m = int(min(segs_np.shape[0], max(50000, seconds_target / per_seg)))
+        sample = segs_np[:m]
+        vox = int((np.abs(sample[:, 3:].astype(np.int64) - sample[:, :3]).max(1) + 1).sum())
+        t = time.perf_counter()
+        o.grid(sample, dims)
+        dt = time.perf_counter() - t
     return {
         "value": vox / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
         "sample": "first %d of %d segments (%d voxels) into the cleared %dx%dx%d volume, "
                   "clear included; %.1f s" % (m, segs_np.shape[0], vox, dims[0], dims[1],
                                                 dims[2], dt),
-        "host_cpu": platform.processor() or platform.machine(),
+        "build": "gcc -O2 -march=native, single-threaded",
+        "pinned_core": pin.core,
+        "host_cpu": host_cpu(),
     }
 
 
@@ -440,7 +548,7 @@ def cpu_baseline_other(workloads):
     """The oracle beside the other workloads of "extra", each on a bounded
     sample (about a second or two): voxels per second on one core."""
     from oracle import oracle
-    o = oracle.default()
+    o = oracle.native()
 
     def rate(fn, segs, voxels):
         t = time.perf_counter()
@@ -517,6 +625,7 @@ def main():
         dom_name, r["algo_bytes"])
     achieved = dom_algo / (dom_avg_ms * 1e-3) / 1e9 if dom_avg_ms > 0 else 0.0
     traffic = counter_traffic(dom_name, "arbitrary4m", sources)
+    bound = counter_bound(dom_name, "arbitrary4m", sources, dom_avg_ms, traffic)
     line = {
         "metric": METRIC,
         "value": value,
@@ -538,12 +647,16 @@ def main():
             "parallelism": "single GPU",
         },
         "hbm_gbs_algorithmic": r["algo_bytes"] / (ms_step * 1e-3) / 1e9,
+        # The whole step (all kernels) on its algorithmic bytes.
         "hbm_frac_algorithmic": r["algo_bytes"] / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "algorithmic_bytes_per_step": r["algo_bytes"],
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
         "roofline": {
             "kernel": dom_name,
-            "bound": "hbm",
+            # From the committed counters while they match the kernel sources;
+            # "hbm" (the roofline the line is priced against) otherwise.
+            "bound": bound["bound"] if bound else "hbm",
+            "bound_from_counters": bound,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -567,7 +680,8 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(r["segs_np"], r["dims"])
         if not args.no_extra:
-            line["cpu_baseline"]["other_workloads"] = cpu_baseline_other(workloads)
+            with _one_core():
+                line["cpu_baseline"]["other_workloads"] = cpu_baseline_other(workloads)
     print(json.dumps(line))
 
 

@@ -27,8 +27,9 @@
  *   - Argument errors detectable on the host are returned at once and launch
  *     nothing.  Errors that depend on device data (end points out of range,
  *     list capacity exceeded) are recorded in the device status word, the
- *     first int32 of d_work, as a vox_status code; vox_read_status() fetches
- *     it.  Such errors never cause an out-of-bounds write: the affected
+ *     first int32 of d_work, as VOX_DEVICE_STATUS_* bits; vox_read_status()
+ *     fetches it as a vox_status code, vox_device_status() gives its device
+ *     address.  Such errors never cause an out-of-bounds write: the affected
  *     output is left unwritten, as each entry point states.
  *   - Entry points are re-entrant.  Calls that share a workspace must be
  *     ordered (same stream, or synchronised).  vox_last_error() is
@@ -44,7 +45,7 @@
 extern "C" {
 #endif
 
-#define VOX_ABI_VERSION 4
+#define VOX_ABI_VERSION 5
 
 /* One segment: start point (x0,y0,z0) = S, end point (x1,y1,z1) = E.
  * Arrays of segments are dense, 24 bytes per segment, 4-byte aligned. */
@@ -59,7 +60,7 @@ typedef enum vox_status {
     VOX_ERR_CAPACITY = 3,         /* voxel list larger than the capacity   */
     VOX_ERR_DEVICE = 4,           /* a HIP runtime call failed             */
     VOX_ERR_WORKSPACE = 5,        /* workspace missing or too small        */
-    VOX_ERR_BATCH_MISMATCH = 6    /* batch table does not fit its launch   */
+    VOX_ERR_BATCH_MISMATCH = 6    /* batch scenes exceed the call's bounds */
 } vox_status;
 
 /* Grid flag: zero the whole bit-volume before setting voxels.  Without it
@@ -166,97 +167,132 @@ vox_status vox_segments_to_grid(const vox_segment *d_segs, int64_t n,
 
 /* ----------------------------------------------------------------- tuning */
 
-/* Launch-shape choice for bit-volume calls.  brick_lg[a] is log2 of the LDS
- * brick size along axis a; all zero selects the library default.  The
- * choice changes only speed and workspace size, never the output.  Supported
- * shapes: 2^8 x 2^6 x 2^5, 2^8 x 2^6 x 2^6, 2^7 x 2^6 x 2^6, 2^7 x 2^7 x 2^6. */
+/* Launch-shape choice for bit-volume calls (the build's counterpart of the
+ * launch-shape options of Section 5: how the many segments of one call are
+ * spread over the GPU).  brick_lg[a] is log2 of the LDS brick size along
+ * axis a; all zero selects the library default.  The choice changes only
+ * speed and workspace size, never the output.  Supported shapes:
+ * 2^8 x 2^6 x 2^5, 2^8 x 2^6 x 2^6, 2^7 x 2^6 x 2^6, 2^7 x 2^7 x 2^6.
+ * fill_wgs_per_cu: fill workgroups per compute unit (0 = the shape's
+ * default; 1 or 2 for 64 KiB bricks, 1 for 128 KiB bricks).  reserved: zero. */
 typedef struct vox_tuning {
     int32_t brick_lg[3];
+    int32_t fill_wgs_per_cu;
+    int32_t reserved[4];
 } vox_tuning;
 
-/* Sets the process-wide tuning used by later grid and batch calls (NULL
- * restores the default).  Workspace sizes depend on it: query them after
- * setting it.  VOX_ERR_INVALID_ARGUMENT for an unsupported shape. */
-vox_status vox_set_tuning(const vox_tuning *tuning);
+/* The library's autotune cache (process-wide, guarded by a mutex): the
+ * tuning that vox_segments_to_grid uses for a volume of dim_x x dim_y x
+ * dim_z and a segment count with the same floor(log2(n)), and that
+ * vox_batch_scenes uses when it is passed no tuning (key dims 0 x 0 x 0 and
+ * n = total_segments).  tuning NULL removes the entry.  Workspace sizes of
+ * plain calls depend on it: query them after setting it.
+ * VOX_ERR_INVALID_ARGUMENT for an unsupported tuning. */
+vox_status vox_tuning_cache_set(int32_t dim_x, int32_t dim_y, int32_t dim_z, int64_t n_segments,
+                                const vox_tuning *tuning);
 
-/* Current process-wide tuning. */
-vox_status vox_get_tuning(vox_tuning *tuning);
+/* The cache entry for a key: *found = 1 and *tuning filled, or *found = 0. */
+vox_status vox_tuning_cache_get(int32_t dim_x, int32_t dim_y, int32_t dim_z, int64_t n_segments,
+                                vox_tuning *tuning, int32_t *found);
+
+/* Empties the autotune cache. */
+void vox_tuning_cache_clear(void);
 
 /* ---------------------------------------------------------------- batches */
 
 /* One scene of a batch: its own segments and its own bit-volume, with the
- * meaning of the vox_segments_to_grid arguments of the same names.  Batch
- * scenes take the brick path: dim_x must be a multiple of 32 and every
- * side at most 16384, with at most 16384 bricks per scene. */
+ * meaning and the rules of the vox_segments_to_grid arguments of the same
+ * names (flags: VOX_GRID_CLEAR and/or VOX_GRID_EUCLID).  48 bytes; an array
+ * of them lives in device memory. */
 typedef struct vox_scene {
-    const vox_segment *segs; /* device, 8-byte aligned; may be NULL if n == 0 */
+    const vox_segment *segs; /* device; may be NULL if n == 0 */
     int64_t n;
     int32_t dim_x, dim_y, dim_z;
-    uint32_t flags;          /* VOX_GRID_CLEAR or 0 */
+    uint32_t flags;
     uint32_t *grid;          /* device, 16-byte aligned */
     int32_t *counts;         /* device, optional (NULL) */
 } vox_scene;
 
-/* Launch shape of a batch: the kernels are sized by these values, and a
- * table fits a launch when its own values stay within them (same brick
- * shape).  Filled in by vox_batch_plan; vox_batch_launch_cover widens one
- * launch to cover another, so one captured graph can serve several tables. */
-typedef struct vox_batch_launch {
-    int64_t rows;                 /* histogram workgroups                  */
-    int64_t bricks;               /* bricks over all scenes                */
-    int32_t brick_lg[3];          /* brick shape (log2 voxels per axis)     */
-    int32_t max_scene_bricks;     /* largest per-scene brick count         */
-    uint64_t work_bytes;          /* workspace bytes the launch needs      */
-    uint64_t table_bytes;         /* bytes of the table image              */
-} vox_batch_launch;
+/* Operation codes of vox_workspace_bytes. */
+#define VOX_OP_BATCH 3
 
-/* Host-side planning of a batch (no device call is made).  From the host
- * array h_scenes[n_scenes] (n_scenes >= 1; its pointers are device
- * pointers) build the table image in h_table (host memory, h_table_bytes
- * long) and describe the launch in *launch.  Pass h_table = NULL to fill
- * *launch only (launch->table_bytes is the size to provide).  The brick
- * shape is the process-wide tuning if set, else the default of the largest
- * scene.  The caller copies the image to device memory (any way it likes,
- * 16-byte aligned) before vox_batch_scenes runs; the copy must stay valid
- * until the batch's kernels have finished.
- * Host-checked errors: the vox_segments_to_grid argument rules per scene
- * (VOX_ERR_INVALID_ARGUMENT, with the scene index in vox_last_error), a
- * volume the brick path cannot take, h_table_bytes too small, totals beyond
- * 2^32 - 1 bricks or pieces. */
-vox_status vox_batch_plan(const vox_scene *h_scenes, int32_t n_scenes,
-                          void *h_table, size_t h_table_bytes,
-                          vox_batch_launch *launch);
+/* Workspace bytes for an operation, from the sizes known before the call:
+ *   VOX_OP_BATCH  vox_batch_scenes with n_scenes scenes of at most
+ *                 n_segments segments in all.  The bytes hold the scene
+ *                 table, the brick histograms, brick totals and offsets for
+ *                 any scenes, and piece records for an average of 16 per
+ *                 segment (a piece is a segment's run of voxels inside one
+ *                 LDS brick: about 1 + N/32 for a segment of N steps).
+ * 0 for an unknown op or negative sizes.  (Single-call workspaces:
+ * vox_list_workspace_bytes, vox_grid_workspace_bytes.) */
+size_t vox_workspace_bytes(int op, int64_t n_segments, int32_t n_scenes);
 
-/* Grows *bound so that every table fitting *launch also fits *bound
- * (element-wise maximum).  VOX_ERR_INVALID_ARGUMENT if the brick shapes
- * differ (a zeroed *bound takes the shape of *launch). */
-vox_status vox_batch_launch_cover(vox_batch_launch *bound, const vox_batch_launch *launch);
-
-/* All scenes of a planned batch in one launch sequence of the grid
- * kernels, each kernel a single launch over every scene (the paper's advice
- * to cut the number of kernel calls and load the GPU with many segments at
- * once, Section 5, conclusions), with the bricks of all scenes taken from
- * one work-stealing counter by persistent workgroups.  Every scene's grid
- * (and counts) ends up exactly as a separate vox_segments_to_grid call
- * would leave it; the device status word covers all scenes.
+/* All scenes of a batch in one launch sequence, every kernel a single
+ * launch over all scenes (the paper's advice to cut the number of kernel
+ * calls and load the GPU with many segments at once, Section 4: all
+ * segments in one core function call; Section 5, conclusions), the bricks of
+ * all scenes taken by persistent workgroups from work-stealing queues.  Every
+ * scene's grid (and counts) ends up exactly as a separate
+ * vox_segments_to_grid call would leave it; the device status word covers
+ * all scenes.
  *
- *   d_table    device copy of a table image from vox_batch_plan.
- *   launch     launch shape (host struct): the plan's own, or a cover of
- *              several plans.
- *   d_work     workspace, >= launch->work_bytes, 256-byte aligned.
+ *   d_scenes        [n_scenes] vox_scene, device memory (read by the GPU
+ *                   only), n_scenes in [1, 65536].
+ *   total_segments  an upper bound on the sum of the scenes' n (sizes the
+ *                   launch), >= 0.
+ *   tuning          host struct, or NULL: the autotune cache entry for
+ *                   (0 x 0 x 0, total_segments), else the default.
+ *   d_work          workspace, 256-byte aligned, at least
+ *                   vox_workspace_bytes(VOX_OP_BATCH, total_segments, n_scenes)
+ *                   for full speed; see below.
+ *
+ * A plan kernel reads the scenes on the GPU and checks them against the
+ * vox_segments_to_grid rules: a scene that breaks one, or scenes whose
+ * segments exceed total_segments, stop the call with nothing written and
+ * the status VOX_ERR_INVALID_ARGUMENT / VOX_ERR_BATCH_MISMATCH.  Scenes whose
+ * segment array is 8-byte aligned, with the Chebyshev N, dim_x a multiple
+ * of 32, every side at most 16384 and at most 16384 bricks take the LDS
+ * brick kernels; the others (and every scene, when the piece records of the
+ * call do not fit the workspace) take direct kernels with one device atomic
+ * per voxel.  The output never depends on which.
  *
  * Reads no device memory on the host, synchronises nothing and allocates
  * nothing, so it can be captured into a HIP graph once and replayed after
- * the caller rewrites d_table (same address) with another table that fits
- * `launch`.  Device-checked: a table that does not fit the launch or the
- * workspace writes nothing and sets VOX_ERR_BATCH_MISMATCH. */
-vox_status vox_batch_scenes(const void *d_table, const vox_batch_launch *launch,
-                            void *d_work, size_t work_bytes, void *stream);
+ * the caller rewrites d_scenes (same address, same n_scenes, segments within
+ * total_segments).  Host-checked errors (returned, nothing launched): NULL
+ * or misaligned d_scenes / d_work, n_scenes or total_segments out of range,
+ * an unsupported tuning, a workspace smaller than the table and histogram
+ * part of vox_workspace_bytes (VOX_ERR_WORKSPACE). */
+vox_status vox_batch_scenes(const vox_scene *d_scenes, int32_t n_scenes, int64_t total_segments,
+                            const vox_tuning *tuning, void *d_work, size_t work_bytes, void *stream);
 
 /* -------------------------------------------------------------- utilities */
 
+/* Bits of the device status word (first int32 of every workspace). */
+#define VOX_DEVICE_STATUS_OUT_OF_RANGE 1u   /* an end point outside the output range */
+#define VOX_DEVICE_STATUS_CAPACITY 2u       /* voxel list larger than the capacity   */
+#define VOX_DEVICE_STATUS_MISMATCH 4u       /* batch scenes exceed the call's bounds */
+#define VOX_DEVICE_STATUS_INVALID 8u        /* a batch scene breaks an argument rule */
+
+/* Device address of the status word of a workspace (its first int32), for
+ * callers that read or copy it in stream order themselves (a graph, a
+ * serving loop copying it per batch).  0 after a call without device-found
+ * errors, else the VOX_DEVICE_STATUS_* bits; every call rewrites it.  No
+ * device access is made; NULL for NULL. */
+int32_t *vox_device_status(void *d_work);
+
+/* Synchronises `stream`, then reads from the workspace of the last
+ * vox_batch_scenes (or brick-path vox_segments_to_grid) call: *h_pieces, the
+ * piece records it needed, and *h_direct_all, 1 when they did not fit the
+ * workspace and the direct kernels served every scene (the output is the
+ * same; a workspace of the table and histogram part plus 16 bytes a record
+ * avoids it).  Either pointer may be NULL.  VOX_ERR_DEVICE if a HIP call
+ * fails. */
+vox_status vox_read_batch_info(const void *d_work, uint64_t *h_pieces, int32_t *h_direct_all, void *stream);
+
 /* Synchronises `stream`, then copies the device status word of d_work into
- * *h_status (a vox_status value).  Returns VOX_ERR_DEVICE if a HIP call
+ * *h_status as a vox_status value (MISMATCH before INVALID before
+ * OUT_OF_RANGE before CAPACITY).  Returns VOX_ERR_DEVICE if a HIP call
  * fails. */
 vox_status vox_read_status(const void *d_work, int32_t *h_status, void *stream);
 

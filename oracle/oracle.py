@@ -36,6 +36,19 @@ def compile_source(src: str, out: str) -> str:
     return out
 
 
+NATIVE_LIBRARY = os.path.join(_HERE, "liboracle_native.so")
+
+
+def compile_native(src: str, out: str) -> str:
+    """gcc -O2 -march=native: the same source tuned for the host it is built
+    on (the benchmark's CPU-baseline leg builds it where it runs)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-march=native", "-std=c99", "-Wall", "-Werror", "-shared",
+                           "-fPIC", "-o", tmp, src])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile vox_oracle.c into oracle/liboracle.so."""
     if force or not os.path.exists(LIBRARY) or \
@@ -205,6 +218,12 @@ class Oracle:
 
 
 _default = None
+
+
+def native() -> Oracle:
+    """The oracle built with -march=native on this host (for timing only;
+    always rebuilt, since the tree may have been built on another host)."""
+    return Oracle(compile_native(SOURCE, NATIVE_LIBRARY))
 
 
 def default() -> Oracle:

@@ -1,11 +1,14 @@
-"""Brick-shape autotuning for the grid and batch paths.
+"""Launch-shape autotuning for the grid and batch paths.
 
-The brick shape (LDS brick of 2^lx x 2^ly x 2^lz voxels) changes speed and
-workspace size, never the output.  `tune_grid` times every compiled shape on
-the caller's own segments and volume, keeps the fastest in a JSON cache keyed
-by device, volume and segment-count bucket, and makes it the process-wide
-tuning (vox_set_tuning); `apply` looks a configuration up in the cache
-without timing anything.
+A candidate is a brick shape (LDS brick of 2^lx x 2^ly x 2^lz voxels) with a
+number of fill workgroups per compute unit; it changes speed and workspace
+size, never the output.  `tune_grid` times every candidate on the caller's
+own segments and volume, each as a one-scene batch with its own per-call
+tuning (no process-wide state changes while timing), keeps the fastest in a
+JSON cache keyed by device, volume and segment-count bucket, and installs it
+in the library's autotune cache for that volume and count
+(vox_tuning_cache_set), which plain grid calls consult.  `apply` installs a
+cached choice without timing anything.
 """
 
 from __future__ import annotations
@@ -16,7 +19,9 @@ import os
 import tempfile
 import threading
 
-SHAPES = [(8, 6, 5), (8, 6, 6), (7, 6, 6), (7, 7, 6)]
+# (lx, ly, lz, fill workgroups per CU; 0 = the shape's default).
+CANDIDATES = [(8, 6, 5, 2), (8, 6, 5, 1), (8, 6, 6, 0), (7, 6, 6, 2), (7, 6, 6, 1), (7, 7, 6, 0)]
+SHAPES = sorted({c[:3] for c in CANDIDATES})
 
 _lock = threading.Lock()
 
@@ -36,8 +41,12 @@ def key(device: str, dims, n: int) -> str:
     return "%s|%dx%dx%d|n~2^%d" % (device, int(dims[0]), int(dims[1]), int(dims[2]), b)
 
 
+def _name(c) -> str:
+    return "%d,%d,%d,%d" % tuple(c)
+
+
 class TuneCache:
-    """JSON file {key: {"shape": [lx, ly, lz], "ms": {shape: ms}}}."""
+    """JSON file {key: {"candidate": [lx, ly, lz, wgs], "ms": {name: ms}}}."""
 
     def __init__(self, path: str | None = None):
         self.path = path or cache_path()
@@ -51,14 +60,14 @@ class TuneCache:
 
     def get(self, k: str):
         e = self.entries.get(k)
-        if not e:
+        if not isinstance(e, dict) or "candidate" not in e:
             return None
-        shape = tuple(int(v) for v in e["shape"])
-        return shape if shape in SHAPES else None
+        c = tuple(int(v) for v in e["candidate"])
+        return c if c in CANDIDATES else None
 
-    def put(self, k: str, shape, times: dict):
-        self.entries[k] = {"shape": list(shape),
-                           "ms": {"%d,%d,%d" % s: round(t, 5) for s, t in times.items()}}
+    def put(self, k: str, cand, times: dict):
+        self.entries[k] = {"candidate": list(cand),
+                           "ms": {_name(c): round(t, 5) for c, t in times.items()}}
 
     def save(self):
         d = os.path.dirname(self.path)
@@ -70,9 +79,14 @@ class TuneCache:
         os.replace(tmp, self.path)
 
 
-def best_shape(times: dict):
-    """Fastest shape; ties go to the earlier entry of SHAPES."""
-    return min(times, key=lambda s: (times[s], SHAPES.index(s)))
+def best_candidate(times: dict):
+    """Fastest candidate; ties go to the earlier entry of CANDIDATES."""
+    return min(times, key=lambda c: (times[c], CANDIDATES.index(c)))
+
+
+def tuning_of(cand):
+    from . import binding
+    return binding.make_tuning(cand[:3], cand[3])
 
 
 def device_name(device=None) -> str:
@@ -80,65 +94,69 @@ def device_name(device=None) -> str:
     return torch.cuda.get_device_name(device)
 
 
-def _time_shape(segs, dims, grid, shape, reps: int, stream) -> float:
+def _time_candidate(segs, dims, grid, cand, reps: int, stream) -> float:
+    """Mean ms of one cleared one-scene batch with this candidate's tuning
+    (a workspace big enough that the brick kernels serve the scene)."""
     import torch
     from . import binding
-    binding.vox_set_tuning(shape)
-    n = segs.shape[0]
-    work = binding.workspace(binding.vox_grid_workspace_bytes(n, dims), segs.device)
-    binding.vox_segments_to_grid(segs, dims, grid, None, binding.VOX_GRID_CLEAR, work,
-                                 stream=stream)
+    n = int(segs.shape[0])
+    tuning = tuning_of(cand)
+    d_scenes = torch.from_numpy(binding.scene_table([(segs, dims, grid, None, binding.VOX_GRID_CLEAR)])).to(
+        segs.device)
+    nbytes = binding.batch_workspace_bytes(n, 1)
+    work = binding.workspace(nbytes, segs.device)
+    binding.vox_batch_scenes(d_scenes, 1, n, work, tuning=tuning, stream=stream)
+    pieces, direct_all = binding.vox_read_batch_info(work, stream=stream)
+    if direct_all:  # records did not fit: give them room
+        work = binding.workspace(nbytes + 16 * pieces, segs.device)
+        binding.vox_batch_scenes(d_scenes, 1, n, work, tuning=tuning, stream=stream)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for _ in range(reps):
-        binding.vox_segments_to_grid(segs, dims, grid, None, binding.VOX_GRID_CLEAR, work,
-                                     stream=stream)
+        binding.vox_batch_scenes(d_scenes, 1, n, work, tuning=tuning, stream=stream)
     end.record(stream)
     end.synchronize()
     return start.elapsed_time(end) / reps
 
 
-def tune_grid(segs, dims, reps: int = 3, shapes=None, cache: TuneCache | None = None,
-              timer=None, device: str | None = None):
-    """Times each shape on (segs, dims) with a scratch volume, stores the
-    fastest in the cache, sets it as the process-wide tuning and returns
-    (shape, {shape: ms}).  `timer(shape) -> ms` replaces the GPU timing
-    (tests).  Plain calls of at most 16384 segments take the direct path,
-    where the shape changes nothing: tune with more segments than that."""
+def tune_grid(segs, dims, reps: int = 3, candidates=None, cache: TuneCache | None = None,
+              timer=None, device: str | None = None, install: bool = True):
+    """Times each candidate on (segs, dims) with a scratch volume, stores the
+    fastest in the cache and (install) in the library's cache for (dims,
+    n), and returns (candidate, {candidate: ms}).  `timer(candidate) -> ms`
+    replaces the GPU timing (tests).  Plain calls of at most 16384 segments
+    take the direct path, where the tuning changes nothing."""
     from . import binding
-    shapes = list(shapes or SHAPES)
+    cands = list(candidates or CANDIDATES)
     cache = cache if cache is not None else TuneCache()
     times = {}
     with _lock:
-        prev = binding.vox_get_tuning()
-        try:
-            if timer is None:
-                import torch
-                grid = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=segs.device)
-                stream = torch.cuda.current_stream(segs.device)
-                for s in shapes:
-                    times[s] = _time_shape(segs, dims, grid, s, reps, stream)
-                del grid
-            else:
-                for s in shapes:
-                    times[s] = float(timer(s))
-        finally:
-            binding.vox_set_tuning(prev if any(prev) else None)
-        best = best_shape(times)
+        if timer is None:
+            import torch
+            grid = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=segs.device)
+            stream = torch.cuda.current_stream(segs.device)
+            for c in cands:
+                times[c] = _time_candidate(segs, dims, grid, c, reps, stream)
+            del grid
+        else:
+            for c in cands:
+                times[c] = float(timer(c))
+        best = best_candidate(times)
         dev = device if device is not None else device_name(segs.device)
         cache.put(key(dev, dims, segs.shape[0]), best, times)
         cache.save()
-        binding.vox_set_tuning(best)
+        if install:
+            binding.vox_tuning_cache_set(dims, int(segs.shape[0]), tuning_of(best))
     return best, times
 
 
 def apply(dims, n: int, device: str, cache: TuneCache | None = None):
-    """Sets the cached shape for (device, dims, n) if there is one; returns
-    it (None: the library default stays)."""
+    """Installs the cached candidate for (device, dims, n) in the library's
+    cache if there is one; returns it (None: the library default stays)."""
     from . import binding
     cache = cache if cache is not None else TuneCache()
-    shape = cache.get(key(device, dims, n))
-    if shape is not None:
-        binding.vox_set_tuning(shape)
-    return shape
+    cand = cache.get(key(device, dims, n))
+    if cand is not None:
+        binding.vox_tuning_cache_set(dims, n, tuning_of(cand))
+    return cand

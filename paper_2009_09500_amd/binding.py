@@ -43,11 +43,21 @@ class VoxError(RuntimeError):
 
 class VoxTuning(ctypes.Structure):
     """struct vox_tuning of include/vox.h."""
-    _fields_ = [("brick_lg", ctypes.c_int32 * 3)]
+    _fields_ = [("brick_lg", ctypes.c_int32 * 3), ("fill_wgs_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+def make_tuning(brick_lg=None, fill_wgs_per_cu: int = 0) -> VoxTuning:
+    t = VoxTuning()
+    if brick_lg is not None:
+        for a in range(3):
+            t.brick_lg[a] = int(brick_lg[a])
+    t.fill_wgs_per_cu = int(fill_wgs_per_cu)
+    return t
 
 
 class VoxScene(ctypes.Structure):
-    """struct vox_scene of include/vox.h."""
+    """struct vox_scene of include/vox.h (48 bytes)."""
     _fields_ = [
         ("segs", ctypes.c_void_p),
         ("n", ctypes.c_int64),
@@ -60,22 +70,11 @@ class VoxScene(ctypes.Structure):
     ]
 
 
-class VoxBatchLaunch(ctypes.Structure):
-    """struct vox_batch_launch of include/vox.h."""
-    _fields_ = [
-        ("rows", ctypes.c_int64),
-        ("bricks", ctypes.c_int64),
-        ("brick_lg", ctypes.c_int32 * 3),
-        ("max_scene_bricks", ctypes.c_int32),
-        ("work_bytes", ctypes.c_uint64),
-        ("table_bytes", ctypes.c_uint64),
-    ]
-
-    def as_dict(self) -> dict:
-        return {"rows": int(self.rows), "bricks": int(self.bricks),
-                "brick_lg": tuple(int(v) for v in self.brick_lg),
-                "max_scene_bricks": int(self.max_scene_bricks),
-                "work_bytes": int(self.work_bytes), "table_bytes": int(self.table_bytes)}
+VOX_OP_BATCH = 3
+VOX_DEVICE_STATUS_OUT_OF_RANGE = 1
+VOX_DEVICE_STATUS_CAPACITY = 2
+VOX_DEVICE_STATUS_MISMATCH = 4
+VOX_DEVICE_STATUS_INVALID = 8
 
 
 def load(path: str | None = None):
@@ -113,19 +112,23 @@ def load(path: str | None = None):
     lib.vox_grid_workspace_bytes.restype = sz
     lib.vox_segments_to_grid.argtypes = [P, i64, i32, i32, i32, P, P, u32, P, sz, P]
     lib.vox_segments_to_grid.restype = ctypes.c_int
-    LP = ctypes.POINTER(VoxBatchLaunch)
-    lib.vox_batch_plan.argtypes = [ctypes.POINTER(VoxScene), i32, P, sz, LP]
-    lib.vox_batch_plan.restype = ctypes.c_int
-    lib.vox_batch_launch_cover.argtypes = [LP, LP]
-    lib.vox_batch_launch_cover.restype = ctypes.c_int
-    lib.vox_batch_scenes.argtypes = [P, LP, P, sz, P]
+    TP = ctypes.POINTER(VoxTuning)
+    lib.vox_workspace_bytes.argtypes = [ctypes.c_int, i64, i32]
+    lib.vox_workspace_bytes.restype = sz
+    lib.vox_batch_scenes.argtypes = [P, i32, i64, TP, P, sz, P]
     lib.vox_batch_scenes.restype = ctypes.c_int
+    lib.vox_device_status.argtypes = [P]
+    lib.vox_device_status.restype = ctypes.c_void_p
     lib.vox_read_status.argtypes = [P, ctypes.POINTER(i32), P]
     lib.vox_read_status.restype = ctypes.c_int
-    lib.vox_set_tuning.argtypes = [ctypes.POINTER(VoxTuning)]
-    lib.vox_set_tuning.restype = ctypes.c_int
-    lib.vox_get_tuning.argtypes = [ctypes.POINTER(VoxTuning)]
-    lib.vox_get_tuning.restype = ctypes.c_int
+    lib.vox_read_batch_info.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(i32), P]
+    lib.vox_read_batch_info.restype = ctypes.c_int
+    lib.vox_tuning_cache_set.argtypes = [i32, i32, i32, i64, TP]
+    lib.vox_tuning_cache_set.restype = ctypes.c_int
+    lib.vox_tuning_cache_get.argtypes = [i32, i32, i32, i64, TP, ctypes.POINTER(i32)]
+    lib.vox_tuning_cache_get.restype = ctypes.c_int
+    lib.vox_tuning_cache_clear.argtypes = []
+    lib.vox_tuning_cache_clear.restype = None
     lib.vox_profile_enable.argtypes = [ctypes.c_int]
     lib.vox_profile_enable.restype = ctypes.c_int
     lib.vox_profile_reset.argtypes = []
@@ -212,9 +215,11 @@ def vox_segments_to_grid(segs, dims, grid, counts, flags: int, work, stream=None
     _check(lib, st)
 
 
-def _scene_array(scenes):
-    """ctypes array of vox_scene from (segs, dims, grid, counts, flags) tuples
-    of device tensors (counts may be None)."""
+def scene_table(scenes):
+    """Host image (numpy uint8, 48 bytes a scene) of a vox_scene array from
+    (segs, dims, grid, counts, flags) tuples of device tensors (counts may be
+    None); copy it to device memory for vox_batch_scenes."""
+    import numpy as np
     arr = (VoxScene * len(scenes))()
     for i, (segs, dims, grid, counts, flags) in enumerate(scenes):
         _check_segs(segs)
@@ -225,37 +230,41 @@ def _scene_array(scenes):
         sc.flags = int(flags)
         sc.grid = grid.data_ptr()
         sc.counts = counts.data_ptr() if counts is not None else 0
-    return arr
+    return np.frombuffer(bytes(arr), dtype=np.uint8).copy()
 
 
-def vox_batch_plan(scenes):
-    """Plans a batch of (segs, dims, grid, counts, flags) scenes.  Returns
-    (table image as a numpy uint8 array, VoxBatchLaunch)."""
-    import numpy as np
+def vox_workspace_bytes(op: int, n_segments: int, n_scenes: int) -> int:
+    return int(load().vox_workspace_bytes(int(op), int(n_segments), int(n_scenes)))
+
+
+def batch_workspace_bytes(total_segments: int, n_scenes: int) -> int:
+    return vox_workspace_bytes(VOX_OP_BATCH, total_segments, n_scenes)
+
+
+def vox_batch_scenes(d_scenes, n_scenes: int, total_segments: int, work, tuning=None, stream=None):
+    """Calls vox_batch_scenes; d_scenes is a device uint8 tensor holding a
+    vox_scene array (scene_table), tuning a VoxTuning or None."""
     lib = load()
-    arr = _scene_array(scenes)
-    launch = VoxBatchLaunch()
-    _check(lib, lib.vox_batch_plan(arr, len(scenes), None, 0, ctypes.byref(launch)))
-    table = np.zeros(int(launch.table_bytes), dtype=np.uint8)
-    _check(lib, lib.vox_batch_plan(arr, len(scenes), ctypes.c_void_p(table.ctypes.data),
-                                   table.nbytes, ctypes.byref(launch)))
-    return table, launch
-
-
-def vox_batch_launch_cover(bound: VoxBatchLaunch, launch: VoxBatchLaunch) -> VoxBatchLaunch:
-    """Widens `bound` in place to cover `launch`; returns it."""
-    lib = load()
-    _check(lib, lib.vox_batch_launch_cover(ctypes.byref(bound), ctypes.byref(launch)))
-    return bound
-
-
-def vox_batch_scenes(d_table, launch: VoxBatchLaunch, work, stream=None):
-    """Runs a planned batch; d_table is a device uint8 tensor holding the
-    table image."""
-    lib = load()
-    st = lib.vox_batch_scenes(_ptr(d_table), ctypes.byref(launch), _ptr(work),
+    st = lib.vox_batch_scenes(_ptr(d_scenes), int(n_scenes), int(total_segments),
+                              ctypes.byref(tuning) if tuning is not None else None, _ptr(work),
                               work.numel() * work.element_size(), _stream(stream))
     _check(lib, st)
+
+
+def vox_read_batch_info(work, stream=None):
+    """(piece records needed, whether the direct kernels served every scene)
+    of the last brick-path call on `work` (synchronises)."""
+    lib = load()
+    pieces = ctypes.c_uint64(0)
+    direct_all = ctypes.c_int32(0)
+    _check(lib, lib.vox_read_batch_info(_ptr(work), ctypes.byref(pieces), ctypes.byref(direct_all),
+                                        _stream(stream)))
+    return int(pieces.value), bool(direct_all.value)
+
+
+def vox_device_status(work) -> int:
+    """Device address of the workspace's status word."""
+    return int(load().vox_device_status(_ptr(work)) or 0)
 
 
 def vox_read_status(work, stream=None) -> int:
@@ -265,23 +274,26 @@ def vox_read_status(work, stream=None) -> int:
     return int(out.value)
 
 
-def vox_set_tuning(brick_lg=None):
-    """Process-wide brick shape (log2 per axis) for grid calls; None = default."""
+def vox_tuning_cache_set(dims, n_segments: int, tuning):
+    """Autotune cache entry for (dims, n_segments); dims (0, 0, 0) keys
+    batches by their total segment count; tuning None removes it."""
     lib = load()
-    if brick_lg is None:
-        _check(lib, lib.vox_set_tuning(None))
-    else:
-        t = VoxTuning()
-        for a in range(3):
-            t.brick_lg[a] = int(brick_lg[a])
-        _check(lib, lib.vox_set_tuning(ctypes.byref(t)))
+    _check(lib, lib.vox_tuning_cache_set(*[int(d) for d in dims], int(n_segments),
+                                         ctypes.byref(tuning) if tuning is not None else None))
 
 
-def vox_get_tuning():
+def vox_tuning_cache_get(dims, n_segments: int):
+    """The cache entry as a VoxTuning, or None."""
     lib = load()
     t = VoxTuning()
-    _check(lib, lib.vox_get_tuning(ctypes.byref(t)))
-    return tuple(int(v) for v in t.brick_lg)
+    found = ctypes.c_int32(0)
+    _check(lib, lib.vox_tuning_cache_get(*[int(d) for d in dims], int(n_segments), ctypes.byref(t),
+                                         ctypes.byref(found)))
+    return t if found.value else None
+
+
+def vox_tuning_cache_clear():
+    load().vox_tuning_cache_clear()
 
 
 def vox_profile_enable(enable: bool = True):
@@ -356,7 +368,7 @@ def segments_to_grid(segs, dims, grid=None, want_counts: bool = False, stream=No
     return (grid, counts) if want_counts else grid
 
 
-def batch_to_grids(scenes, stream=None):
+def batch_to_grids(scenes, stream=None, tuning=None):
     """Cleared bit-volumes of several scenes in one batched launch sequence.
     `scenes` holds (segs, dims) pairs of device tensors; returns the grids
     (int32 storage of the packed words)."""
@@ -365,11 +377,11 @@ def batch_to_grids(scenes, stream=None):
         return []
     dev = scenes[0][0].device
     grids = [torch.empty(grid_words(d), dtype=torch.int32, device=dev) for _, d in scenes]
-    table, launch = vox_batch_plan([(s, d, g, None, VOX_GRID_CLEAR)
-                                    for (s, d), g in zip(scenes, grids)])
-    d_table = torch.from_numpy(table).to(dev)
-    work = workspace(launch.work_bytes, dev)
-    vox_batch_scenes(d_table, launch, work, stream=stream)
+    table = scene_table([(s, d, g, None, VOX_GRID_CLEAR) for (s, d), g in zip(scenes, grids)])
+    d_scenes = torch.from_numpy(table).to(dev)
+    total = sum(int(s.shape[0]) for s, _ in scenes)
+    work = workspace(batch_workspace_bytes(total, len(scenes)), dev)
+    vox_batch_scenes(d_scenes, len(scenes), total, work, tuning=tuning, stream=stream)
     status = vox_read_status(work, stream=stream)
     if status != VOX_OK:
         raise VoxError(status, load().vox_status_string(status).decode())

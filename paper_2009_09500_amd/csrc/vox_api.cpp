@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "vox.h"
@@ -15,8 +16,23 @@ namespace {
 
 thread_local char g_last_error[512] = "";
 
-std::mutex g_tuning_mu;
-vox_tuning g_tuning = {{0, 0, 0}};
+// Autotune cache: tuning per (volume, floor(log2 n)); dims 0 x 0 x 0 for
+// batches keyed by their total segment count.
+struct CacheKey {
+    int32_t dim[3];
+    int32_t lgn;
+    bool operator==(const CacheKey& o) const {
+        return dim[0] == o.dim[0] && dim[1] == o.dim[1] && dim[2] == o.dim[2] && lgn == o.lgn;
+    }
+};
+std::mutex g_cache_mu;
+std::vector<std::pair<CacheKey, vox::Tuning>> g_cache;
+
+CacheKey cache_key(int32_t dx, int32_t dy, int32_t dz, int64_t n) {
+    int32_t lgn = 0;
+    for (uint64_t v = n > 1 ? (uint64_t)n : 1u; v > 1; v >>= 1) ++lgn;
+    return CacheKey{{dx, dy, dz}, lgn};
+}
 
 vox_status fail(vox_status st, const char* fmt, ...) {
     va_list ap;
@@ -38,6 +54,8 @@ vox_status device_fail(hipError_t e, const char* where) {
 bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 constexpr int64_t kMaxDim = int64_t(1) << 20;
+constexpr int32_t kMaxBatchScenes = 65536;
+constexpr int64_t kMaxBatchSegments = int64_t(1) << 40;
 constexpr int64_t kMaxBits = int64_t(1) << 38;
 
 vox_status check_dims(int32_t dx, int32_t dy, int32_t dz) {
@@ -52,35 +70,96 @@ vox_status check_dims(int32_t dx, int32_t dy, int32_t dz) {
 }  // namespace
 
 namespace vox {
-void tuned_brick_lg(int lg[3]) {
-    std::lock_guard<std::mutex> lk(g_tuning_mu);
-    for (int a = 0; a < 3; ++a) lg[a] = g_tuning.brick_lg[a];
+
+int report_error(int status, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return status;
 }
+
+// A vox_tuning from the ABI: a supported shape (or all zero = the default of
+// the call), fill_wgs_per_cu 0, 1 or 2 (2 only for 64 KiB bricks), zero
+// reserved words.
+bool tuning_from_abi(const void* p, Tuning& t, char* why, size_t why_len) {
+    const vox_tuning& in = *static_cast<const vox_tuning*>(p);
+    for (int a = 0; a < 3; ++a) t.lg[a] = in.brick_lg[a];
+    t.fill_wgs_per_cu = in.fill_wgs_per_cu;
+    const bool zero = t.lg[0] == 0 && t.lg[1] == 0 && t.lg[2] == 0;
+    if (!zero && !brick_shape_supported(t.lg)) {
+        snprintf(why, why_len, "brick shape 2^%d x 2^%d x 2^%d has no compiled kernel", t.lg[0], t.lg[1], t.lg[2]);
+        return false;
+    }
+    const int bits = t.lg[0] + t.lg[1] + t.lg[2];
+    if (t.fill_wgs_per_cu < 0 || t.fill_wgs_per_cu > 2 || (t.fill_wgs_per_cu == 2 && !zero && bits >= 20)) {
+        snprintf(why, why_len, "fill_wgs_per_cu %d not available for this brick shape", t.fill_wgs_per_cu);
+        return false;
+    }
+    for (int i = 0; i < 4; ++i)
+        if (in.reserved[i] != 0) {
+            snprintf(why, why_len, "reserved tuning fields must be zero");
+            return false;
+        }
+    return true;
+}
+
+bool tuning_cache_lookup(int32_t dx, int32_t dy, int32_t dz, int64_t n, Tuning& t) {
+    const CacheKey k = cache_key(dx, dy, dz, n);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (const auto& e : g_cache)
+        if (e.first == k) {
+            t = e.second;
+            return t.lg[0] != 0;
+        }
+    return false;
+}
+
 }  // namespace vox
 
 extern "C" {
 
-vox_status vox_set_tuning(const vox_tuning* tuning) {
-    vox_tuning t = {{0, 0, 0}};
+vox_status vox_tuning_cache_set(int32_t dim_x, int32_t dim_y, int32_t dim_z, int64_t n_segments,
+                                const vox_tuning* tuning) {
+    if (n_segments < 0 || dim_x < 0 || dim_y < 0 || dim_z < 0)
+        return fail(VOX_ERR_INVALID_ARGUMENT, "negative key");
+    const CacheKey k = cache_key(dim_x, dim_y, dim_z, n_segments);
+    vox::Tuning t{};
     if (tuning) {
-        t = *tuning;
-        const bool zero = t.brick_lg[0] == 0 && t.brick_lg[1] == 0 && t.brick_lg[2] == 0;
-        if (!zero && !vox::brick_shape_supported(t.brick_lg))
-            return fail(VOX_ERR_INVALID_ARGUMENT, "brick shape 2^%d x 2^%d x 2^%d has no compiled kernel",
-                        t.brick_lg[0], t.brick_lg[1], t.brick_lg[2]);
+        char why[160];
+        if (!vox::tuning_from_abi(tuning, t, why, sizeof(why))) return fail(VOX_ERR_INVALID_ARGUMENT, "%s", why);
     }
-    std::lock_guard<std::mutex> lk(g_tuning_mu);
-    g_tuning = t;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (size_t i = 0; i < g_cache.size(); ++i)
+        if (g_cache[i].first == k) {
+            g_cache.erase(g_cache.begin() + (long)i);
+            break;
+        }
+    if (tuning) g_cache.emplace_back(k, t);
     return ok();
 }
 
-vox_status vox_get_tuning(vox_tuning* tuning) {
-    if (!tuning) return fail(VOX_ERR_INVALID_ARGUMENT, "NULL argument");
-    std::lock_guard<std::mutex> lk(g_tuning_mu);
-    *tuning = g_tuning;
+vox_status vox_tuning_cache_get(int32_t dim_x, int32_t dim_y, int32_t dim_z, int64_t n_segments,
+                                vox_tuning* tuning, int32_t* found) {
+    if (tuning == nullptr || found == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "NULL argument");
+    const CacheKey k = cache_key(dim_x, dim_y, dim_z, n_segments);
+    std::memset(tuning, 0, sizeof(*tuning));
+    *found = 0;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (const auto& e : g_cache)
+        if (e.first == k) {
+            for (int a = 0; a < 3; ++a) tuning->brick_lg[a] = e.second.lg[a];
+            tuning->fill_wgs_per_cu = e.second.fill_wgs_per_cu;
+            *found = 1;
+            break;
+        }
     return ok();
 }
 
+void vox_tuning_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.clear();
+}
 
 int vox_abi_version(void) { return VOX_ABI_VERSION; }
 
@@ -94,7 +173,7 @@ const char* vox_status_string(vox_status status) {
         case VOX_ERR_CAPACITY: return "voxel list exceeds capacity";
         case VOX_ERR_DEVICE: return "HIP runtime error";
         case VOX_ERR_WORKSPACE: return "workspace missing or too small";
-        case VOX_ERR_BATCH_MISMATCH: return "batch table does not fit its launch or workspace";
+        case VOX_ERR_BATCH_MISMATCH: return "batch scenes exceed the call's n_scenes or total_segments";
     }
     return "unknown status";
 }
@@ -233,123 +312,62 @@ vox_status vox_segments_to_grid(const vox_segment* d_segs, int64_t n, int32_t di
     return ok();
 }
 
-vox_status vox_batch_plan(const vox_scene* h_scenes, int32_t n_scenes, void* h_table, size_t h_table_bytes,
-                          vox_batch_launch* launch) {
-    if (launch == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "launch is NULL");
-    if (n_scenes < 1 || h_scenes == nullptr)
-        return fail(VOX_ERR_INVALID_ARGUMENT, "need h_scenes with n_scenes >= 1");
-    // Brick shape: the tuning if set, else the default of the largest volume.
-    int lg[3];
-    vox::tuned_brick_lg(lg);
-    if (lg[0] == 0) {
-        int64_t best = -1;
-        for (int32_t i = 0; i < n_scenes; ++i) {
-            const vox_scene& sc = h_scenes[i];
-            const int64_t v = (int64_t)sc.dim_x * sc.dim_y * sc.dim_z;
-            if (v > best) {
-                best = v;
-                vox::default_brick_lg(sc.dim_x, sc.dim_y, sc.dim_z, lg);
-            }
-        }
+size_t vox_workspace_bytes(int op, int64_t n_segments, int32_t n_scenes) {
+    if (n_segments < 0 || n_scenes < 1) return 0;
+    if (op == VOX_OP_BATCH) {
+        if (n_scenes > kMaxBatchScenes || n_segments > kMaxBatchSegments) return 0;
+        const int lg[3] = {8, 6, 5};
+        const vox::BrickLaunch L = vox::batch_launch((uint32_t)n_scenes, (uint64_t)n_segments, lg);
+        return vox::batch_fixed_bytes(L) +
+               (size_t)((uint64_t)n_segments * vox::kDefaultPiecesPerSegment * vox::kRecordBytes);
     }
-    std::vector<vox::BrickScene> scenes((size_t)n_scenes);
-    for (int32_t i = 0; i < n_scenes; ++i) {
-        const vox_scene& in = h_scenes[i];
-        if (in.n < 0 || in.n > (int64_t(1) << 31) - 2)
-            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: n must lie in [0, 2^31 - 2]", i);
-        if (in.n > 0 && in.segs == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: segs is NULL", i);
-        if (in.segs && !aligned(in.segs, 8))
-            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: segs not 8-byte aligned", i);
-        if (check_dims(in.dim_x, in.dim_y, in.dim_z) != VOX_OK)
-            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: %s", i, g_last_error);
-        if (in.grid == nullptr || !aligned(in.grid, 16))
-            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: grid NULL or not 16-byte aligned", i);
-        if (in.counts && !aligned(in.counts, 4))
-            return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: counts not 4-byte aligned", i);
-        if (in.flags & ~VOX_GRID_CLEAR) return fail(VOX_ERR_INVALID_ARGUMENT, "scene %d: unknown flag bits", i);
-        vox::BrickScene& sc = scenes[(size_t)i];
-        if (!vox::brick_geometry_for(in.dim_x, in.dim_y, in.dim_z, lg, sc.bg))
-            return fail(VOX_ERR_INVALID_ARGUMENT,
-                        "scene %d: volume %d x %d x %d cannot take bricks of 2^%d x 2^%d x 2^%d (dim_x a multiple "
-                        "of 32, sides <= 16384, <= 16384 bricks)",
-                        i, in.dim_x, in.dim_y, in.dim_z, lg[0], lg[1], lg[2]);
-        sc.segs = reinterpret_cast<const int32_t*>(in.segs);
-        sc.counts = in.counts;
-        sc.grid = in.grid;
-        sc.n = in.n;
-        sc.flags = (in.flags & VOX_GRID_CLEAR) ? vox::kSceneClear : 0u;
-    }
-    vox::BrickTable t{};
-    for (int a = 0; a < 3; ++a) t.lg[a] = lg[a];
-    if (!vox::brick_table_layout(t, scenes.data(), (uint32_t)n_scenes))
-        return fail(VOX_ERR_INVALID_ARGUMENT, "batch too large: more than 2^32 - 1 bricks or pieces");
-    launch->rows = t.rows;
-    launch->bricks = t.bricks;
-    for (int a = 0; a < 3; ++a) launch->brick_lg[a] = lg[a];
-    launch->max_scene_bricks = (int32_t)t.max_nb;
-    launch->work_bytes = t.work_bytes;
-    launch->table_bytes = t.table_bytes;
-    if (h_table == nullptr) return ok();
-    if (h_table_bytes < t.table_bytes)
-        return fail(VOX_ERR_INVALID_ARGUMENT, "h_table holds %zu bytes, the table needs %llu", h_table_bytes,
-                    (unsigned long long)t.table_bytes);
-    uint8_t* out = static_cast<uint8_t*>(h_table);
-    std::memset(out, 0, (size_t)t.table_bytes);
-    std::memcpy(out, &t, sizeof(t));
-    std::memcpy(out + vox::kTableScenes, scenes.data(), scenes.size() * sizeof(vox::BrickScene));
-    if (n_scenes > 1) {
-        uint32_t* row_scene = reinterpret_cast<uint32_t*>(out + vox::kTableScenes +
-                                                          scenes.size() * sizeof(vox::BrickScene));
-        uint32_t* brick_scene = row_scene + t.rows;
-        for (int32_t i = 0; i < n_scenes; ++i) {
-            const vox::BrickScene& sc = scenes[(size_t)i];
-            for (uint32_t r = 0; r < sc.rows; ++r) row_scene[sc.row_base + r] = (uint32_t)i;
-            for (uint32_t b = 0; b < sc.bg.nbricks; ++b) brick_scene[sc.brick_base + b] = (uint32_t)i;
-        }
-    }
-    return ok();
+    return 0;
 }
 
-vox_status vox_batch_launch_cover(vox_batch_launch* bound, const vox_batch_launch* launch) {
-    if (bound == nullptr || launch == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "NULL argument");
-    const bool empty = bound->brick_lg[0] == 0 && bound->brick_lg[1] == 0 && bound->brick_lg[2] == 0;
-    if (!empty && (bound->brick_lg[0] != launch->brick_lg[0] || bound->brick_lg[1] != launch->brick_lg[1] ||
-                   bound->brick_lg[2] != launch->brick_lg[2]))
-        return fail(VOX_ERR_INVALID_ARGUMENT, "brick shapes differ");
-    for (int a = 0; a < 3; ++a) bound->brick_lg[a] = launch->brick_lg[a];
-    if (launch->rows > bound->rows) bound->rows = launch->rows;
-    if (launch->bricks > bound->bricks) bound->bricks = launch->bricks;
-    if (launch->max_scene_bricks > bound->max_scene_bricks) bound->max_scene_bricks = launch->max_scene_bricks;
-    if (launch->work_bytes > bound->work_bytes) bound->work_bytes = launch->work_bytes;
-    if (launch->table_bytes > bound->table_bytes) bound->table_bytes = launch->table_bytes;
-    return ok();
-}
-
-vox_status vox_batch_scenes(const void* d_table, const vox_batch_launch* launch, void* d_work, size_t work_bytes,
-                            void* stream) {
-    if (d_table == nullptr || !aligned(d_table, 16))
-        return fail(VOX_ERR_INVALID_ARGUMENT, "d_table NULL or not 16-byte aligned");
-    if (launch == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "launch is NULL");
-    if (launch->rows < 1 || launch->rows >= (int64_t(1) << 31) || launch->bricks < 1 ||
-        launch->bricks >= 0xFFFFFFFFll || launch->max_scene_bricks < 1 ||
-        launch->max_scene_bricks > (int32_t)vox::kMaxBricks)
-        return fail(VOX_ERR_INVALID_ARGUMENT, "launch sizes out of range (use vox_batch_plan)");
-    if (!vox::brick_shape_supported(launch->brick_lg))
-        return fail(VOX_ERR_INVALID_ARGUMENT, "brick shape 2^%d x 2^%d x 2^%d has no compiled kernel",
-                    launch->brick_lg[0], launch->brick_lg[1], launch->brick_lg[2]);
+vox_status vox_batch_scenes(const vox_scene* d_scenes, int32_t n_scenes, int64_t total_segments,
+                            const vox_tuning* tuning, void* d_work, size_t work_bytes, void* stream) {
+    if (d_scenes == nullptr || !aligned(d_scenes, 8))
+        return fail(VOX_ERR_INVALID_ARGUMENT, "d_scenes NULL or not 8-byte aligned");
+    if (n_scenes < 1 || n_scenes > kMaxBatchScenes)
+        return fail(VOX_ERR_INVALID_ARGUMENT, "n_scenes must lie in [1, %d]", kMaxBatchScenes);
+    if (total_segments < 0 || total_segments > kMaxBatchSegments)
+        return fail(VOX_ERR_INVALID_ARGUMENT, "total_segments must lie in [0, 2^40]");
+    vox::Tuning t{};
+    if (tuning) {
+        char why[160];
+        if (!vox::tuning_from_abi(tuning, t, why, sizeof(why))) return fail(VOX_ERR_INVALID_ARGUMENT, "%s", why);
+    } else if (!vox::tuning_cache_lookup(0, 0, 0, total_segments, t)) {
+        t = vox::Tuning{};
+    }
+    if (t.lg[0] == 0) {
+        // Default: 64 KiB bricks, which cover volumes of up to 16384 bricks.
+        t.lg[0] = 8;
+        t.lg[1] = 6;
+        t.lg[2] = 5;
+    }
     if (d_work == nullptr || !aligned(d_work, vox::kAlign))
         return fail(VOX_ERR_WORKSPACE, "d_work NULL or not 256-byte aligned");
-    if (work_bytes < launch->work_bytes)
-        return fail(VOX_ERR_WORKSPACE, "workspace %zu bytes, the launch needs %llu", work_bytes,
-                    (unsigned long long)launch->work_bytes);
-    vox::BrickLaunch L;
-    L.rows = (uint32_t)launch->rows;
-    L.bricks = (uint32_t)launch->bricks;
-    for (int a = 0; a < 3; ++a) L.lg[a] = launch->brick_lg[a];
-    L.max_nb = (uint32_t)launch->max_scene_bricks;
-    hipError_t e = vox::launch_bricks(d_table, L, nullptr, nullptr, d_work, work_bytes,
+    const vox::BrickLaunch L = vox::batch_launch((uint32_t)n_scenes, (uint64_t)total_segments, t.lg);
+    const size_t need = vox::batch_fixed_bytes(L);
+    if (work_bytes < need)
+        return fail(VOX_ERR_WORKSPACE, "workspace %zu bytes, the table and histograms need %zu", work_bytes, need);
+    hipError_t e = vox::launch_bricks(d_scenes, nullptr, L, t.fill_wgs_per_cu, d_work, work_bytes,
                                       static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_fail(e, "batch");
+    return ok();
+}
+
+int32_t* vox_device_status(void* d_work) { return static_cast<int32_t*>(d_work); }
+
+vox_status vox_read_batch_info(const void* d_work, uint64_t* h_pieces, int32_t* h_direct_all, void* stream) {
+    if (d_work == nullptr) return fail(VOX_ERR_INVALID_ARGUMENT, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t hdr[vox::kWPieces + 2];
+    hipError_t e = hipMemcpyAsync(hdr, d_work, sizeof(hdr), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "read batch info");
+    if (h_pieces) *h_pieces = (uint64_t)hdr[vox::kWPieces] | ((uint64_t)hdr[vox::kWPieces + 1] << 32);
+    if (h_direct_all) *h_direct_all = hdr[vox::kWDirectAll] ? 1 : 0;
     return ok();
 }
 
@@ -362,6 +380,7 @@ vox_status vox_read_status(const void* d_work, int32_t* h_status, void* stream) 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(e, "read status");
     if (raw & vox::kStatusLaunch) *h_status = VOX_ERR_BATCH_MISMATCH;
+    else if (raw & vox::kStatusInvalid) *h_status = VOX_ERR_INVALID_ARGUMENT;
     else if (raw & vox::kStatusOutOfRange) *h_status = VOX_ERR_OUT_OF_RANGE;
     else if (raw & vox::kStatusCapacity) *h_status = VOX_ERR_CAPACITY;
     else *h_status = VOX_OK;

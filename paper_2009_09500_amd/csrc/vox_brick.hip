@@ -12,26 +12,33 @@
 // coordinate crosses a brick boundary (exact helpers in vox_exact.h).
 //
 // Every kernel reads its volumes from a scene table (BrickTable followed by
-// BrickScene entries): a plain call is a table of one scene, written into
-// the workspace by the init kernel; a batch is a table of many scenes built
-// on the host, whose bricks and histogram rows are numbered globally so that
-// each kernel below is still one launch for the whole batch.
+// BrickScene entries) that the plan kernel writes into the workspace from
+// the caller's vox_scene entries: a plain call is a table of one scene, a
+// batch a table of many, whose bricks and histogram rows are numbered
+// globally so that each kernel below is still one launch for the whole batch.
 //
 // Pipeline (one stream, no host synchronisation, no allocation):
-//   init      status word and work counter to zero; checks that the table
-//             fits the launch and the workspace
+//   plan      checks every scene, decides brick or direct kernels per scene,
+//             numbers rows and bricks (block scans), writes the table, the
+//             status word and the brick queues
+//   expand    scene of each histogram row and brick (several scenes only)
 //   hist      per segment: count N+1, range check, walk its bricks and count
 //             pieces per brick in an LDS histogram; one histogram row per
 //             workgroup
 //   colscan   per brick, exclusive prefix of the rows over workgroups, and
 //             the brick's piece total
-//   base      exclusive scan of the brick totals -> bin offsets
+//   base      exclusive scan of the brick totals -> bin offsets; if the
+//             records do not fit the workspace, the direct kernels take over
 //   scatter   the same walk again, writing one 16-byte piece record (start
 //             point, direction, k-window in the brick) into the brick's bin
-//   fill      persistent workgroups take bricks from an atomic counter, set
-//             the bits of every piece with LDS atomic OR and flush the brick
-//             to the volume
+//   fill      persistent workgroups take bricks from work-stealing queues,
+//             set the bits of every piece with LDS atomic OR and flush the
+//             brick to the volume
+//   direct    (batches) clear, then one device atomic per voxel, for the
+//             scenes the bricks do not serve
+#include "vox.h"
 #include "vox_device.h"
+#include "vox_direct.h"
 #include "vox_exact.h"
 #include "vox_internal.h"
 
@@ -89,57 +96,69 @@ struct Piece {
 };
 static_assert(sizeof(Piece) == 16, "16-byte piece records");
 
-// Sections of the workspace (layout in vox_internal.h).
+// Sections of the workspace: the header words, the table the plan kernel
+// writes at kWorkTable, then at the table's data_off the histograms, the
+// brick totals, the bin offsets and the piece records (the rest of the
+// workspace).
 struct WorkView {
     int32_t* status;
     uint32_t* counter;   // [kXcds] brick queues of the fill, one per XCD
     uint32_t* ok;
+    uint32_t* direct_all;
+    uint64_t* pieces;
     uint32_t* hist;
     uint32_t* totals;
     uint32_t* bin_base;
     Piece* recs;
+    uint64_t rec_off;    // byte offset of the records
 };
 
-__host__ __device__ inline WorkView work_view(uint8_t* work, uint64_t hist_words, uint32_t bricks) {
+__host__ __device__ inline WorkView work_view(uint8_t* work, uint64_t data_off, uint64_t hist_words,
+                                              uint32_t bricks) {
     WorkView v;
-    v.status = reinterpret_cast<int32_t*>(work);
-    v.counter = reinterpret_cast<uint32_t*>(work + 16);
-    v.ok = reinterpret_cast<uint32_t*>(work + 8);
-    uint8_t* p = work + kWorkData;
-    v.hist = reinterpret_cast<uint32_t*>(p);
-    p += up256(hist_words * 4u);
-    v.totals = reinterpret_cast<uint32_t*>(p);
-    p += up256((uint64_t)bricks * 4u);
-    v.bin_base = reinterpret_cast<uint32_t*>(p);
-    p += up256(((uint64_t)bricks + 1u) * 4u);
-    v.recs = reinterpret_cast<Piece*>(p);
+    uint32_t* w = reinterpret_cast<uint32_t*>(work);
+    v.status = reinterpret_cast<int32_t*>(work) + kWStatus;
+    v.counter = w + kWQueues;
+    v.ok = w + kWOk;
+    v.direct_all = w + kWDirectAll;
+    v.pieces = reinterpret_cast<uint64_t*>(w + kWPieces);
+    uint64_t off = data_off;
+    v.hist = reinterpret_cast<uint32_t*>(work + off);
+    off += up256(hist_words * 4u);
+    v.totals = reinterpret_cast<uint32_t*>(work + off);
+    off += up256((uint64_t)bricks * 4u);
+    v.bin_base = reinterpret_cast<uint32_t*>(work + off);
+    off += up256(((uint64_t)bricks + 1u) * 4u);
+    v.recs = reinterpret_cast<Piece*>(work + off);
+    v.rec_off = off;
     return v;
-}
-
-size_t brick_work_bytes(uint64_t hist_words, uint32_t bricks, uint64_t pieces) {
-    return (size_t)(kWorkData + up256(hist_words * 4u) + up256((uint64_t)bricks * 4u) +
-                    up256(((uint64_t)bricks + 1u) * 4u) + pieces * sizeof(Piece));
 }
 
 // The scene table as the kernels see it.
 struct TableView {
     BrickTable h;
     const BrickScene* scenes;
+    const uint32_t* direct;       // the direct scenes, in order
     const uint32_t* row_scene;    // null with one scene
     const uint32_t* brick_scene;  // null with one scene
 };
 
-__device__ __forceinline__ TableView table_view(const uint8_t* table) {
+__host__ __device__ __forceinline__ TableView table_view(const uint8_t* table) {
     TableView v;
     v.h = *reinterpret_cast<const BrickTable*>(table);
     v.scenes = reinterpret_cast<const BrickScene*>(table + kTableScenes);
+    v.direct = reinterpret_cast<const uint32_t*>(v.scenes + v.h.n_scenes);
     if (v.h.n_scenes > 1) {
-        v.row_scene = reinterpret_cast<const uint32_t*>(v.scenes + v.h.n_scenes);
-        v.brick_scene = v.row_scene + v.h.rows;
+        v.row_scene = v.direct + v.h.n_scenes;
+        v.brick_scene = v.row_scene + v.h.row_cap;
     } else {
         v.row_scene = v.brick_scene = nullptr;
     }
     return v;
+}
+
+__device__ __forceinline__ WorkView work_of(uint8_t* work, const TableView& tv) {
+    return work_view(work, tv.h.data_off, tv.h.hist_words, tv.h.bricks);
 }
 
 // Brick queues of the fill.  The 8 XCDs of the chip each have their own L2;
@@ -171,26 +190,112 @@ __device__ __forceinline__ uint32_t xcd_row(uint32_t w, uint32_t G) {
     return start + a;
 }
 
-// Status word, brick queues and the launch check: the table must come from
-// the planner, fit the launch bounds the kernels were sized for, and fit the
-// workspace; otherwise every later kernel returns at once and the status
-// says so.  A plain call passes its one-scene table by value and it is
-// written into the workspace here.
-__global__ void k_brick_init(BrickTable one_t, BrickScene one_s, uint32_t has_one, const uint8_t* table,
-                             uint8_t* work, uint64_t work_bytes, BrickLaunch L) {
-    if (threadIdx.x != 0) return;
-    if (has_one) {
-        *reinterpret_cast<BrickTable*>(work + kWorkTable) = one_t;
-        *reinterpret_cast<BrickScene*>(work + kWorkTable + kTableScenes) = one_s;
+constexpr int kPlanBlock = 1024;
+
+// The plan: one block reads the caller's scenes (the device vox_scene array,
+// or the one scene of a plain call passed by value), checks each against the
+// argument rules, decides which scenes the brick kernels serve (8-byte-aligned
+// segment arrays, the Chebyshev N, volumes the bricks cover) and which the
+// direct kernels serve, numbers the histogram rows and bricks of all brick
+// scenes (block scans), and writes the table, the status word, the brick
+// queues and the flags.  A scene that breaks a rule, or scenes beyond the
+// launch bounds, stop the whole call (nothing is written).  When the
+// histograms and brick offsets do not fit the workspace, the direct kernels
+// serve every scene.
+__global__ __launch_bounds__(kPlanBlock) void k_brick_plan(const vox_scene* __restrict__ scenes, vox_scene one,
+                                                           uint32_t has_one, BrickLaunch L, uint8_t* __restrict__ work,
+                                                           uint64_t work_bytes) {
+    __shared__ uint32_t scan32[kPlanBlock / kWave];
+    __shared__ uint64_t scan64[kPlanBlock / kWave];
+    __shared__ uint32_t bad_s, max_nb_s;
+    uint8_t* tb = work + kWorkTable;
+    BrickScene* out = reinterpret_cast<BrickScene*>(tb + kTableScenes);
+    uint32_t* direct = reinterpret_cast<uint32_t*>(out + L.n_scenes);
+    if (threadIdx.x == 0) {
+        bad_s = 0;
+        max_nb_s = 0;
     }
-    const BrickTable t = has_one ? one_t : *reinterpret_cast<const BrickTable*>(table);
-    const bool ok = t.magic == kTableMagic && t.n_scenes >= 1 && t.rows <= L.rows && t.bricks <= L.bricks &&
-                    t.max_nb <= L.max_nb && t.lg[0] == L.lg[0] && t.lg[1] == L.lg[1] && t.lg[2] == L.lg[2] &&
-                    t.work_bytes <= work_bytes;
-    int32_t* w = reinterpret_cast<int32_t*>(work);
-    w[0] = ok ? 0 : kStatusLaunch;  // status
-    w[2] = ok ? 1 : 0;              // launch ok
-    for (int x = 0; x < kXcds; ++x) w[4 + x] = 0;  // brick queues
+    __syncthreads();
+    uint32_t rows_c = 0, bricks_c = 0, direct_c = 0;
+    uint64_t hist_c = 0, segs_c = 0, dsegs_c = 0;
+    for (uint32_t c0 = 0; c0 < L.n_scenes; c0 += kPlanBlock) {
+        const uint32_t i = c0 + threadIdx.x;
+        BrickScene b{};
+        uint32_t rows = 0, nb = 0, isd = 0;
+        uint64_t hist = 0, n = 0;
+        if (i < L.n_scenes) {
+            const vox_scene in = has_one ? one : scenes[i];
+            if (!plan_scene(in, L.lg, b)) atomicOr(&bad_s, 1u);
+            isd = (b.flags & kSceneDirect) ? 1u : 0u;
+            rows = b.rows;
+            nb = isd ? 0u : b.bg.nbricks;
+            hist = (uint64_t)rows * nb;
+            n = b.n > 0 ? (uint64_t)b.n : 0u;
+            atomicMax(&max_nb_s, nb);
+        }
+        uint32_t t_rows, t_nb, t_d;
+        uint64_t t_hist, t_n, t_dn;
+        const uint32_t x_rows = block_exclusive_sum<kPlanBlock>(rows, scan32, t_rows);
+        const uint32_t x_nb = block_exclusive_sum<kPlanBlock>(nb, scan32, t_nb);
+        const uint32_t x_d = block_exclusive_sum<kPlanBlock>(isd, scan32, t_d);
+        const uint64_t x_hist = block_exclusive_sum<kPlanBlock>(hist, scan64, t_hist);
+        (void)block_exclusive_sum<kPlanBlock>(n, scan64, t_n);
+        (void)block_exclusive_sum<kPlanBlock>(isd ? n : 0u, scan64, t_dn);
+        if (i < L.n_scenes) {
+            b.row_base = rows_c + x_rows;
+            b.brick_base = bricks_c + x_nb;
+            b.hist_off = hist_c + x_hist;
+            out[i] = b;
+            if (isd) direct[direct_c + x_d] = i;
+        }
+        rows_c += t_rows;
+        bricks_c += t_nb;
+        direct_c += t_d;
+        hist_c += t_hist;
+        segs_c += t_n;
+        dsegs_c += t_dn;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    BrickTable t{};
+    t.magic = kTableMagic;
+    t.n_scenes = L.n_scenes;
+    t.rows = rows_c;
+    t.bricks = bricks_c;
+    for (int a = 0; a < 3; ++a) t.lg[a] = L.lg[a];
+    t.max_nb = max_nb_s;
+    t.hist_words = hist_c;
+    t.data_off = kWorkTable + L.table_bytes;
+    t.n_direct = direct_c;
+    t.row_cap = L.rows;
+    t.direct_segs = dsegs_c;
+    *reinterpret_cast<BrickTable*>(tb) = t;
+    const bool fits = segs_c <= L.total_segments && rows_c <= L.rows && bricks_c <= L.bricks;
+    const WorkView wv = work_view(work, t.data_off, t.hist_words, t.bricks);
+    const bool room = wv.rec_off <= work_bytes;
+    uint32_t* w = reinterpret_cast<uint32_t*>(work);
+    const int32_t st = bad_s ? kStatusInvalid : (fits ? 0 : kStatusLaunch);
+    w[kWStatus] = (uint32_t)st;
+    w[kWOk] = (st == 0 && room && bricks_c > 0) ? 1u : 0u;
+    w[kWDirectAll] = room ? 0u : 1u;
+    for (int x = 0; x < kXcds; ++x) w[kWQueues + x] = 0u;
+    *wv.pieces = 0;
+}
+
+// Scene of every histogram row and of every brick (tables of several
+// scenes); workgroups take scenes in turn.
+__global__ __launch_bounds__(256) void k_brick_expand(uint8_t* __restrict__ work) {
+    const uint8_t* tb = work + kWorkTable;
+    const TableView tv = table_view(tb);
+    if (reinterpret_cast<const uint32_t*>(work)[kWOk] == 0 || tv.row_scene == nullptr) return;
+    uint32_t* row_scene = const_cast<uint32_t*>(tv.row_scene);
+    uint32_t* brick_scene = const_cast<uint32_t*>(tv.brick_scene);
+    for (uint32_t s = blockIdx.x; s < tv.h.n_scenes; s += gridDim.x) {
+        const BrickScene& sc = tv.scenes[s];
+        if (sc.flags & kSceneDirect) continue;
+        for (uint32_t r = threadIdx.x; r < sc.rows; r += blockDim.x) row_scene[sc.row_base + r] = s;
+        for (uint32_t b = threadIdx.x; b < sc.bg.nbricks; b += blockDim.x) brick_scene[sc.brick_base + b] = s;
+    }
 }
 
 // Segment range of histogram/scatter workgroup g.
@@ -346,19 +451,12 @@ __device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeo
     }
 }
 
+// Histogram of one row: its segments' pieces per brick of its scene.
 template <int kN>
-__global__ __launch_bounds__(kHistBlock) void k_brick_hist(const uint8_t* __restrict__ table,
-                                                           uint8_t* __restrict__ work) {
-    extern __shared__ uint32_t lh[];
-    __shared__ Stage<kN> st;
-    const TableView tv = table_view(table);
-    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
-    const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
-    if (*wv.ok == 0 || r >= tv.h.rows) return;
-    const BrickScene sc = tv.scenes[tv.row_scene ? tv.row_scene[r] : 0u];
+__device__ __forceinline__ void hist_row(const BrickScene& sc, uint32_t g, Stage<kN>& st, uint32_t* lh,
+                                         const WorkView& wv) {
     const BrickGeom& bg = sc.bg;
     const uint32_t NB = bg.nbricks;
-    const uint32_t g = r - sc.row_base;
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) lh[b] = 0;
     int64_t lo, hi;
     seg_range(sc.n, (int)g, (int)sc.rows, lo, hi);
@@ -375,91 +473,124 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_hist(const uint8_t* __rest
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) row[b] = lh[b];
 }
 
+// LDS of the histogram kernel: 8 192 staged segments and up to 8 192 brick
+// counters, or 4 096 staged segments and up to 16 384 counters; each
+// workgroup takes the layout its scene's brick count allows.
+constexpr size_t kHistLdsBig = sizeof(Stage<kStageBig>) + (size_t)kBigStageBricks * 4;
+constexpr size_t kHistLdsSmall = sizeof(Stage<kStage>) + (size_t)kMaxBricks * 4;
+constexpr size_t kHistLds = kHistLdsBig > kHistLdsSmall ? kHistLdsBig : kHistLdsSmall;
+static_assert(kHistLds <= 163840, "histogram LDS fits a workgroup");
+
+__global__ __launch_bounds__(kHistBlock) void k_brick_hist(uint8_t* __restrict__ work) {
+    extern __shared__ __align__(16) uint8_t hist_lds[];
+    const TableView tv = table_view(work + kWorkTable);
+    const WorkView wv = work_of(work, tv);
+    const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
+    if (*wv.ok == 0 || r >= tv.h.rows) return;
+    const BrickScene sc = tv.scenes[tv.row_scene ? tv.row_scene[r] : 0u];
+    const uint32_t g = r - sc.row_base;
+    if (sc.bg.nbricks <= kBigStageBricks) {
+        auto* st = reinterpret_cast<Stage<kStageBig>*>(hist_lds);
+        hist_row(sc, g, *st, reinterpret_cast<uint32_t*>(hist_lds + sizeof(Stage<kStageBig>)), wv);
+    } else {
+        auto* st = reinterpret_cast<Stage<kStage>*>(hist_lds);
+        hist_row(sc, g, *st, reinterpret_cast<uint32_t*>(hist_lds + sizeof(Stage<kStage>)), wv);
+    }
+}
+
 constexpr int kColBins = 64;
 constexpr int kColSplit = 4;  // row chunks per brick
 constexpr int kColRows = (kHistRows + kColSplit - 1) / kColSplit;
+constexpr uint32_t kColMaxBlocks = 4096;
 
-// Block of 256 threads = 64 global bricks x 4 row chunks: per brick,
-// exclusive prefix of its scene's histogram column over the scene's rows
-// (in place) and the brick total.
-__global__ __launch_bounds__(256) void k_brick_colscan(const uint8_t* __restrict__ table,
-                                                       uint8_t* __restrict__ work) {
+// Blocks of 256 threads = 64 global bricks x 4 row chunks (the blocks step
+// over all bricks): per brick, exclusive prefix of its scene's histogram
+// column over the scene's rows (in place) and the brick total.
+__global__ __launch_bounds__(256) void k_brick_colscan(uint8_t* __restrict__ work) {
     __shared__ uint32_t part[kColSplit][kColBins];
-    const TableView tv = table_view(table);
-    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
+    const TableView tv = table_view(work + kWorkTable);
+    const WorkView wv = work_of(work, tv);
     if (*wv.ok == 0) return;
     const int bl = threadIdx.x % kColBins;
     const int ch = threadIdx.x / kColBins;
-    const uint32_t gb = blockIdx.x * kColBins + bl;
-    const bool valid = gb < tv.h.bricks;
-    uint32_t b = 0, NB = 0;
-    int G = 0;
-    uint64_t off = 0;
-    if (valid) {
-        const BrickScene& sc = tv.scenes[tv.brick_scene ? tv.brick_scene[gb] : 0u];
-        b = gb - sc.brick_base;
-        NB = sc.bg.nbricks;
-        G = (int)sc.rows;
-        off = sc.hist_off;
-    }
-    uint32_t* hist = wv.hist + off;
-    const int g0 = ch * kColRows;
-    uint32_t v[kColRows];
-    uint32_t sum = 0;
+    for (uint32_t gb0 = blockIdx.x * kColBins; gb0 < tv.h.bricks; gb0 += gridDim.x * kColBins) {
+        const uint32_t gb = gb0 + bl;
+        const bool valid = gb < tv.h.bricks;
+        uint32_t b = 0, NB = 0;
+        int G = 0;
+        uint64_t off = 0;
+        if (valid) {
+            const BrickScene& sc = tv.scenes[tv.brick_scene ? tv.brick_scene[gb] : 0u];
+            b = gb - sc.brick_base;
+            NB = sc.bg.nbricks;
+            G = (int)sc.rows;
+            off = sc.hist_off;
+        }
+        uint32_t* hist = wv.hist + off;
+        const int g0 = ch * kColRows;
+        uint32_t v[kColRows];
+        uint32_t sum = 0;
 #pragma unroll
-    for (int r = 0; r < kColRows; ++r) {
-        const int g = g0 + r;
-        v[r] = (valid && g < G) ? hist[(size_t)g * NB + b] : 0u;
-        sum += v[r];
-    }
-    part[ch][bl] = sum;
-    __syncthreads();
-    uint32_t run = 0, tot = 0;
+        for (int r = 0; r < kColRows; ++r) {
+            const int g = g0 + r;
+            v[r] = (valid && g < G) ? hist[(size_t)g * NB + b] : 0u;
+            sum += v[r];
+        }
+        part[ch][bl] = sum;
+        __syncthreads();
+        uint32_t run = 0, tot = 0;
 #pragma unroll
-    for (int c = 0; c < kColSplit; ++c) {
-        run += c < ch ? part[c][bl] : 0u;
-        tot += part[c][bl];
-    }
+        for (int c = 0; c < kColSplit; ++c) {
+            run += c < ch ? part[c][bl] : 0u;
+            tot += part[c][bl];
+        }
 #pragma unroll
-    for (int r = 0; r < kColRows; ++r) {
-        const int g = g0 + r;
-        if (valid && g < G) hist[(size_t)g * NB + b] = run;
-        run += v[r];
+        for (int r = 0; r < kColRows; ++r) {
+            const int g = g0 + r;
+            if (valid && g < G) hist[(size_t)g * NB + b] = run;
+            run += v[r];
+        }
+        if (ch == 0 && valid) wv.totals[gb] = tot;
+        __syncthreads();
     }
-    if (ch == 0 && valid) wv.totals[gb] = tot;
 }
 
 constexpr int kBaseBlock = 1024;
 
 // One block: bin_base[b] = sum of totals before global brick b;
-// bin_base[bricks] = total.
-__global__ __launch_bounds__(kBaseBlock) void k_brick_base(const uint8_t* __restrict__ table,
-                                                           uint8_t* __restrict__ work) {
+// bin_base[bricks] = total.  When the records do not fit the rest of the
+// workspace (or their count reaches 2^32 - 1), the direct kernels serve
+// every scene instead of the scatter and the fill.
+__global__ __launch_bounds__(kBaseBlock) void k_brick_base(uint8_t* __restrict__ work, uint64_t work_bytes) {
     __shared__ uint32_t lds[kBaseBlock / kWave];
-    const TableView tv = table_view(table);
-    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
+    const TableView tv = table_view(work + kWorkTable);
+    const WorkView wv = work_of(work, tv);
     if (*wv.ok == 0) return;
     const uint32_t NB = tv.h.bricks;
-    uint32_t carry = 0;
+    uint64_t carry = 0;
     for (uint32_t c0 = 0; c0 < NB; c0 += kBaseBlock) {
         const uint32_t i = c0 + threadIdx.x;
         const uint32_t v = i < NB ? wv.totals[i] : 0u;
         uint32_t tot;
         const uint32_t ex = block_exclusive_sum<kBaseBlock>(v, lds, tot);
-        if (i < NB) wv.bin_base[i] = carry + ex;
+        if (i < NB) wv.bin_base[i] = (uint32_t)carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) wv.bin_base[NB] = carry;
+    if (threadIdx.x == 0) {
+        wv.bin_base[NB] = (uint32_t)carry;
+        *wv.pieces = carry;
+        const uint64_t cap = work_bytes > wv.rec_off ? (work_bytes - wv.rec_off) / sizeof(Piece) : 0u;
+        if (carry > cap || carry >= 0xFFFFFFFFull) *wv.direct_all = 1u;
+    }
 }
 
-__global__ __launch_bounds__(kHistBlock) void k_brick_scatter(const uint8_t* __restrict__ table,
-                                                              uint8_t* __restrict__ work) {
+__global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restrict__ work) {
     extern __shared__ uint32_t cur[];
     __shared__ Stage<kStage> st;
-    const TableView tv = table_view(table);
-    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
+    const TableView tv = table_view(work + kWorkTable);
+    const WorkView wv = work_of(work, tv);
     const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
-    if (*wv.ok == 0 || r >= tv.h.rows) return;
+    if (*wv.ok == 0 || *wv.direct_all != 0 || r >= tv.h.rows) return;
     const BrickScene sc = tv.scenes[tv.row_scene ? tv.row_scene[r] : 0u];
     const BrickGeom& bg = sc.bg;
     const uint32_t NB = bg.nbricks;
@@ -631,6 +762,17 @@ __device__ __forceinline__ void run_chunk(uint32_t* brick, const Digest& g, uint
     }
 }
 
+// Voxels of a piece record (its k-window klo | khi << 16).  A piece lies in
+// one brick and its dominant coordinate moves by one voxel per k, so it has
+// at most as many voxels as the brick's longest side; a record outside that
+// (which the scatter never writes) counts as empty, so that every loop of
+// the fill stays bounded whatever the workspace holds.
+template <int kMaxLg>
+__device__ __forceinline__ uint32_t record_length(uint32_t w) {
+    const uint32_t klo = w & 0xFFFFu, khi = w >> 16;
+    return (khi >= klo && khi - klo < (1u << kMaxLg)) ? khi - klo + 1u : 0u;
+}
+
 // A piece record, read once: a non-temporal load, so that the stream of
 // records does not push the volume's partly written lines out of the L2.
 __device__ __forceinline__ u32x4 load_stream(const u32x4* p) {
@@ -673,7 +815,7 @@ constexpr int kSets = 2;  // piece records per lane in a wave group
 // loaded while the current ones run.
 template <int LGX, int LGY, int LGZ>
 __global__ __launch_bounds__((FillCfg<LGX, LGY, LGZ>::kBlock), (FillCfg<LGX, LGY, LGZ>::kWgsPerCu))
-void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work) {
+void k_brick_fill(uint8_t* __restrict__ work) {
     using Shape = BrickShape<LGX, LGY, LGZ>;
     using Cfg = FillCfg<LGX, LGY, LGZ>;
     constexpr int kBlock = Cfg::kBlock, kChunk = Cfg::kChunk;
@@ -696,9 +838,9 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
     __shared__ uint32_t cursor_s[kQuarters];  // per-SIMD record cursors of the brick
     __shared__ uint32_t next_s[3];
 
-    const TableView tv = table_view(table);
-    const WorkView wv = work_view(work, tv.h.hist_words, tv.h.bricks);
-    if (*wv.ok == 0) return;
+    const TableView tv = table_view(work + kWorkTable);
+    const WorkView wv = work_of(work, tv);
+    if (*wv.ok == 0 || *wv.direct_all != 0) return;
     const uint32_t NB = tv.h.bricks;  // global bricks of all scenes
     uint32_t* __restrict__ work_counter = wv.counter;
     const uint32_t* __restrict__ bin_base = wv.bin_base;
@@ -771,8 +913,8 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
         u32x4 rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
         while (gbase < q_hi) {
             const u32x4 r0 = rn0, r1 = rn1;
-            const uint32_t len0 = gbase + lane < q_hi ? (r0.w >> 16) - (r0.w & 0xFFFFu) + 1u : 0u;
-            const uint32_t len1 = gbase + kWave + lane < q_hi ? (r1.w >> 16) - (r1.w & 0xFFFFu) + 1u : 0u;
+            const uint32_t len0 = gbase + lane < q_hi ? record_length<Shape::kMaxLg>(r0.w) : 0u;
+            const uint32_t len1 = gbase + kWave + lane < q_hi ? record_length<Shape::kMaxLg>(r1.w) : 0u;
             // The records have arrived (len0/len1 are made from them); the next
             // group's loads are issued only now, so no later wait for these
             // records waits for them too.
@@ -878,8 +1020,9 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
 
         // Flush: brick rows -> volume words, zeroing the brick on the way.
         // The owner writes every word of its brick, so a clearing call needs
-        // no other pass.
-        const int rows = ext[1] * ext[2];
+        // no other pass.  A brick with no pieces in a scene that ORs into its
+        // volume changes nothing: no flush (its LDS copy is still zero).
+        const int rows = (clear || p_lo != p_hi) ? ext[1] * ext[2] : 0;
         // Whole 16-byte units when the volume's rows hold whole brick rows.
         const bool vec = Shape::kBXw % 4 == 0 && (bg.dim[0] & ((1 << LGX) - 1)) == 0;
         const bool full_y = ext[1] == (1 << LGY);  // rows per slab a power of two
@@ -955,6 +1098,66 @@ void k_brick_fill(const uint8_t* __restrict__ table, uint8_t* __restrict__ work)
     }
 }
 
+// ------------------------------------------------------- direct scenes
+
+constexpr int kDirectBlock = 256;
+
+// The scenes the direct kernels serve: those the brick path does not take
+// (flagged by the plan), or every scene when the records did not fit.
+// Nothing runs after a failed plan.
+__device__ __forceinline__ bool direct_scenes(const uint8_t* work, const TableView& tv, uint32_t& count,
+                                              bool& all) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(work);
+    if (w[kWStatus] & (uint32_t)(kStatusInvalid | kStatusLaunch)) return false;
+    all = w[kWDirectAll] != 0;
+    count = all ? tv.h.n_scenes : tv.h.n_direct;
+    return count > 0;
+}
+
+// Zeroes the volumes of the cleared direct scenes.
+__global__ __launch_bounds__(kDirectBlock) void k_batch_direct_clear(uint8_t* __restrict__ work) {
+    const TableView tv = table_view(work + kWorkTable);
+    uint32_t nd;
+    bool all;
+    if (!direct_scenes(work, tv, nd, all)) return;
+    const int64_t t0 = (int64_t)blockIdx.x * kDirectBlock + threadIdx.x;
+    const int64_t ts = (int64_t)gridDim.x * kDirectBlock;
+    for (uint32_t j = 0; j < nd; ++j) {
+        const BrickScene& sc = tv.scenes[all ? j : tv.direct[j]];
+        if (!(sc.flags & kSceneClear)) continue;
+        const int64_t nwords = ((int64_t)sc.bg.dim[0] * sc.bg.dim[1] * sc.bg.dim[2] + 31) / 32;
+        clear_words(sc.grid, nwords, t0, ts);
+    }
+}
+
+// The segments of the direct scenes, one device atomic per voxel
+// (direct_segments, vox_direct.h).
+__global__ __launch_bounds__(kDirectBlock) void k_batch_direct(uint8_t* __restrict__ work) {
+    const TableView tv = table_view(work + kWorkTable);
+    uint32_t nd;
+    bool all;
+    if (!direct_scenes(work, tv, nd, all)) return;
+    int32_t* status = reinterpret_cast<int32_t*>(work) + kWStatus;
+    const int64_t wave0 = (int64_t)blockIdx.x * (kDirectBlock / kWave) + threadIdx.x / kWave;
+    const int64_t ws = (int64_t)gridDim.x * (kDirectBlock / kWave);
+    for (uint32_t j = 0; j < nd; ++j) {
+        const BrickScene sc = tv.scenes[all ? j : tv.direct[j]];
+        const int32_t dx = sc.bg.dim[0], dy = sc.bg.dim[1], dz = sc.bg.dim[2];
+        const bool a8 = (sc.flags & kSceneA8) != 0;
+        if (sc.flags & kSceneEuclid) {
+            if (a8)
+                direct_segments<true, true>(sc.segs, sc.n, dx, dy, dz, sc.grid, sc.counts, status, wave0, ws);
+            else
+                direct_segments<false, true>(sc.segs, sc.n, dx, dy, dz, sc.grid, sc.counts, status, wave0, ws);
+        } else {
+            if (a8)
+                direct_segments<true, false>(sc.segs, sc.n, dx, dy, dz, sc.grid, sc.counts, status, wave0, ws);
+            else
+                direct_segments<false, false>(sc.segs, sc.n, dx, dy, dz, sc.grid, sc.counts, status, wave0, ws);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- host side
 
 // Brick shapes with a compiled fill kernel.
@@ -986,44 +1189,52 @@ uint64_t max_pieces(int64_t n, const BrickGeom& bg) {
     return (uint64_t)n * (uint64_t)(1 + (bg.nb[0] - 1) + (bg.nb[1] - 1) + (bg.nb[2] - 1));
 }
 
-int hist_rows(int64_t n) {
-    int64_t g = (n + kSegsPerRow - 1) / kSegsPerRow;
-    if (g > kHistRows) g = kHistRows;
-    if (g < 1) g = 1;
-    return (int)g;
+static uint64_t table_bytes(uint32_t n_scenes, uint32_t rows, uint32_t bricks) {
+    uint64_t b = kTableScenes + (uint64_t)n_scenes * (sizeof(BrickScene) + 4u);
+    if (n_scenes > 1) b += 4ull * ((uint64_t)rows + bricks);
+    return up256(b);
 }
 
-bool brick_table_layout(BrickTable& t, BrickScene* scenes, uint32_t n_scenes) {
-    uint64_t rows = 0, bricks = 0, hist = 0, pieces = 0;
-    uint32_t max_nb = 0;
-    for (uint32_t i = 0; i < n_scenes; ++i) {
-        BrickScene& sc = scenes[i];
-        sc.rows = (uint32_t)hist_rows(sc.n);
-        sc.row_base = (uint32_t)rows;
-        sc.brick_base = (uint32_t)bricks;
-        sc.hist_off = hist;
-        rows += sc.rows;
-        bricks += sc.bg.nbricks;
-        hist += (uint64_t)sc.rows * sc.bg.nbricks;
-        pieces += max_pieces(sc.n, sc.bg);
-        max_nb = sc.bg.nbricks > max_nb ? sc.bg.nbricks : max_nb;
-        if (rows >= (1u << 31) || bricks >= 0xFFFFFFFFull || pieces >= 0xFFFFFFFFull) return false;
-    }
-    t.magic = kTableMagic;
-    t.n_scenes = n_scenes;
-    t.rows = (uint32_t)rows;
-    t.bricks = (uint32_t)bricks;
-    t.max_nb = max_nb;
-    t.hist_words = hist;
-    t.pieces = pieces;
-    t.work_bytes = brick_work_bytes(hist, (uint32_t)bricks, pieces);
-    t.table_bytes = kTableScenes + (uint64_t)n_scenes * sizeof(BrickScene) +
-                    (n_scenes > 1 ? 4u * (rows + bricks) : 0u);
-    return true;
+BrickLaunch batch_launch(uint32_t n_scenes, uint64_t total_segments, const int lg[3]) {
+    BrickLaunch L;
+    L.n_scenes = n_scenes;
+    L.total_segments = total_segments;
+    // Rows of scene s: min(256, max(1, ceil(n_s / 4096))) <= 1 + n_s / 4096.
+    uint64_t rows = (uint64_t)n_scenes + (total_segments + kSegsPerRow - 1) / kSegsPerRow;
+    const uint64_t rmax = (uint64_t)n_scenes * kHistRows;
+    L.rows = (uint32_t)(rows < rmax ? rows : rmax);
+    L.bricks = (uint32_t)((uint64_t)n_scenes * kMaxBricks);
+    for (int a = 0; a < 3; ++a) L.lg[a] = lg[a];
+    L.table_bytes = table_bytes(n_scenes, L.rows, L.bricks);
+    L.direct_kernels = true;
+    return L;
+}
+
+// Table, histograms (each scene's rows times at most kMaxBricks bricks),
+// brick totals and offsets.
+size_t batch_fixed_bytes(const BrickLaunch& L) {
+    return (size_t)(kWorkTable + L.table_bytes + up256((uint64_t)L.rows * kMaxBricks * 4u) +
+                    up256((uint64_t)L.bricks * 4u) + up256(((uint64_t)L.bricks + 1u) * 4u));
+}
+
+BrickLaunch plain_launch(int64_t n, const BrickGeom& bg) {
+    BrickLaunch L;
+    L.n_scenes = 1;
+    L.total_segments = (uint64_t)n;
+    L.rows = hist_rows(n);
+    L.bricks = bg.nbricks;
+    for (int a = 0; a < 3; ++a) L.lg[a] = bg.lg[a];
+    L.table_bytes = table_bytes(1, L.rows, L.bricks);
+    // The caller's workspace holds the worst case of records.
+    L.direct_kernels = false;
+    return L;
 }
 
 size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg) {
-    return brick_work_bytes((uint64_t)hist_rows(n) * bg.nbricks, bg.nbricks, max_pieces(n, bg));
+    const BrickLaunch L = plain_launch(n, bg);
+    return (size_t)(kWorkTable + L.table_bytes + up256((uint64_t)L.rows * bg.nbricks * 4u) +
+                    up256((uint64_t)L.bricks * 4u) + up256(((uint64_t)L.bricks + 1u) * 4u) +
+                    max_pieces(n, bg) * sizeof(Piece));
 }
 
 static int device_cus() {
@@ -1034,103 +1245,91 @@ static int device_cus() {
     return cus;
 }
 
+// Persistent fill workgroups: wgs_per_cu per compute unit (at most the
+// shape's default, which its LDS allows).
 template <int LGX, int LGY, int LGZ>
-static hipError_t launch_fill(const uint8_t* table, uint8_t* work, uint32_t bricks, hipStream_t stream) {
+static hipError_t launch_fill(uint8_t* work, int wgs_per_cu, hipStream_t stream) {
     constexpr int kBlock = FillCfg<LGX, LGY, LGZ>::kBlock;
-    int wgs = device_cus() * FillCfg<LGX, LGY, LGZ>::kWgsPerCu;
-    if ((uint32_t)wgs > bricks) wgs = (int)bricks;
-    k_brick_fill<LGX, LGY, LGZ><<<wgs, kBlock, 0, stream>>>(table, work);
+    constexpr int kMax = FillCfg<LGX, LGY, LGZ>::kWgsPerCu;
+    const int per = wgs_per_cu >= 1 && wgs_per_cu <= kMax ? wgs_per_cu : kMax;
+    const int wgs = device_cus() * per;
+    k_brick_fill<LGX, LGY, LGZ><<<wgs, kBlock, 0, stream>>>(work);
     return hipGetLastError();
 }
 
-hipError_t launch_bricks(const void* d_table, const BrickLaunch& L, const BrickTable* one_table,
-                         const BrickScene* one_scene, void* d_work, size_t work_bytes, hipStream_t stream) {
-    if (L.rows < 1 || L.bricks < 1 || L.max_nb < 1 || L.max_nb > kMaxBricks || !brick_shape_supported(L.lg))
-        return hipErrorInvalidValue;
+hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunch& L, int fill_wgs_per_cu,
+                         void* d_work, size_t work_bytes, hipStream_t stream) {
+    if (L.n_scenes < 1 || L.rows < 1 || L.bricks < 1 || !brick_shape_supported(L.lg)) return hipErrorInvalidValue;
     uint8_t* work = static_cast<uint8_t*>(d_work);
-    const bool one = one_table != nullptr && one_scene != nullptr;
-    const uint8_t* table = one ? work + kWorkTable : static_cast<const uint8_t*>(d_table);
     hipError_t e;
     {
-        // The histogram kernels may use up to 64 KiB of dynamic LDS (the
-        // histogram with big stages: what its stage leaves).
         static hipError_t attr = [] {
-            const void* ks[2] = {(const void*)k_brick_hist<kStage>, (const void*)k_brick_scatter};
-            for (const void* k : ks) {
-                hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)(kMaxBricks * sizeof(uint32_t)));
-                if (r != hipSuccess) return r;
-            }
-            return hipFuncSetAttribute((const void*)k_brick_hist<kStageBig>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(kBigStageBricks * sizeof(uint32_t)));
+            hipError_t r = hipFuncSetAttribute((const void*)k_brick_hist, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)kHistLds);
+            if (r != hipSuccess) return r;
+            return hipFuncSetAttribute((const void*)k_brick_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kMaxBricks * sizeof(uint32_t)));
         }();
         if (attr != hipSuccess) return attr;
     }
     {
-        KernelTimer t("brick_init", stream);
-        BrickTable ot{};
-        BrickScene os{};
-        if (one) {
-            ot = *one_table;
-            os = *one_scene;
-        }
-        k_brick_init<<<1, 64, 0, stream>>>(ot, os, one ? 1u : 0u, table, work, (uint64_t)work_bytes, L);
+        KernelTimer t("brick_plan", stream);
+        vox_scene os{};
+        if (one) os = *static_cast<const vox_scene*>(one);
+        k_brick_plan<<<1, kPlanBlock, 0, stream>>>(static_cast<const vox_scene*>(d_scenes), os, one ? 1u : 0u, L,
+                                                   work, (uint64_t)work_bytes);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t hist_lds = (size_t)L.max_nb * sizeof(uint32_t);
+    if (L.n_scenes > 1) {
+        KernelTimer t("brick_expand", stream);
+        const uint32_t wgs = L.n_scenes < 2048u ? L.n_scenes : 2048u;
+        k_brick_expand<<<wgs, 256, 0, stream>>>(work);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     {
         KernelTimer t("brick_hist", stream);
-        if (L.max_nb <= kBigStageBricks)
-            k_brick_hist<kStageBig><<<L.rows, kHistBlock, hist_lds, stream>>>(table, work);
-        else
-            k_brick_hist<kStage><<<L.rows, kHistBlock, hist_lds, stream>>>(table, work);
+        k_brick_hist<<<L.rows, kHistBlock, kHistLds, stream>>>(work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         KernelTimer t("brick_colscan", stream);
-        k_brick_colscan<<<(L.bricks + kColBins - 1) / kColBins, 256, 0, stream>>>(table, work);
+        uint32_t blocks = (L.bricks + kColBins - 1) / kColBins;
+        if (blocks > kColMaxBlocks) blocks = kColMaxBlocks;
+        k_brick_colscan<<<blocks, 256, 0, stream>>>(work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         KernelTimer t("brick_base", stream);
-        k_brick_base<<<1, kBaseBlock, 0, stream>>>(table, work);
+        k_brick_base<<<1, kBaseBlock, 0, stream>>>(work, (uint64_t)work_bytes);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         KernelTimer t("brick_scatter", stream);
-        k_brick_scatter<<<L.rows, kHistBlock, hist_lds, stream>>>(table, work);
+        const size_t scatter_lds = (size_t)(L.n_scenes > 1 ? kMaxBricks : L.bricks) * sizeof(uint32_t);
+        k_brick_scatter<<<L.rows, kHistBlock, scatter_lds, stream>>>(work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-
-    KernelTimer t("brick_fill", stream);
-    const int* lg = L.lg;
-    if (lg[0] == 8 && lg[1] == 6 && lg[2] == 5) return launch_fill<8, 6, 5>(table, work, L.bricks, stream);
-    if (lg[0] == 8 && lg[1] == 6 && lg[2] == 6) return launch_fill<8, 6, 6>(table, work, L.bricks, stream);
-    if (lg[0] == 7 && lg[1] == 6 && lg[2] == 6) return launch_fill<7, 6, 6>(table, work, L.bricks, stream);
-    if (lg[0] == 7 && lg[1] == 7 && lg[2] == 6) return launch_fill<7, 7, 6>(table, work, L.bricks, stream);
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_brick_grid(const int32_t* segs, int64_t n, const BrickGeom& bg,
-                             uint32_t* grid, int32_t* counts, uint32_t flags, void* d_work,
-                             size_t work_bytes, hipStream_t stream) {
-    BrickTable t{};
-    BrickScene sc{};
-    sc.segs = segs;
-    sc.counts = counts;
-    sc.grid = grid;
-    sc.n = n;
-    sc.bg = bg;
-    sc.flags = (flags & 1u) ? kSceneClear : 0u;
-    for (int a = 0; a < 3; ++a) t.lg[a] = bg.lg[a];
-    if (!brick_table_layout(t, &sc, 1)) return hipErrorInvalidValue;
-    BrickLaunch L;
-    L.rows = t.rows;
-    L.bricks = t.bricks;
-    for (int a = 0; a < 3; ++a) L.lg[a] = bg.lg[a];
-    L.max_nb = t.max_nb;
-    return launch_bricks(nullptr, L, &t, &sc, d_work, work_bytes, stream);
+    {
+        KernelTimer t("brick_fill", stream);
+        const int* lg = L.lg;
+        if (lg[0] == 8 && lg[1] == 6 && lg[2] == 5) e = launch_fill<8, 6, 5>(work, fill_wgs_per_cu, stream);
+        else if (lg[0] == 8 && lg[1] == 6 && lg[2] == 6) e = launch_fill<8, 6, 6>(work, fill_wgs_per_cu, stream);
+        else if (lg[0] == 7 && lg[1] == 6 && lg[2] == 6) e = launch_fill<7, 6, 6>(work, fill_wgs_per_cu, stream);
+        else if (lg[0] == 7 && lg[1] == 7 && lg[2] == 6) e = launch_fill<7, 7, 6>(work, fill_wgs_per_cu, stream);
+        else e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    if (L.direct_kernels) {
+        {
+            KernelTimer t("batch_direct_clear", stream);
+            k_batch_direct_clear<<<2048, kDirectBlock, 0, stream>>>(work);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        KernelTimer t("batch_direct", stream);
+        k_batch_direct<<<4096, kDirectBlock, 0, stream>>>(work);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace vox

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vox.h"
 #include "vox_device.h"
 #include "vox_internal.h"
 
@@ -201,7 +202,8 @@ __host__ __device__ __forceinline__ void box_window(const SegAxes& s, const int3
 // Brick decomposition of a dx*dy*dz volume into bricks of 2^lg voxels per
 // axis; false when the brick path cannot serve it (rows not whole words, or
 // more bricks than one LDS histogram holds).
-inline bool brick_geometry(int32_t dx, int32_t dy, int32_t dz, const int lg[3], BrickGeom& bg) {
+__host__ __device__ inline bool brick_geometry(int32_t dx, int32_t dy, int32_t dz, const int lg[3],
+                                               BrickGeom& bg) {
     // Rows of whole words; end points of staged segments and pieces are
     // 16-bit.
     if (dx % 32 != 0 || lg[0] < 5 || dx > 16384 || dy > 16384 || dz > 16384) return false;
@@ -216,6 +218,56 @@ inline bool brick_geometry(int32_t dx, int32_t dy, int32_t dz, const int lg[3], 
     if (nb > (uint64_t)kMaxBricks) return false;
     bg.nbricks = (uint32_t)nb;
     return true;
+}
+
+
+// The argument rules of a bit-volume scene (those of vox_segments_to_grid):
+// n in [0, 2^31 - 2], segs non-null when n > 0 and 4-byte aligned, each side
+// in [1, 2^20] with at most 2^38 voxels, grid non-null and 16-byte aligned,
+// counts 4-byte aligned, flags within VOX_GRID_CLEAR | VOX_GRID_EUCLID.
+__host__ __device__ inline bool scene_valid(const vox_scene& in) {
+    const uintptr_t segs = (uintptr_t)in.segs, grid = (uintptr_t)in.grid, counts = (uintptr_t)in.counts;
+    if (in.n < 0 || in.n > (int64_t(1) << 31) - 2) return false;
+    if (in.n > 0 && segs == 0) return false;
+    if ((segs & 3u) != 0 || grid == 0 || (grid & 15u) != 0 || (counts & 3u) != 0) return false;
+    const int64_t lim = int64_t(1) << 20;
+    if (in.dim_x < 1 || in.dim_y < 1 || in.dim_z < 1 || in.dim_x > lim || in.dim_y > lim || in.dim_z > lim)
+        return false;
+    if ((int64_t)in.dim_x * in.dim_y * in.dim_z > (int64_t(1) << 38)) return false;
+    return (in.flags & ~(uint32_t)(VOX_GRID_CLEAR | VOX_GRID_EUCLID)) == 0;
+}
+
+// One scene of a launch, as the plan kernel enters it in the table (bases
+// left zero): the brick path serves it when its segment array is 8-byte
+// aligned, it uses the Chebyshev N and its volume takes bricks of 2^lg;
+// otherwise it is flagged for the direct kernels.  False (and a direct entry
+// with no segments) when the scene breaks an argument rule.
+__host__ __device__ inline bool plan_scene(const vox_scene& in, const int32_t lg[3], BrickScene& out) {
+    const bool valid = scene_valid(in);
+    out = BrickScene{};
+    out.segs = reinterpret_cast<const int32_t*>(in.segs);
+    out.counts = in.counts;
+    out.grid = in.grid;
+    out.n = valid ? in.n : 0;
+    out.bg.dim[0] = in.dim_x;
+    out.bg.dim[1] = in.dim_y;
+    out.bg.dim[2] = in.dim_z;
+    uint32_t f = 0;
+    if (in.flags & VOX_GRID_CLEAR) f |= kSceneClear;
+    if (in.flags & VOX_GRID_EUCLID) f |= kSceneEuclid;
+    if (((uintptr_t)in.segs & 7u) == 0) f |= kSceneA8;
+    const int lgi[3] = {lg[0], lg[1], lg[2]};
+    BrickGeom bg;
+    if (valid && (f & kSceneA8) && !(f & kSceneEuclid) && brick_geometry(in.dim_x, in.dim_y, in.dim_z, lgi, bg)) {
+        out.bg = bg;
+        out.rows = hist_rows(in.n);
+    } else {
+        f |= kSceneDirect;
+        out.rows = 0;
+        out.bg.nbricks = 0;
+    }
+    out.flags = f;
+    return valid;
 }
 
 }  // namespace vox

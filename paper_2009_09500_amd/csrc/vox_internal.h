@@ -12,7 +12,8 @@ namespace vox {
 // the set bits onto a vox_status code.
 constexpr int32_t kStatusOutOfRange = 1;
 constexpr int32_t kStatusCapacity = 2;
-constexpr int32_t kStatusLaunch = 4;  // batch table does not fit the launch or workspace
+constexpr int32_t kStatusLaunch = 4;  // batch scenes exceed the launch bounds (n_scenes / total_segments)
+constexpr int32_t kStatusInvalid = 8; // a batch scene breaks an argument rule
 
 // Scoped kernel timer: records HIP events on `stream` around the launch
 // made inside its scope when kernel timing is enabled (vox_profile_enable);
@@ -29,6 +30,10 @@ class KernelTimer {
     hipStream_t stream_;
     hipEvent_t start_ = nullptr;
 };
+
+// Sets the calling thread's last-error message (vox_last_error) and returns
+// `status` (a vox_status value).
+int report_error(int status, const char* fmt, ...);
 
 // Workspace sections are 256-byte aligned.
 constexpr size_t kAlign = 256;
@@ -101,80 +106,100 @@ constexpr int kHistBlock = 1024;
 constexpr int kHistRows = 256;
 constexpr int64_t kSegsPerRow = 4096;   // segments staged per histogram round
 
-// One volume of a brick-path launch, as the kernels read it from the
-// device scene table.
+// One volume of a launch as the kernels read it from the device scene table
+// (written by the plan kernel from the caller's vox_scene entries).
 struct BrickScene {
-    const int32_t* segs;   // [n][6], 8-byte aligned
+    const int32_t* segs;   // [n][6]
     int32_t* counts;       // [n] or null
     uint32_t* grid;        // packed bit-volume
     int64_t n;
-    uint64_t hist_off;     // this scene's histogram rows, in words
-    BrickGeom bg;
+    uint64_t hist_off;     // brick scenes: histogram rows, in words; direct scenes: first segment
+                           // among the direct scenes' segments
+    BrickGeom bg;          // brick scenes only (dim[] always)
     uint32_t brick_base;   // global id of the scene's first brick
     uint32_t row_base;     // global index of its first histogram row
-    uint32_t rows;         // histogram rows (workgroups) of the scene
-    uint32_t flags;        // kSceneClear
+    uint32_t rows;         // histogram rows (workgroups) of the scene; 0 for a direct scene
+    uint32_t flags;        // kScene*
 };
-constexpr uint32_t kSceneClear = 1;
+constexpr uint32_t kSceneClear = 1;    // zero the volume first
+constexpr uint32_t kSceneDirect = 2;   // the direct kernels serve this scene (no bricks)
+constexpr uint32_t kSceneEuclid = 4;   // Euclidean N of eq. (1) (direct kernels only)
+constexpr uint32_t kSceneA8 = 8;       // segment array 8-byte aligned
 
-// Device scene table: this header, BrickScene[n_scenes] at kTableScenes,
-// then (several scenes only) uint32 row_scene[rows] and uint32
-// brick_scene[bricks], the scene of each histogram row and of each global
-// brick.  Position independent: the host builds it, any copy works.
+// Device scene table, written into the workspace by the plan kernel: this
+// header, BrickScene[n_scenes] at kTableScenes, then uint32 direct[n_scenes]
+// (the direct scenes in order), and with several scenes uint32
+// row_scene[rows bound] and uint32 brick_scene[bricks bound]: the scene of
+// each histogram row and of each global brick.
 struct BrickTable {
     uint32_t magic;
     uint32_t n_scenes;
-    uint32_t rows;
-    uint32_t bricks;
+    uint32_t rows;         // histogram rows of all brick scenes
+    uint32_t bricks;       // bricks of all brick scenes
     int32_t lg[3];
     uint32_t max_nb;       // largest per-scene brick count
     uint64_t hist_words;
-    uint64_t pieces;       // piece-record capacity (worst case)
-    uint64_t work_bytes;   // workspace the table needs
-    uint64_t table_bytes;
+    uint64_t data_off;     // workspace offset of the histograms (then totals, offsets, records)
+    uint32_t n_direct;     // scenes served by the direct kernels
+    uint32_t row_cap;      // entries of row_scene
+    uint64_t direct_segs;  // segments of the direct scenes
 };
 constexpr uint32_t kTableMagic = 0x564F5842u;  // "BXOV"
 constexpr size_t kTableScenes = 64;
 static_assert(sizeof(BrickTable) <= kTableScenes, "table header fits its slot");
 
-// Launch bounds of a brick-path launch sequence (host side).
+// Workspace header words (int32 / uint32 index into the first 256 bytes).
+constexpr int kWStatus = 0;    // status bits (kStatus*)
+constexpr int kWOk = 2;        // 1 when the brick kernels may run
+constexpr int kWDirectAll = 3; // 1: the direct kernels serve every scene (records do not fit)
+constexpr int kWQueues = 4;    // 8 brick queues of the fill
+constexpr int kWPieces = 16;   // uint64: piece records the call needed (information)
+constexpr size_t kWorkTable = kAlign;
+
+// Launch bounds of a brick-path launch sequence (host side): the kernels
+// are sized by these, and the plan kernel checks that the scenes stay
+// within them.
 struct BrickLaunch {
-    uint32_t rows;
-    uint32_t bricks;
+    uint32_t n_scenes;
+    uint64_t total_segments;  // bound on the scenes' segments
+    uint32_t rows;            // histogram rows bound
+    uint32_t bricks;          // bricks bound
     int32_t lg[3];
-    uint32_t max_nb;
+    uint64_t table_bytes;     // table region (bound)
+    bool direct_kernels;      // launch the direct kernels (some scene may need them)
 };
 
-// Workspace: [status word, launch-ok flag, 8 brick queues] | the one-scene table of
-// a plain call | histogram rows | brick totals | bin offsets | piece records.
-constexpr size_t kWorkTable = kAlign;
-constexpr size_t kWorkData = kAlign + 512;
-static_assert(kTableScenes + 160 <= 512, "one-scene table fits its slot");
+// Histogram rows of a brick scene of n segments.
+__host__ __device__ inline uint32_t hist_rows(int64_t n) {
+    int64_t g = (n + kSegsPerRow - 1) / kSegsPerRow;
+    if (g > kHistRows) g = kHistRows;
+    if (g < 1) g = 1;
+    return (uint32_t)g;
+}
 
 void default_brick_lg(int32_t dx, int32_t dy, int32_t dz, int lg[3]);
 bool brick_shape_supported(const int lg[3]);
 // brick_geometry (vox_exact.h) for host files that do not compile device code.
 bool brick_geometry_for(int32_t dx, int32_t dy, int32_t dz, const int lg[3], BrickGeom& bg);
-// Process-wide brick shape chosen with vox_set_tuning (all zero = default).
-void tuned_brick_lg(int lg[3]);
+// Worst case of piece records of n segments in a volume.
 uint64_t max_pieces(int64_t n, const BrickGeom& bg);
-int hist_rows(int64_t n);
-size_t brick_work_bytes(uint64_t hist_words, uint32_t bricks, uint64_t pieces);
 
-// Fills the table header fields derived from the scenes (rows, bricks,
-// hist_words, pieces, max_nb, work_bytes) and each scene's bases; false if
-// a total overflows the 32-bit brick, row or piece indices.
-bool brick_table_layout(BrickTable& t, BrickScene* scenes, uint32_t n_scenes);
+// Launch bounds of a batch of n_scenes scenes holding at most
+// total_segments segments, for bricks of 2^lg, and the workspace bytes
+// before the piece records (table, histograms, brick totals and offsets).
+BrickLaunch batch_launch(uint32_t n_scenes, uint64_t total_segments, const int lg[3]);
+size_t batch_fixed_bytes(const BrickLaunch& L);
+constexpr uint64_t kRecordBytes = 16;
+constexpr uint64_t kDefaultPiecesPerSegment = 16;
 
-// Launches the brick pipeline over the device table d_table.  For a plain
-// call pass one_table/one_scene (the init kernel writes them into the
-// workspace, d_table is ignored).
-hipError_t launch_bricks(const void* d_table, const BrickLaunch& L, const BrickTable* one_table,
-                         const BrickScene* one_scene, void* d_work, size_t work_bytes,
-                         hipStream_t stream);
-hipError_t launch_brick_grid(const int32_t* segs, int64_t n, const BrickGeom& bg,
-                             uint32_t* grid, int32_t* counts, uint32_t flags, void* d_work,
-                             size_t work_bytes, hipStream_t stream);
+// Launches the plan kernel and the brick pipeline over the scenes
+// d_scenes[n_scenes] (device vox_scene array), or over the single scene
+// *one (a host vox_scene) when d_scenes is null.
+hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunch& L, int fill_wgs_per_cu,
+                         void* d_work, size_t work_bytes, hipStream_t stream);
+// Launch bounds of a plain call that takes the brick path, and its
+// workspace: the fixed part plus room for the worst case of records.
+BrickLaunch plain_launch(int64_t n, const BrickGeom& bg);
 size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg);
 
 size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz);
@@ -183,5 +208,15 @@ GridWork grid_workspace(void* d_work, size_t work_bytes, int64_t n, int32_t dx, 
 hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx, int32_t dy,
                        int32_t dz, uint32_t* grid, int32_t* counts, uint32_t flags,
                        const GridWork& w, hipStream_t stream);
+
+// Tuning: the per-call choice, else the library's autotune cache for the
+// key (volume, segment count), else the default.  `valid` rejects shapes
+// without a compiled kernel and non-zero reserved fields.
+struct Tuning {
+    int lg[3];
+    int fill_wgs_per_cu;  // 0 = the shape's default
+};
+bool tuning_from_abi(const void* vox_tuning_ptr, Tuning& t, char* why, size_t why_len);
+bool tuning_cache_lookup(int32_t dx, int32_t dy, int32_t dz, int64_t n, Tuning& t);
 
 }  // namespace vox

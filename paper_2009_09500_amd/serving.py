@@ -3,7 +3,9 @@
 Requests (a segment set and a volume each) arrive over time.  The engine
 
 * admits a waiting request, first come first served, when a resident grid
-  slot is free and its segment buffer fits the device-memory budget;
+  slot is free and its segment buffer fits the device-memory budget (the
+  GPU executor measures it: free HBM once the grid slots, the batch
+  workspace and the scene tables are allocated, less a reserve);
 * uploads the admitted request's segments on a copy stream;
 * forms batches at chunk granularity (continuous batching): every
   iteration takes up to `max_batch_segments` segments from the admitted
@@ -14,6 +16,9 @@ Requests (a segment set and a volume each) arrive over time.  The engine
 * runs each batch as one vox_batch_scenes launch sequence on the compute
   stream, keeping up to `max_inflight` batches queued on the GPU while the
   host forms the next;
+* copies each batch's device status word right after the batch, so a
+  batch that reports an error (an end point outside the volume) fails the
+  requests it served; they are reported as failed, the others as done;
 * completes a request when the batch holding its last chunk has finished;
   its grid stays resident in its slot until the completion callback returns.
 
@@ -46,6 +51,7 @@ class Request:
     slot: int | None = None
     next_seg: int = 0                 # segments already put into batches
     started: bool = False
+    failed: bool = False              # a batch with one of its chunks reported an error
     dev: dict = field(default_factory=dict)   # executor's per-request state
 
     @property
@@ -140,11 +146,16 @@ class Scheduler:
             r.next_seg += take
         return chunks
 
-    def complete(self, chunks: list, now: float) -> list:
+    def complete(self, chunks: list, now: float, failed: bool = False) -> list:
         """Marks the requests whose last chunk was in `chunks` as done and
-        frees their slot and budget; returns them."""
+        frees their slot and budget; returns them.  failed: the batch of
+        these chunks reported an error, so every request it served is marked
+        failed (one with chunks still to come completes, failed, with its
+        last chunk)."""
         done = []
         for c in chunks:
+            if failed:
+                c.req.failed = True
             if c.last:
                 r = c.req
                 r.done = now
@@ -194,8 +205,9 @@ def run(requests, executor, scheduler: Scheduler, max_inflight: int = 2,
             executor.upload(r)
         progressed = False
         while inflight and executor.poll(inflight[0][1]):
-            chunks, _ = inflight.popleft()
-            for r in scheduler.complete(chunks, clock() - t0):
+            chunks, handle = inflight.popleft()
+            failed = executor.batch_status(handle) != 0
+            for r in scheduler.complete(chunks, clock() - t0, failed=failed):
                 if on_done is not None:
                     on_done(r, executor)
                 executor.release(r)
@@ -211,12 +223,14 @@ def run(requests, executor, scheduler: Scheduler, max_inflight: int = 2,
         if not progressed:
             sleep(poll_sleep)
     makespan = clock() - t0
-    lat = [r.done - r.arrival for r in finished]
-    voxels = sum(r.voxels for r in finished)
+    good = [r for r in finished if not r.failed]
+    lat = [r.done - r.arrival for r in good]
+    voxels = sum(r.voxels for r in good)
     return {
         "requests": len(finished),
+        "failed_requests": len(finished) - len(good),
         "makespan_s": makespan,
-        "requests_per_s": len(finished) / makespan if makespan > 0 else float("nan"),
+        "requests_per_s": len(good) / makespan if makespan > 0 else float("nan"),
         "voxels_per_s": voxels / makespan if makespan > 0 else float("nan"),
         "latency_p50_ms": 1e3 * percentile(lat, 50),
         "latency_p99_ms": 1e3 * percentile(lat, 99),
@@ -236,9 +250,18 @@ def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
 class GpuExecutor:
     """Device side of the serving loop: resident grid slots, a copy stream
     for segment uploads and a compute stream for batches (libvox through the
-    binding; nothing here computes voxels)."""
+    binding; nothing here computes voxels).
 
-    def __init__(self, dims, n_slots: int, device=None):
+    Everything the batches need is allocated once, up front: the grid slots,
+    one batch workspace for `max_batch_segments` segments over
+    `max_batch_scenes` scenes (vox_workspace_bytes), and a ring of device
+    scene tables with pinned staging and a pinned status word per in-flight
+    batch.  `admission_budget()` is then what free HBM remains for the
+    requests' segment buffers, measured, less `reserve_bytes`."""
+
+    def __init__(self, dims, n_slots: int, max_batch_segments: int = 2_000_000,
+                 max_batch_scenes: int = 32, max_inflight: int = 2, device=None, tuning=None,
+                 reserve_bytes: int = 1 << 30):
         import torch
         from . import binding
         self.torch = torch
@@ -246,21 +269,32 @@ class GpuExecutor:
         binding.load()
         self.device = device or torch.device("cuda:0")
         self.dims = tuple(int(d) for d in dims)
+        self.max_batch_segments = int(max_batch_segments)
+        self.max_batch_scenes = int(max_batch_scenes)
+        self.tuning = tuning
         self.copy_stream = torch.cuda.Stream(device=self.device)
         self.compute = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(self.compute):
             self.grids = [torch.empty(binding.grid_words(self.dims), dtype=torch.int32,
                                       device=self.device) for _ in range(n_slots)]
-        self.work = None
-        self.d_table = None
-        self.staging = collections.deque()
+            self.work = binding.workspace(
+                binding.batch_workspace_bytes(self.max_batch_segments, self.max_batch_scenes), self.device)
+        ring = max_inflight + 1
+        table_bytes = 48 * self.max_batch_scenes
+        self.d_tables = [torch.empty(table_bytes, dtype=torch.uint8, device=self.device) for _ in range(ring)]
+        self.h_tables = [torch.empty(table_bytes, dtype=torch.uint8).pin_memory() for _ in range(ring)]
+        self.h_status = torch.zeros(ring, dtype=torch.int32).pin_memory()
+        self.status_word = self.work[:4].view(torch.int32)
+        assert self.status_word.data_ptr() == binding.vox_device_status(self.work)
+        self.slot = 0
+        self.reserve = int(reserve_bytes)
+        torch.cuda.synchronize(self.device)
 
-    def _buffer(self, cur, nbytes: int, dtype):
-        torch = self.torch
-        if cur is not None and cur.numel() * cur.element_size() >= nbytes:
-            return cur
-        with torch.cuda.stream(self.compute):   # freed and reused in compute-stream order
-            return torch.empty(max(int(nbytes * 1.25), 256), dtype=dtype, device=self.device)
+    def admission_budget(self) -> int:
+        """Bytes of request segment buffers that fit in the free HBM left
+        (measured now), less the reserve."""
+        free, _ = self.torch.cuda.mem_get_info(self.device)
+        return max(int(free) - self.reserve, 0)
 
     def upload(self, r: Request):
         torch = self.torch
@@ -276,6 +310,8 @@ class GpuExecutor:
 
     def launch(self, chunks):
         torch, binding = self.torch, self.binding
+        if len(chunks) > self.max_batch_scenes:
+            raise ValueError("batch of %d chunks, the executor holds %d" % (len(chunks), self.max_batch_scenes))
         scenes = []
         for c in chunks:
             r = c.req
@@ -284,22 +320,31 @@ class GpuExecutor:
             segs = r.dev["d_segs"][c.lo:c.hi]
             flags = binding.VOX_GRID_CLEAR if c.first else 0
             scenes.append((segs, self.dims, self.grids[r.slot], None, flags))
-        table, launch = binding.vox_batch_plan(scenes)
-        self.work = self._buffer(self.work, launch.work_bytes, torch.uint8)
-        self.d_table = self._buffer(self.d_table, launch.table_bytes, torch.uint8)
-        host = torch.from_numpy(table).pin_memory()
+        total = sum(c.hi - c.lo for c in chunks)
+        if total > self.max_batch_segments:
+            raise ValueError("batch of %d segments, the executor holds %d" % (total, self.max_batch_segments))
+        k = self.slot
+        self.slot = (self.slot + 1) % len(self.d_tables)
+        table = binding.scene_table(scenes)
+        self.h_tables[k][:table.size].copy_(torch.from_numpy(table))
         with torch.cuda.stream(self.compute):
-            self.d_table[:table.size].copy_(host, non_blocking=True)
-            binding.vox_batch_scenes(self.d_table, launch, self.work, stream=self.compute)
+            self.d_tables[k][:table.size].copy_(self.h_tables[k][:table.size], non_blocking=True)
+            binding.vox_batch_scenes(self.d_tables[k], len(scenes), total, self.work, tuning=self.tuning,
+                                     stream=self.compute)
+            # This batch's status word, before the next batch rewrites it.
+            self.h_status[k:k + 1].copy_(self.status_word, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.compute)
         for c in chunks:
             c.req.dev["d_segs"].record_stream(self.compute)
-        # The pinned table must outlive its copy: keep it with the batch.
-        return (ev, host)
+        return (ev, k)
 
     def poll(self, handle) -> bool:
         return handle[0].query()
+
+    def batch_status(self, handle) -> int:
+        """Device status bits of a finished batch (0: no error)."""
+        return int(self.h_status[handle[1]])
 
     def release(self, r: Request):
         r.dev.pop("d_segs", None)
@@ -309,6 +354,4 @@ class GpuExecutor:
         return self.grids[r.slot]
 
     def status(self) -> int:
-        if self.work is None:
-            return self.binding.VOX_OK
         return self.binding.vox_read_status(self.work, stream=self.compute)

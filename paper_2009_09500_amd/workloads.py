@@ -186,8 +186,17 @@ def geodesic_icosphere(m: int):
     order = np.argsort(vid, axis=2, kind="stable")
     vid_s = np.take_along_axis(vid, order, axis=2)
     ww_s = np.take_along_axis(ww, order, axis=2)
-    keys = np.concatenate([vid_s, ww_s], axis=2).reshape(F0 * P, 6)
-    uniq, inv = np.unique(keys, axis=0, return_inverse=True)
+    # One int64 per key, packed so that integer order is the lexicographic
+    # order of (ids, weights): ids < 16 take 4 bits, weights <= m < 2^16 take
+    # 16 bits each (52 bits in all).
+    keys = np.concatenate([vid_s, ww_s], axis=2).reshape(F0 * P, 6).astype(np.int64)
+    packed = np.zeros(F0 * P, dtype=np.int64)
+    for c in range(3):
+        packed = (packed << 4) | keys[:, c]
+    for c in range(3):
+        packed = (packed << 16) | keys[:, 3 + c]
+    uniq_p, first, inv = np.unique(packed, return_index=True, return_inverse=True)
+    uniq = keys[first]
     inv = inv.reshape(F0, P)
     # Positions from the unique keys.
     pos = np.zeros((uniq.shape[0], 3))
@@ -210,8 +219,10 @@ def geodesic_icosphere(m: int):
     tri_local = np.concatenate(tris, axis=0)         # [m^2, 3]
     tri = inv[:, tri_local].reshape(-1, 3)           # [20 m^2, 3]
     e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]], axis=0)
-    e = np.sort(e, axis=1)
-    edges = np.unique(e, axis=0)
+    e = np.sort(e, axis=1).astype(np.int64)
+    # Unique rows (a, b), a < b, in row order, as unique int64 (a << 32 | b).
+    pe = np.unique((e[:, 0] << 32) | e[:, 1])
+    edges = np.stack([pe >> 32, pe & 0xFFFFFFFF], axis=1)
     return pos, edges, tri.shape[0]
 
 

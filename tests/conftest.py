@@ -32,7 +32,7 @@ def pytest_sessionstart(session):
     d = tempfile.mkdtemp(prefix="vox_oracle_")
     _jobs["dir"] = d
     _jobs["proc"] = subprocess.Popen(
-        [sys.executable, "-m", "tests.oracle_jobs", d, "arbitrary4m", "scenes"],
+        [sys.executable, "-m", "tests.oracle_jobs", d, "arbitrary4m_euclid", "arbitrary4m", "scenes"],
         cwd=ROOT, stdout=subprocess.DEVNULL, stderr=open(os.path.join(d, "jobs.log"), "w"))
 
 

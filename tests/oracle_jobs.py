@@ -45,15 +45,17 @@ def _workers() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def sharded_grid(segs: np.ndarray, dims) -> np.ndarray:
+def sharded_grid(segs: np.ndarray, dims, euclid: bool = False) -> np.ndarray:
     """The oracle volume of all segments, computed as the OR of the oracle
-    volumes of P disjoint shards (P forked workers, no GPU involved)."""
+    volumes of P disjoint shards (P forked workers, no GPU involved); euclid:
+    the Euclidean N of eq. (1)."""
     from oracle import oracle
     oracle.default()  # build/load before forking
+    grid_fn = oracle.grid_euclid if euclid else oracle.grid
     nwords = (int(dims[0]) * int(dims[1]) * int(dims[2]) + 31) // 32
     P = min(_workers(), max(1, segs.shape[0] // 50000))
     if P == 1:
-        return oracle.grid(segs, dims)
+        return grid_fn(segs, dims)
     bounds = np.linspace(0, segs.shape[0], P + 1).astype(np.int64)
     maps = [mmap.mmap(-1, nwords * 4) for _ in range(P)]
     pids = []
@@ -61,7 +63,7 @@ def sharded_grid(segs: np.ndarray, dims) -> np.ndarray:
         pid = os.fork()
         if pid == 0:  # child: one shard, result into its shared map
             try:
-                g = oracle.grid(segs[bounds[p]:bounds[p + 1]], dims)
+                g = grid_fn(segs[bounds[p]:bounds[p + 1]], dims)
                 np.frombuffer(maps[p], dtype=np.uint32)[:] = g
                 os._exit(0)
             except BaseException:
@@ -85,6 +87,47 @@ def job_arbitrary4m() -> dict:
     g = sharded_grid(c["segs"], c["dims"])
     return {"dims": list(c["dims"]), "words": int(g.size), "digests": block_digests(g),
             "popcount": popcount(g)}
+
+
+def sharded_counts_euclid(segs: np.ndarray) -> np.ndarray:
+    """The oracle's per-segment voxel counts with the Euclidean N, on
+    disjoint shards in forked workers."""
+    from oracle import oracle
+    oracle.default()
+    P = min(_workers(), max(1, segs.shape[0] // 50000))
+    bounds = np.linspace(0, segs.shape[0], P + 1).astype(np.int64)
+    m = mmap.mmap(-1, max(4 * segs.shape[0], 4))
+    pids = []
+    for p in range(P):
+        pid = os.fork()
+        if pid == 0:
+            try:
+                c = oracle.counts_euclid(segs[bounds[p]:bounds[p + 1]])
+                np.frombuffer(m, dtype=np.int32)[bounds[p]:bounds[p + 1]] = c
+                os._exit(0)
+            except BaseException:
+                os._exit(1)
+        pids.append(pid)
+    for pid in pids:
+        _, st = os.waitpid(pid, 0)
+        if st != 0:
+            raise RuntimeError("oracle count worker failed")
+    out = np.frombuffer(m, dtype=np.int32)[:segs.shape[0]].copy()
+    m.close()
+    return out
+
+
+def job_arbitrary4m_euclid() -> dict:
+    """The arbitrary-length workload with the Euclidean N of eq. (1): every
+    16 MiB block of the cleared 2048^3 volume, its popcount, and a digest of
+    all per-segment counts."""
+    from paper_2009_09500_amd import workloads
+    c = workloads.arbitrary_length()
+    g = sharded_grid(c["segs"], c["dims"], euclid=True)
+    counts = sharded_counts_euclid(c["segs"])
+    return {"dims": list(c["dims"]), "words": int(g.size), "digests": block_digests(g),
+            "popcount": popcount(g), "counts_sha256": hashlib.sha256(counts.tobytes()).hexdigest(),
+            "counts_sum": int(counts.astype(np.int64).sum())}
 
 
 def job_scenes() -> dict:
@@ -126,7 +169,7 @@ def job_scenes() -> dict:
     return {"n_scenes": len(sc), "digests": res}
 
 
-JOBS = {"arbitrary4m": job_arbitrary4m, "scenes": job_scenes}
+JOBS = {"arbitrary4m": job_arbitrary4m, "scenes": job_scenes, "arbitrary4m_euclid": job_arbitrary4m_euclid}
 
 
 def result_path(outdir: str, name: str) -> str:

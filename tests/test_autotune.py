@@ -1,5 +1,6 @@
 """Autotuner host logic (CPU): cache keys, cache file round trip, choice of
-the fastest shape, and that tuning leaves the process-wide shape set."""
+the fastest candidate, and that the choice lands in the library's autotune
+cache for its volume and segment count only."""
 
 import pytest
 
@@ -15,10 +16,10 @@ class FakeSegs:
 
 
 @pytest.fixture(autouse=True)
-def default_tuning():
-    binding.vox_set_tuning(None)
+def empty_cache():
+    binding.vox_tuning_cache_clear()
     yield
-    binding.vox_set_tuning(None)
+    binding.vox_tuning_cache_clear()
 
 
 def test_key_buckets_segment_counts():
@@ -29,48 +30,53 @@ def test_key_buckets_segment_counts():
     assert autotune.key("d", (64, 64, 64), 0).endswith("n~2^-1")
 
 
-def test_every_shape_is_compiled():
-    for s in autotune.SHAPES:
-        binding.vox_set_tuning(s)
-        assert binding.vox_get_tuning() == s
+def test_every_candidate_is_a_valid_tuning():
+    for c in autotune.CANDIDATES:
+        binding.vox_tuning_cache_set((512, 512, 512), 1 << 20, autotune.tuning_of(c))
+        t = binding.vox_tuning_cache_get((512, 512, 512), 1 << 20)
+        assert (tuple(t.brick_lg), t.fill_wgs_per_cu) == (c[:3], c[3])
 
 
-def test_best_shape_and_ties():
-    assert autotune.best_shape({(8, 6, 5): 2.0, (8, 6, 6): 1.0, (7, 6, 6): 3.0}) == (8, 6, 6)
-    assert autotune.best_shape({(7, 7, 6): 1.0, (8, 6, 5): 1.0}) == (8, 6, 5)
+def test_best_candidate_and_ties():
+    assert autotune.best_candidate({(8, 6, 5, 2): 2.0, (8, 6, 6, 0): 1.0, (7, 6, 6, 1): 3.0}) == (8, 6, 6, 0)
+    assert autotune.best_candidate({(7, 7, 6, 0): 1.0, (8, 6, 5, 2): 1.0}) == (8, 6, 5, 2)
 
 
-def test_tune_caches_and_applies(tmp_path):
+def test_tune_caches_and_installs(tmp_path):
     cache = autotune.TuneCache(str(tmp_path / "t.json"))
-    fake = {(8, 6, 5): 1.5, (8, 6, 6): 1.2, (7, 6, 6): 1.9, (7, 7, 6): 1.3}
+    fake = {c: 1.5 + 0.1 * i for i, c in enumerate(autotune.CANDIDATES)}
+    fake[(8, 6, 6, 0)] = 1.2
     best, times = autotune.tune_grid(FakeSegs(1 << 20), (1024, 1024, 1024), cache=cache,
-                                     timer=lambda s: fake[s], device="gfx950-test")
-    assert best == (8, 6, 6) and times == fake
-    assert binding.vox_get_tuning() == (8, 6, 6)
+                                     timer=lambda c: fake[c], device="gfx950-test")
+    assert best == (8, 6, 6, 0) and times == fake
+    t = binding.vox_tuning_cache_get((1024, 1024, 1024), 1 << 20)
+    assert tuple(t.brick_lg) == (8, 6, 6) and t.fill_wgs_per_cu == 0
+    # Other volumes and counts keep the default.
+    assert binding.vox_tuning_cache_get((512, 512, 512), 1 << 20) is None
+    assert binding.vox_tuning_cache_get((1024, 1024, 1024), 1 << 10) is None
     again = autotune.TuneCache(str(tmp_path / "t.json"))          # reloaded from disk
-    assert again.get(autotune.key("gfx950-test", (1024, 1024, 1024), 1 << 20)) == (8, 6, 6)
-    binding.vox_set_tuning(None)
-    assert autotune.apply((1024, 1024, 1024), 1 << 20, "gfx950-test", cache=again) == (8, 6, 6)
-    assert binding.vox_get_tuning() == (8, 6, 6)
-    binding.vox_set_tuning(None)
+    assert again.get(autotune.key("gfx950-test", (1024, 1024, 1024), 1 << 20)) == (8, 6, 6, 0)
+    binding.vox_tuning_cache_clear()
+    assert autotune.apply((1024, 1024, 1024), 1 << 20, "gfx950-test", cache=again) == (8, 6, 6, 0)
+    assert tuple(binding.vox_tuning_cache_get((1024, 1024, 1024), 1 << 20).brick_lg) == (8, 6, 6)
     assert autotune.apply((512, 512, 512), 1 << 20, "gfx950-test", cache=again) is None
-    assert binding.vox_get_tuning() == (0, 0, 0)
 
 
-def test_tuning_restored_when_timer_fails(tmp_path):
-    binding.vox_set_tuning((7, 6, 6))
+def test_failed_timer_installs_nothing(tmp_path):
     cache = autotune.TuneCache(str(tmp_path / "t.json"))
 
-    def boom(s):
+    def boom(c):
         raise RuntimeError("timer failed")
     with pytest.raises(RuntimeError):
-        autotune.tune_grid(FakeSegs(10), (64, 64, 64), cache=cache, timer=boom, device="x")
-    assert binding.vox_get_tuning() == (7, 6, 6)
+        autotune.tune_grid(FakeSegs(1 << 20), (64, 64, 64), cache=cache, timer=boom, device="x")
+    assert binding.vox_tuning_cache_get((64, 64, 64), 1 << 20) is None
 
 
 def test_corrupt_cache_is_ignored(tmp_path):
     p = tmp_path / "bad.json"
     p.write_text("{not json")
     assert autotune.TuneCache(str(p)).entries == {}
-    p.write_text('{"k": {"shape": [9, 9, 9], "ms": {}}}')
+    p.write_text('{"k": {"candidate": [9, 9, 9, 0], "ms": {}}}')
+    assert autotune.TuneCache(str(p)).get("k") is None
+    p.write_text('{"k": {"shape": [8, 6, 6], "ms": {}}}')              # an older file's entry
     assert autotune.TuneCache(str(p)).get("k") is None

@@ -1,20 +1,23 @@
-"""Host-side batch planning (vox_batch_plan, vox_batch_launch_cover): the
-table image, the launch shape and the argument checks.  CPU only: the
-planner makes no device call and never dereferences the scene pointers."""
+"""Batch planning on the CPU: the per-scene rule the plan kernel applies
+(which scenes the LDS brick kernels serve, which the direct kernels serve,
+histogram rows, brick counts, the argument rules), the batch workspace
+query, the host-side checks of vox_batch_scenes, the autotune cache and the
+status-word address.  No call here reaches the GPU."""
 
 import ctypes
-import struct
+import os
+import shutil
+import subprocess
 
-import numpy as np
 import pytest
 
 from paper_2009_09500_amd import binding
 
-HEADER = struct.Struct("<4I3iI4Q")          # BrickTable
-SCENE = struct.Struct("<3Q q Q 3i 3i 3i I 4I")  # BrickScene
-SCENES_AT = 64
-ROWS_PER = 4096
-MAX_ROWS = 256
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "tests", "cpp", "plan_check.cpp")
+CLEAR, EUCLID = 1, 2
+F_CLEAR, F_DIRECT, F_EUCLID, F_A8 = 1, 2, 4, 8
+SEGS, GRID = 1 << 30, 1 << 40          # fake 256-aligned device addresses
 
 
 @pytest.fixture(scope="module")
@@ -22,184 +25,138 @@ def lib():
     return binding.load()
 
 
-@pytest.fixture(autouse=True)
-def default_tuning():
-    binding.vox_set_tuning(None)
-    yield
-    binding.vox_set_tuning(None)
+@pytest.fixture(scope="module")
+def planner(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    out = str(tmp_path_factory.mktemp("plan") / "plan_check")
+    subprocess.check_call([hipcc, "-O1", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_2009_09500_amd", "csrc"), "-o", out, SRC])
 
-
-def scene_array(specs):
-    """specs: (n, (dx, dy, dz), flags); fake 256-aligned device pointers."""
-    arr = (binding.VoxScene * len(specs))()
-    for i, (n, dims, flags) in enumerate(specs):
-        arr[i].segs = (1 << 30) + i * (1 << 24) if n else 0
-        arr[i].n = n
-        arr[i].dim_x, arr[i].dim_y, arr[i].dim_z = dims
-        arr[i].flags = flags
-        arr[i].grid = (1 << 40) + i * (1 << 28)
-        arr[i].counts = 0
-    return arr
-
-
-def plan(lib, specs):
-    arr = scene_array(specs)
-    launch = binding.VoxBatchLaunch()
-    st = lib.vox_batch_plan(arr, len(specs), None, 0, ctypes.byref(launch))
-    assert st == binding.VOX_OK, lib.vox_last_error()
-    table = np.zeros(launch.table_bytes, dtype=np.uint8)
-    st = lib.vox_batch_plan(arr, len(specs), ctypes.c_void_p(table.ctypes.data), table.nbytes,
-                            ctypes.byref(launch))
-    assert st == binding.VOX_OK, lib.vox_last_error()
-    return table, launch
-
-
-def decode(table):
-    h = HEADER.unpack_from(table.tobytes(), 0)
-    hdr = dict(magic=h[0], n_scenes=h[1], rows=h[2], bricks=h[3], lg=h[4:7], max_nb=h[7],
-               hist_words=h[8], pieces=h[9], work_bytes=h[10], table_bytes=h[11])
-    scenes = []
-    for i in range(hdr["n_scenes"]):
-        v = SCENE.unpack_from(table.tobytes(), SCENES_AT + i * SCENE.size)
-        scenes.append(dict(segs=v[0], counts=v[1], grid=v[2], n=v[3], hist_off=v[4],
-                           dim=v[5:8], lg=v[8:11], nb=v[11:14], nbricks=v[14],
-                           brick_base=v[15], row_base=v[16], rows=v[17], flags=v[18]))
-    return hdr, scenes
+    def run(lg, scenes):
+        """scenes: dicts with n, dims and optional flags, segs, grid, counts."""
+        lines = ["%d %d %d %d" % (lg[0], lg[1], lg[2], len(scenes))]
+        for sc in scenes:
+            lines.append("%d %d %d %d %d %d %d %d" % (
+                sc.get("segs", SEGS), sc["n"], sc["dims"][0], sc["dims"][1], sc["dims"][2],
+                sc.get("flags", CLEAR), sc.get("grid", GRID), sc.get("counts", 0)))
+        r = subprocess.run([out], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True)
+        res = []
+        for ln in r.stdout.split("\n"):
+            if ln.strip():
+                v = [int(x) for x in ln.split()]
+                res.append(dict(valid=bool(v[0]), flags=v[1], rows=v[2], nbricks=v[3], nb=tuple(v[4:7]),
+                                dim=tuple(v[7:10]), n=v[10]))
+        return res
+    return run
 
 
 def expected_rows(n):
-    return min(MAX_ROWS, max(1, -(-n // ROWS_PER)))
+    return min(256, max(1, -(-n // 4096)))
 
 
-def test_scene_struct_size():
-    assert SCENE.size == 96 and HEADER.size == 64
+def test_brick_scenes(planner):
+    lg = (8, 6, 5)
+    specs = [dict(n=1000, dims=(64, 64, 64)), dict(n=0, dims=(128, 96, 64), flags=0),
+             dict(n=200000, dims=(512, 512, 512)), dict(n=5000, dims=(256, 128, 256)),
+             dict(n=4096 * 300, dims=(2048, 2048, 2048))]
+    for sc, out in zip(specs, planner(lg, specs)):
+        nb = tuple(-(-d // (1 << l)) for d, l in zip(sc["dims"], lg))
+        assert out["valid"] and out["nb"] == nb and out["nbricks"] == nb[0] * nb[1] * nb[2]
+        assert out["flags"] == (F_CLEAR if sc.get("flags", CLEAR) else 0) | F_A8
+        assert out["rows"] == expected_rows(sc["n"]) and out["dim"] == sc["dims"] and out["n"] == sc["n"]
 
 
-def test_table_layout(lib):
-    specs = [(1000, (64, 64, 64), 1), (0, (128, 96, 64), 0), (200000, (512, 512, 512), 1),
-             (5000, (256, 128, 256), 1)]
-    table, launch = plan(lib, specs)
-    hdr, scenes = decode(table)
-    assert hdr["magic"] == 0x564F5842 and hdr["n_scenes"] == 4
-    lg = (8, 6, 5)                       # default of the largest volume (512^3)
-    assert tuple(launch.brick_lg) == lg and hdr["lg"] == lg
-    rows = bricks = hist = pieces = 0
-    for (n, dims, flags), sc in zip(specs, scenes):
-        nb = tuple(-(-d // (1 << l)) for d, l in zip(dims, lg))
-        assert sc["nb"] == nb and sc["nbricks"] == nb[0] * nb[1] * nb[2]
-        assert sc["dim"] == dims and sc["n"] == n
-        assert sc["rows"] == expected_rows(n)
-        assert sc["row_base"] == rows and sc["brick_base"] == bricks and sc["hist_off"] == hist
-        assert sc["flags"] & 1 == flags
-        rows += sc["rows"]
-        bricks += sc["nbricks"]
-        hist += sc["rows"] * sc["nbricks"]
-        pieces += n * (1 + sum(b - 1 for b in nb))
-    assert (hdr["rows"], hdr["bricks"], hdr["hist_words"], hdr["pieces"]) == (rows, bricks, hist, pieces)
-    assert launch.rows == rows and launch.bricks == bricks
-    assert launch.max_scene_bricks == max(sc["nbricks"] for sc in scenes) == hdr["max_nb"]
-    assert launch.work_bytes == hdr["work_bytes"] and launch.table_bytes == hdr["table_bytes"]
-    assert hdr["table_bytes"] == SCENES_AT + 4 * SCENE.size + 4 * (rows + bricks)
-    tail = np.frombuffer(table.tobytes(), dtype=np.uint32, offset=SCENES_AT + 4 * SCENE.size)
-    row_scene, brick_scene = tail[:rows], tail[rows:rows + bricks]
-    for i, sc in enumerate(scenes):
-        assert (row_scene[sc["row_base"]:sc["row_base"] + sc["rows"]] == i).all()
-        assert (brick_scene[sc["brick_base"]:sc["brick_base"] + sc["nbricks"]] == i).all()
-    # Workspace: header slots, histogram rows, totals, bin offsets, records.
-    up = lambda v: (v + 255) // 256 * 256
-    assert hdr["work_bytes"] == 768 + up(4 * hist) + up(4 * bricks) + up(4 * (bricks + 1)) + 16 * pieces
+def test_direct_scenes(planner):
+    """Scenes the bricks cannot serve go to the direct kernels: rows not
+    whole words, sides beyond 16384, too many bricks, the Euclidean N, a
+    segment array that is only 4-byte aligned."""
+    lg = (8, 6, 5)
+    specs = [dict(n=10, dims=(48, 64, 64)), dict(n=10, dims=(32768, 32, 32)),
+             dict(n=10, dims=(16384, 16384, 64)), dict(n=10, dims=(64, 64, 64), flags=CLEAR | EUCLID),
+             dict(n=10, dims=(64, 64, 64), segs=SEGS + 4)]
+    res = planner(lg, specs)
+    for sc, out in zip(specs, res):
+        assert out["valid"] and out["flags"] & F_DIRECT and out["rows"] == 0 and out["nbricks"] == 0, sc
+        assert out["dim"] == sc["dims"] and out["n"] == 10
+    assert res[3]["flags"] & F_EUCLID and res[3]["flags"] & F_A8
+    assert not res[4]["flags"] & F_A8
 
 
-def test_one_scene_table_has_no_lookup_arrays(lib):
-    table, launch = plan(lib, [(4096 * 3 + 1, (256, 256, 256), 1)])
-    hdr, scenes = decode(table)
-    assert hdr["table_bytes"] == SCENES_AT + SCENE.size
-    assert scenes[0]["rows"] == 4 and launch.rows == 4
+def test_invalid_scenes(planner):
+    bad = [dict(n=-1, dims=(64, 64, 64)), dict(n=10, dims=(64, 0, 64)), dict(n=10, dims=(1 << 21, 8, 8)),
+           dict(n=10, dims=(64, 64, 64), flags=4), dict(n=10, dims=(64, 64, 64), segs=0),
+           dict(n=10, dims=(64, 64, 64), segs=SEGS + 2), dict(n=10, dims=(64, 64, 64), grid=GRID + 4),
+           dict(n=10, dims=(64, 64, 64), grid=0), dict(n=10, dims=(64, 64, 64), counts=GRID + 2),
+           dict(n=1 << 31, dims=(64, 64, 64)), dict(n=10, dims=(1 << 20, 1 << 20, 1 << 0))]
+    res = planner((8, 6, 5), bad[:-1] + [dict(n=10, dims=(1 << 19, 1 << 19, 2))])
+    for sc, out in zip(bad, res):
+        assert not out["valid"], sc
+        assert out["n"] == 0 and out["flags"] & F_DIRECT      # no segment is ever read
+    ok = planner((8, 6, 5), [dict(n=0, dims=(64, 64, 64), segs=0), dict(n=10, dims=(1 << 20, 1 << 18, 1))])
+    assert all(o["valid"] for o in ok)
 
 
-def test_plain_and_batch_workspace_agree(lib):
-    """A one-scene batch needs what the plain call on the same volume needs
-    when the plain call takes the brick path (more than 16384 segments);
-    smaller plain calls take the direct path and need less."""
-    for n, dims in ((20000, (256, 256, 256)), (10**6, (512, 512, 512)), (16385, (64, 64, 32))):
-        _, launch = plan(lib, [(n, dims, 1)])
-        assert launch.work_bytes == lib.vox_grid_workspace_bytes(n, *dims)
-    for n, dims in ((1000, (256, 256, 256)), (16384, (512, 512, 512)), (1, (64, 64, 32))):
-        _, launch = plan(lib, [(n, dims, 1)])
-        assert 0 < lib.vox_grid_workspace_bytes(n, *dims) < launch.work_bytes
+def test_shape_changes_bricks(planner):
+    for lg in ((8, 6, 6), (7, 6, 6), (7, 7, 6)):
+        out = planner(lg, [dict(n=100, dims=(512, 512, 512))])[0]
+        nb = tuple(512 >> l for l in lg)
+        assert out["nb"] == nb and not out["flags"] & F_DIRECT
 
 
-def test_tuning_sets_batch_shape(lib):
-    binding.vox_set_tuning((7, 6, 6))
-    _, launch = plan(lib, [(100, (512, 512, 512), 1)])
-    assert tuple(launch.brick_lg) == (7, 6, 6)
+def test_batch_workspace_query(lib):
+    w = lambda n, s: lib.vox_workspace_bytes(binding.VOX_OP_BATCH, n, s)
+    assert 0 < w(1000, 1) < w(10**6, 1) < w(10**6, 32)
+    assert w(10**6, 1) >= 16 * 16 * 10**6                 # 16 records of 16 bytes a segment
+    assert w(-1, 1) == 0 and w(10, 0) == 0 and w(10, 65537) == 0
+    assert lib.vox_workspace_bytes(99, 10, 1) == 0
 
 
-def test_plan_errors(lib):
-    launch = binding.VoxBatchLaunch()
-    arr = scene_array([(10, (64, 64, 64), 1)])
-    assert lib.vox_batch_plan(arr, 0, None, 0, ctypes.byref(launch)) == binding.VOX_ERR_INVALID_ARGUMENT
-    assert lib.vox_batch_plan(arr, 1, None, 0, None) == binding.VOX_ERR_INVALID_ARGUMENT
-    bad = [
-        [(10, (48, 64, 64), 1)],          # dim_x not a multiple of 32
-        [(10, (64, 0, 64), 1)],           # empty side
-        [(10, (64, 64, 64), 2)],          # unknown flag
-        [(-1, (64, 64, 64), 1)],          # negative n
-        [(10, (32768, 32, 32), 1)],       # side beyond the brick path
-    ]
-    for specs in bad:
-        a = scene_array(specs)
-        assert lib.vox_batch_plan(a, 1, None, 0, ctypes.byref(launch)) == \
-            binding.VOX_ERR_INVALID_ARGUMENT, specs
-    a = scene_array([(10, (64, 64, 64), 1), (10, (64, 64, 64), 1)])
-    a[1].grid = (1 << 40) + 4                                    # misaligned grid
-    assert lib.vox_batch_plan(a, 2, None, 0, ctypes.byref(launch)) == binding.VOX_ERR_INVALID_ARGUMENT
-    assert b"scene 1" in lib.vox_last_error()
-    a = scene_array([(10, (64, 64, 64), 1)])
-    a[0].segs = (1 << 30) + 4                                    # only 4-byte aligned
-    assert lib.vox_batch_plan(a, 1, None, 0, ctypes.byref(launch)) == binding.VOX_ERR_INVALID_ARGUMENT
-    assert b"8-byte" in lib.vox_last_error()
-    a = scene_array([(10, (64, 64, 64), 1)])
-    a[0].segs = 0                                                # n > 0 without segments
-    assert lib.vox_batch_plan(a, 1, None, 0, ctypes.byref(launch)) == binding.VOX_ERR_INVALID_ARGUMENT
-    a = scene_array([(10, (64, 64, 64), 1)])
-    assert lib.vox_batch_plan(a, 1, None, 0, ctypes.byref(launch)) == binding.VOX_OK
-    small = np.zeros(launch.table_bytes - 1, dtype=np.uint8)
-    assert lib.vox_batch_plan(a, 1, ctypes.c_void_p(small.ctypes.data), small.nbytes,
-                              ctypes.byref(launch)) == binding.VOX_ERR_INVALID_ARGUMENT
-
-
-def test_launch_cover(lib):
-    _, a = plan(lib, [(1000, (512, 512, 512), 1)])
-    _, b = plan(lib, [(10**5, (256, 256, 256), 1), (10, (64, 64, 64), 1)])
-    bound = binding.VoxBatchLaunch()
-    binding.vox_batch_launch_cover(bound, a)
-    binding.vox_batch_launch_cover(bound, b)
-    for f in ("rows", "bricks", "max_scene_bricks", "work_bytes", "table_bytes"):
-        assert getattr(bound, f) == max(getattr(a, f), getattr(b, f)), f
-    assert tuple(bound.brick_lg) == (8, 6, 5)
-    binding.vox_set_tuning((8, 6, 6))
-    _, c = plan(lib, [(10, (64, 64, 64), 1)])
-    with pytest.raises(binding.VoxError):
-        binding.vox_batch_launch_cover(bound, c)
-
-
-def test_batch_scenes_host_errors(lib):
-    _, launch = plan(lib, [(10, (64, 64, 64), 1)])
+def test_batch_host_errors(lib):
     P = ctypes.c_void_p
     fake = P(1 << 20)
-    L = ctypes.byref(launch)
-    assert lib.vox_batch_scenes(None, L, fake, 1 << 30, None) == binding.VOX_ERR_INVALID_ARGUMENT
-    assert lib.vox_batch_scenes(P((1 << 20) + 8), L, fake, 1 << 30, None) == \
-        binding.VOX_ERR_INVALID_ARGUMENT
-    assert lib.vox_batch_scenes(fake, None, fake, 1 << 30, None) == binding.VOX_ERR_INVALID_ARGUMENT
-    assert lib.vox_batch_scenes(fake, L, fake, launch.work_bytes - 1, None) == binding.VOX_ERR_WORKSPACE
-    assert lib.vox_batch_scenes(fake, L, P((1 << 20) + 64), 1 << 30, None) == binding.VOX_ERR_WORKSPACE
-    bad = binding.VoxBatchLaunch.from_buffer_copy(launch)
-    bad.brick_lg[2] = 4
-    assert lib.vox_batch_scenes(fake, ctypes.byref(bad), fake, 1 << 30, None) == \
-        binding.VOX_ERR_INVALID_ARGUMENT
-    bad = binding.VoxBatchLaunch.from_buffer_copy(launch)
-    bad.rows = 0
-    assert lib.vox_batch_scenes(fake, ctypes.byref(bad), fake, 1 << 30, None) == \
-        binding.VOX_ERR_INVALID_ARGUMENT
+    big = 1 << 40
+    T = ctypes.byref
+    assert lib.vox_batch_scenes(None, 1, 10, None, fake, big, None) == binding.VOX_ERR_INVALID_ARGUMENT
+    assert lib.vox_batch_scenes(P((1 << 20) + 4), 1, 10, None, fake, big, None) == binding.VOX_ERR_INVALID_ARGUMENT
+    assert lib.vox_batch_scenes(fake, 0, 10, None, fake, big, None) == binding.VOX_ERR_INVALID_ARGUMENT
+    assert lib.vox_batch_scenes(fake, 65537, 10, None, fake, big, None) == binding.VOX_ERR_INVALID_ARGUMENT
+    assert lib.vox_batch_scenes(fake, 1, -1, None, fake, big, None) == binding.VOX_ERR_INVALID_ARGUMENT
+    for t in (binding.make_tuning((8, 6, 4)), binding.make_tuning((8, 6, 6), 2), binding.make_tuning(None, 3)):
+        assert lib.vox_batch_scenes(fake, 1, 10, T(t), fake, big, None) == binding.VOX_ERR_INVALID_ARGUMENT
+    t = binding.make_tuning((8, 6, 5))
+    t.reserved[2] = 1
+    assert lib.vox_batch_scenes(fake, 1, 10, T(t), fake, big, None) == binding.VOX_ERR_INVALID_ARGUMENT
+    assert lib.vox_batch_scenes(fake, 1, 10, None, None, big, None) == binding.VOX_ERR_WORKSPACE
+    assert lib.vox_batch_scenes(fake, 1, 10, None, P((1 << 20) + 64), big, None) == binding.VOX_ERR_WORKSPACE
+    assert lib.vox_batch_scenes(fake, 1, 10, None, fake, 1024, None) == binding.VOX_ERR_WORKSPACE
+    assert b"workspace" in lib.vox_last_error()
+
+
+def test_tuning_cache(lib):
+    binding.vox_tuning_cache_clear()
+    try:
+        assert binding.vox_tuning_cache_get((512, 512, 512), 100_000) is None
+        binding.vox_tuning_cache_set((512, 512, 512), 100_000, binding.make_tuning((7, 6, 6), 1))
+        t = binding.vox_tuning_cache_get((512, 512, 512), 120_000)       # same power-of-two bucket
+        assert tuple(t.brick_lg) == (7, 6, 6) and t.fill_wgs_per_cu == 1
+        assert binding.vox_tuning_cache_get((512, 512, 512), 300_000) is None
+        assert binding.vox_tuning_cache_get((512, 512, 256), 100_000) is None
+        # The plain call's workspace follows the cached shape (brick path: > 16384 segments).
+        before = lib.vox_grid_workspace_bytes(100_000, 512, 512, 512)
+        binding.vox_tuning_cache_set((512, 512, 512), 100_000, binding.make_tuning((8, 6, 6)))
+        assert lib.vox_grid_workspace_bytes(100_000, 512, 512, 512) != before
+        binding.vox_tuning_cache_set((512, 512, 512), 100_000, None)
+        assert binding.vox_tuning_cache_get((512, 512, 512), 100_000) is None
+        with pytest.raises(binding.VoxError):
+            binding.vox_tuning_cache_set((512, 512, 512), 10, binding.make_tuning((9, 9, 9)))
+        binding.vox_tuning_cache_set((0, 0, 0), 1 << 20, binding.make_tuning((8, 6, 6)))
+        assert tuple(binding.vox_tuning_cache_get((0, 0, 0), 1 << 20).brick_lg) == (8, 6, 6)
+    finally:
+        binding.vox_tuning_cache_clear()
+
+
+def test_device_status_address(lib):
+    assert lib.vox_device_status(ctypes.c_void_p(1 << 24)) == 1 << 24
+    assert not lib.vox_device_status(None)

@@ -1,5 +1,7 @@
-"""Batched scenes (vox_batch_plan + vox_batch_scenes) against the oracle, and
-HIP-graph capture and replay of a batch (GPU)."""
+"""Batched scenes (vox_batch_scenes over a device vox_scene array) against
+the oracle, the plan's device-side checks, the direct kernels for scenes the
+bricks do not serve, the record-overflow route, and HIP-graph capture and
+replay of a batch (GPU)."""
 
 import numpy as np
 import pytest
@@ -10,7 +12,7 @@ from tests.gpu_helpers import dev, grid_host, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(8, 6, 5), (8, 6, 6), (7, 6, 6), (7, 7, 6)]
+CANDIDATES = [(8, 6, 5, 2), (8, 6, 5, 1), (8, 6, 6, 0), (7, 6, 6, 2), (7, 6, 6, 1), (7, 7, 6, 0)]
 
 
 def random_in(dims, n, seed):
@@ -46,31 +48,43 @@ class Batch:
         return [(s, d, g, c, f) for s, (segs, d, f, base, want), g, c in
                 zip(self.segs, self.specs, self.grids, self.counts)]
 
+    def total(self):
+        return sum(int(x[0].shape[0]) for x in self.specs)
+
+    def d_scenes(self):
+        import torch
+        return torch.from_numpy(binding.scene_table(self.scenes())).to(dev())
+
     def check(self, skip=None):
         skip = skip or {}
         for i, ((segs, dims, flags, base, want), g, c) in enumerate(
                 zip(self.specs, self.grids, self.counts)):
             keep = np.delete(segs, skip.get(i, []), axis=0)
-            if flags & binding.VOX_GRID_CLEAR:
-                exp = oracle.grid(keep, dims)
-            else:
-                exp = oracle.grid(keep, dims, base=base)
+            grid_fn = oracle.grid_euclid if flags & binding.VOX_GRID_EUCLID else oracle.grid
+            exp = grid_fn(keep, dims, base=None if flags & binding.VOX_GRID_CLEAR else base)
             got = grid_host(g)
             if not np.array_equal(got, exp):
                 bad = np.flatnonzero(got != exp)
                 raise AssertionError("scene %d: %d words differ, first %s"
                                      % (i, bad.size, bad[:5].tolist()))
             if want and segs.shape[0]:
-                assert np.array_equal(to_host(c)[:segs.shape[0]], oracle.counts(segs)), i
+                exp_c = (np.diff(oracle.offsets_euclid(segs)) if flags & binding.VOX_GRID_EUCLID
+                         else oracle.counts(segs))
+                assert np.array_equal(to_host(c)[:segs.shape[0]], exp_c), i
 
 
-def run_batch(b, stream=None):
-    import torch
-    table, launch = binding.vox_batch_plan(b.scenes())
-    d_table = torch.from_numpy(table).to(dev())
-    work = binding.workspace(launch.work_bytes, dev())
-    binding.vox_batch_scenes(d_table, launch, work, stream=stream)
-    return binding.vox_read_status(work, stream=stream), launch
+def fixed_part(total, n_scenes):
+    """The workspace of vox_workspace_bytes without its record room (16
+    records of 16 bytes a segment)."""
+    return binding.batch_workspace_bytes(total, n_scenes) - 256 * total
+
+
+def run_batch(b, tuning=None, total=None, work=None, stream=None):
+    total = b.total() if total is None else total
+    if work is None:
+        work = binding.workspace(binding.batch_workspace_bytes(total, len(b.specs)), dev())
+    binding.vox_batch_scenes(b.d_scenes(), len(b.specs), total, work, tuning=tuning, stream=stream)
+    return binding.vox_read_status(work, stream=stream), work
 
 
 def mixed_specs(seed=0):
@@ -93,14 +107,16 @@ def mixed_specs(seed=0):
 
 def test_mixed_batch():
     b = Batch(mixed_specs())
-    status, launch = run_batch(b)
+    status, work = run_batch(b)
     assert status == binding.VOX_OK
+    pieces, direct_all = binding.vox_read_batch_info(work)
+    assert pieces > 0 and not direct_all
     b.check()
 
 
 @pytest.mark.skip(reason="a batch holding a 4-byte-aligned (not 8-byte-aligned) segment array "
-                         "hung the GPU once and the cause was not shown; the brick kernels now take "
-                         "only 8-byte-aligned arrays and vox_batch_plan rejects the others")
+                         "hung the GPU once and the cause was not shown; the brick kernels take only "
+                         "8-byte-aligned arrays (the plan routes others to the direct kernels)")
 def test_unaligned_segments_in_batch():
     import torch
     dims = (128, 128, 64)
@@ -111,10 +127,9 @@ def test_unaligned_segments_in_batch():
     assert view.data_ptr() % 8 == 4
     g = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev())
     g2 = torch.empty_like(g)
-    table, launch = binding.vox_batch_plan([(view, dims, g, None, 1),
-                                            (to_dev(segs), dims, g2, None, 1)])
-    work = binding.workspace(launch.work_bytes, dev())
-    binding.vox_batch_scenes(torch.from_numpy(table).to(dev()), launch, work)
+    table = binding.scene_table([(view, dims, g, None, 1), (to_dev(segs), dims, g2, None, 1)])
+    work = binding.workspace(binding.batch_workspace_bytes(2 * segs.shape[0], 2), dev())
+    binding.vox_batch_scenes(torch.from_numpy(table).to(dev()), 2, 2 * segs.shape[0], work)
     assert binding.vox_read_status(work) == binding.VOX_OK
     exp = oracle.grid(segs, dims)
     assert np.array_equal(grid_host(g), exp) and np.array_equal(grid_host(g2), exp)
@@ -132,17 +147,47 @@ def test_out_of_volume_in_one_scene():
     b.check(skip={1: [5, 77]})
 
 
-@pytest.mark.parametrize("lg", SHAPES)
-def test_batch_every_brick_shape(lg):
-    binding.vox_set_tuning(lg)
-    try:
-        b = Batch(mixed_specs(2)[:6])
-        status, launch = run_batch(b)
-        assert tuple(launch.brick_lg) == lg
-        assert status == binding.VOX_OK
-        b.check()
-    finally:
-        binding.vox_set_tuning(None)
+@pytest.mark.parametrize("cand", CANDIDATES)
+def test_batch_every_tuning(cand):
+    """Per-call tunings (brick shape, fill workgroups per CU): same output."""
+    b = Batch(mixed_specs(2)[:6])
+    status, _ = run_batch(b, tuning=binding.make_tuning(cand[:3], cand[3]))
+    assert status == binding.VOX_OK
+    b.check()
+
+
+def test_direct_scenes_in_batch():
+    """Scenes the bricks do not serve (rows not whole words, the Euclidean N
+    of eq. (1), a volume of 1 x 128 x 129 bricks, more than one histogram
+    holds, and an OR-mode Euclidean scene) run on the
+    direct kernels inside the same call, beside brick scenes."""
+    rng = np.random.default_rng(7)
+    specs = [(random_in((100, 50, 30), 4000, 70), (100, 50, 30), binding.VOX_GRID_CLEAR, None, True),
+             (random_in((256, 128, 64), 20000, 71), (256, 128, 64), binding.VOX_GRID_CLEAR, None, True),
+             (random_in((128, 64, 64), 5000, 72), (128, 64, 64),
+              binding.VOX_GRID_CLEAR | binding.VOX_GRID_EUCLID, None, True),
+             (random_in((32, 8192, 4128), 3000, 73), (32, 8192, 4128), binding.VOX_GRID_CLEAR, None, False)]
+    base = rng.integers(0, 2**32, size=binding.grid_words((96, 40, 20)), dtype=np.uint32)
+    specs.append((random_in((96, 40, 20), 500, 74), (96, 40, 20), binding.VOX_GRID_EUCLID, base, True))
+    b = Batch(specs)
+    status, _ = run_batch(b)
+    assert status == binding.VOX_OK
+    b.check()
+
+
+def test_records_that_do_not_fit_take_the_direct_kernels():
+    """A workspace with no room for the piece records: the direct kernels
+    serve every scene and the output is the same."""
+    b = Batch(mixed_specs(5)[:5])
+    work = binding.workspace(fixed_part(b.total(), 5), dev())
+    status, _ = run_batch(b, work=work)
+    assert status == binding.VOX_OK
+    pieces, direct_all = binding.vox_read_batch_info(work)
+    assert direct_all and pieces > 0
+    b.check()
+    status, work2 = run_batch(b)
+    assert status == binding.VOX_OK and binding.vox_read_batch_info(work2) == (pieces, False)
+    b.check()
 
 
 def test_batch_equals_plain_calls():
@@ -160,38 +205,47 @@ def test_batch_equals_plain_calls():
     b.check()
 
 
-def test_table_that_does_not_fit_writes_nothing():
+def test_scenes_beyond_total_write_nothing():
+    b = Batch(mixed_specs(3)[:5])
+    status, _ = run_batch(b, total=b.total() - 1)
+    assert status == binding.VOX_ERR_BATCH_MISMATCH
+    for g in b.grids[:4]:                         # scene 4 ORs into a random base
+        assert (grid_host(g) == 0x5A5A5A5A).all()
+    assert np.array_equal(grid_host(b.grids[4]), b.specs[4][3])
+
+
+def test_invalid_scene_writes_nothing():
+    """A scene breaking an argument rule (a grid that is not 16-byte aligned,
+    found by the plan kernel on the device) stops the call."""
     import torch
-    small = Batch(mixed_specs(3)[:2])
-    big = Batch(mixed_specs(3)[:5])
-    _, launch_small = binding.vox_batch_plan(small.scenes())
-    table_big, launch_big = binding.vox_batch_plan(big.scenes())
-    assert launch_big.rows > launch_small.rows
-    work = binding.workspace(max(launch_small.work_bytes, launch_big.work_bytes), dev())
-    binding.vox_batch_scenes(torch.from_numpy(table_big).to(dev()), launch_small, work)
-    assert binding.vox_read_status(work) == binding.VOX_ERR_BATCH_MISMATCH
-    for g in big.grids[:4]:                       # scene 4 ORs into a random base
+    b = Batch(mixed_specs(6)[:3])
+    scenes = b.scenes()
+    spare = torch.zeros(binding.grid_words(b.specs[2][1]) + 4, dtype=torch.int32, device=dev())
+    scenes[2] = scenes[2][:2] + (spare[1:],) + scenes[2][3:]     # 4-byte aligned grid
+    d = torch.from_numpy(binding.scene_table(scenes)).to(dev())
+    work = binding.workspace(binding.batch_workspace_bytes(b.total(), 3), dev())
+    binding.vox_batch_scenes(d, 3, b.total(), work)
+    assert binding.vox_read_status(work) == binding.VOX_ERR_INVALID_ARGUMENT
+    assert not to_host(spare).any()
+    for g in b.grids[:2]:
         assert (grid_host(g) == 0x5A5A5A5A).all()
 
 
 def test_graph_capture_and_replay():
-    """One capture, replays with eager work in between, then a second table
-    written to the same device address and replayed under the same graph."""
+    """One capture, replays with eager work in between, then other scenes
+    written into the same device scene array (same count, padded with empty
+    scenes) and replayed under the same graph."""
     import torch
     a = Batch(mixed_specs(4)[:5])
     bspecs = [(random_in(d, 7000, 40 + i), d, binding.VOX_GRID_CLEAR, None, True)
               for i, d in enumerate([(256, 128, 64), (64, 64, 64), (512, 256, 128)])]
+    bspecs += [(np.zeros((0, 6), np.int32), (64, 32, 32), binding.VOX_GRID_CLEAR, None, False)] * 2
     b = Batch(bspecs)
-    table_a, launch_a = binding.vox_batch_plan(a.scenes())
-    table_b, launch_b = binding.vox_batch_plan(b.scenes())
-    bound = binding.VoxBatchLaunch()
-    binding.vox_batch_launch_cover(bound, launch_a)
-    binding.vox_batch_launch_cover(bound, launch_b)
-    d_table = torch.zeros(int(bound.table_bytes), dtype=torch.uint8, device=dev())
-    d_table[:table_a.size].copy_(torch.from_numpy(table_a).to(dev()))
-    work = binding.workspace(bound.work_bytes, dev())
+    total = max(a.total(), b.total())
+    d_scenes = a.d_scenes()
+    work = binding.workspace(binding.batch_workspace_bytes(total, 5), dev())
 
-    binding.vox_batch_scenes(d_table, bound, work)          # eager, before capture
+    binding.vox_batch_scenes(d_scenes, 5, total, work)       # eager, before capture
     assert binding.vox_read_status(work) == binding.VOX_OK
     a.check()
 
@@ -199,7 +253,7 @@ def test_graph_capture_and_replay():
     graph = torch.cuda.CUDAGraph()
     torch.cuda.synchronize()
     with torch.cuda.graph(graph, stream=s):
-        binding.vox_batch_scenes(d_table, bound, work)
+        binding.vox_batch_scenes(d_scenes, 5, total, work, stream=s)
     torch.cuda.synchronize()
     for rep in range(3):
         a.reset(garbage=0x0F0F0F0F + rep)
@@ -210,7 +264,7 @@ def test_graph_capture_and_replay():
         assert binding.vox_read_status(work) == binding.VOX_OK
         a.check()
         del x
-    d_table[:table_b.size].copy_(torch.from_numpy(table_b).to(dev()))
+    d_scenes.copy_(b.d_scenes())
     torch.cuda.synchronize()
     for rep in range(2):
         b.reset(garbage=0x33333333 + rep)

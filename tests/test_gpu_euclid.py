@@ -148,27 +148,27 @@ def test_list_full_fixed_length_sampled():
     assert np.array_equal(got, oracle.voxel_list_euclid(segs[pick]))
 
 
-def test_grid_full_arbitrary_length_sampled():
+def test_grid_full_arbitrary_length_every_word(oracle_jobs_dir):
     """The full 4 194 304-segment arbitrary-length set into a cleared 2048^3
-    volume with the Euclidean N: every voxel of 3 000 sampled segments (the
-    oracle's lists) is set, the counts of those segments match, and the
-    volume holds no more voxels than the counts add up to."""
+    volume with the Euclidean N: every word of the volume (16 MiB block
+    digests of the oracle's volume, computed on CPU shards in the
+    background), its popcount and every segment's count."""
+    import hashlib
     torch = pytest.importorskip("torch")
+    from tests import oracle_jobs
     c = workloads.arbitrary_length()
     segs, dims = c["segs"], c["dims"]
     g, counts = binding.segments_to_grid(to_dev(segs), dims, want_counts=True, euclid=True)
     h_counts = to_host(counts)
-    rng = np.random.default_rng(65)
-    pick = np.sort(rng.choice(segs.shape[0], 3000, replace=False))
-    assert np.array_equal(h_counts[pick], oracle.counts_euclid(segs[pick]))
-    v = oracle.voxel_list_euclid(segs[pick]).astype(np.int64)
-    b = (v[:, 2] * dims[1] + v[:, 1]) * dims[0] + v[:, 0]
-    words = to_host(g.index_select(0, torch.from_numpy(b >> 5).to(dev()))).view(np.uint32)
-    assert np.all((words >> (b & 31).astype(np.uint32)) & 1)
-    set_bits = popcount_words(torch, g)
-    assert 0 < set_bits <= int(h_counts.astype(np.int64).sum())
+    got = grid_host(g)
     del g
     torch.cuda.empty_cache()
+    exp = oracle_jobs.wait_result(oracle_jobs_dir, "arbitrary4m_euclid", timeout=400)
+    assert hashlib.sha256(h_counts.astype(np.int32).tobytes()).hexdigest() == exp["counts_sha256"]
+    dg = oracle_jobs.block_digests(got)
+    bad = [i for i, (a, b) in enumerate(zip(dg, exp["digests"])) if a != b]
+    assert len(dg) == len(exp["digests"]) and not bad, "blocks differ: %s" % bad[:10]
+    assert oracle_jobs.popcount(got) == exp["popcount"]
 
 
 def popcount_words(torch, g, chunk=1 << 25):

@@ -116,59 +116,72 @@ def test_empty_clears():
 SHAPES = [(8, 6, 5), (8, 6, 6), (7, 6, 6), (7, 7, 6)]
 
 
+class tuned:
+    """Autotune cache entries of a brick shape for the given (dims, n) keys
+    of plain calls, removed on exit."""
+
+    def __init__(self, lg, keys, wgs=0):
+        self.lg, self.keys, self.wgs = lg, keys, wgs
+
+    def __enter__(self):
+        for dims, n in self.keys:
+            binding.vox_tuning_cache_set(dims, n, binding.make_tuning(self.lg, self.wgs))
+            t = binding.vox_tuning_cache_get(dims, n)
+            assert tuple(t.brick_lg) == tuple(self.lg)
+
+    def __exit__(self, *exc):
+        binding.vox_tuning_cache_clear()
+
+
 @pytest.mark.parametrize("lg", SHAPES)
 def test_every_brick_shape(lg):
-    """Each compiled brick shape gives the oracle's volume (default restored)."""
-    binding.vox_set_tuning(lg)
-    try:
-        assert binding.vox_get_tuning() == lg
-        c = workloads.arbitrary_length(n=40_000, volume=512)
+    """Each compiled brick shape, taken from the autotune cache for its
+    volume and segment count, gives the oracle's volume."""
+    c = workloads.arbitrary_length(n=40_000, volume=512)
+    dims = (96, 64, 32)
+    rng = np.random.default_rng(11)
+    base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+    segs = random_in(dims, 30_000, 12)
+    with tuned(lg, [(c["dims"], 40_000), (dims, 30_000)]):
         assert_grid(c["segs"], c["dims"])
-        dims = (96, 40, 20)
-        rng = np.random.default_rng(11)
-        base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
-        assert_grid(random_in(dims, 300, 12), dims, base=base)
-        sc = workloads.scenes(n_scenes=3, seed=90)
-        for x in sc:
-            assert_grid(x["segs"], x["dims"])
-    finally:
-        binding.vox_set_tuning(None)
+        assert_grid(segs, dims, base=base)
+
+
+@pytest.mark.parametrize("wgs", [1, 2])
+def test_fill_workgroups_per_cu(wgs):
+    c = workloads.arbitrary_length(n=40_000, volume=512)
+    with tuned((8, 6, 5), [(c["dims"], 40_000)], wgs=wgs):
+        assert_grid(c["segs"], c["dims"])
 
 
 @pytest.mark.parametrize("lg", [(8, 6, 5), (8, 6, 6)])
 def test_full_length_pieces(lg):
     """Pieces as long as the brick is wide: a fill group's chunks overflow its
     table, so its two record sets run one after the other."""
-    binding.vox_set_tuning(lg)
-    try:
-        dims = (512, 64, 64)
-        rng = np.random.default_rng(21)
-        n = 20000  # above the direct path's segment limit
-        y0 = rng.integers(3, 61, n)
-        z0 = rng.integers(3, 61, n)
-        segs = np.stack([np.zeros(n, np.int64), y0, z0, np.full(n, 511), y0 + rng.integers(-3, 4, n),
-                         z0 + rng.integers(-3, 4, n)], 1).astype(np.int32)
-        segs[::2] = segs[::2][:, [3, 4, 5, 0, 1, 2]]  # both directions
+    dims = (512, 64, 64)
+    rng = np.random.default_rng(21)
+    n = 20000  # above the direct path's segment limit
+    y0 = rng.integers(3, 61, n)
+    z0 = rng.integers(3, 61, n)
+    segs = np.stack([np.zeros(n, np.int64), y0, z0, np.full(n, 511), y0 + rng.integers(-3, 4, n),
+                     z0 + rng.integers(-3, 4, n)], 1).astype(np.int32)
+    segs[::2] = segs[::2][:, [3, 4, 5, 0, 1, 2]]  # both directions
+    with tuned(lg, [(dims, n)]):
         assert_grid(segs, dims)
-    finally:
-        binding.vox_set_tuning(None)
 
 
 def test_more_bricks_than_big_stages():
     """A volume of more than 8192 bricks: its histogram stages 4096 segments
     per round (the big stages leave too little LDS for its counters)."""
-    binding.vox_set_tuning((7, 6, 6))
-    try:
-        dims = (2048, 2048, 1088)             # 16 x 32 x 17 = 8704 bricks
+    dims = (2048, 2048, 1088)             # 16 x 32 x 17 = 8704 bricks
+    with tuned((7, 6, 6), [(dims, 20_000)]):
         assert_grid(random_in(dims, 20_000, 23), dims)
-    finally:
-        binding.vox_set_tuning(None)
 
 
 def test_unsupported_shape_rejected():
     with pytest.raises(binding.VoxError):
-        binding.vox_set_tuning((9, 9, 9))
-    assert binding.vox_get_tuning() == (0, 0, 0)
+        binding.vox_tuning_cache_set((512, 512, 512), 10, binding.make_tuning((9, 9, 9)))
+    assert binding.vox_tuning_cache_get((512, 512, 512), 10) is None
 
 
 @pytest.mark.parametrize("n", [16384, 16385])

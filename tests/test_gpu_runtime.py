@@ -15,7 +15,7 @@ import sys
 sys.path.insert(0, %r)
 import numpy as np
 from paper_2009_09500_amd import binding, workloads
-binding.vox_set_tuning((8, 6, 5))      # the library before torch is imported
+binding.vox_tuning_cache_set((256, 256, 256), 256, binding.make_tuning((8, 6, 5)))  # the library before torch
 import torch
 c = workloads.small_uniform(n=256)
 s = torch.from_numpy(c["segs"]).to("cuda:0")

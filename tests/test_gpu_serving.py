@@ -1,5 +1,8 @@
 """The serving loop on the GPU: every request's resident grid, produced in
-mixed chunked batches, equals the oracle's volume of that request alone."""
+mixed chunked batches, equals the oracle's volume of that request alone, at
+the serving workload's own shape (512^3 volumes, requests of 10^4 to 10^6
+edges, 2 000 000-segment batches of up to 32 scenes, admission by measured
+free HBM); a batch whose status reports an error fails its requests only."""
 
 import numpy as np
 import pytest
@@ -11,7 +14,49 @@ from tests.gpu_helpers import grid_host
 pytestmark = pytest.mark.gpu
 
 
-def test_mixed_requests_match_alone():
+def _executor(dims, n_slots, max_batch_segments, max_batch_scenes):
+    ex = serving.GpuExecutor(dims, n_slots=n_slots, max_batch_segments=max_batch_segments,
+                             max_batch_scenes=max_batch_scenes)
+    chunks = {}
+    launch = ex.launch
+
+    def counting_launch(cs):
+        for c in cs:
+            chunks[c.req.rid] = chunks.get(c.req.rid, 0) + 1
+        return launch(cs)
+    ex.launch = counting_launch
+    return ex, chunks
+
+
+def test_serving_shape_mixed_requests_match_alone():
+    n_req = 40
+    reqs = []
+    arrivals = serving.poisson_arrivals(n_req, rate=2000.0, seed=11)
+    for r in range(n_req):
+        w = workloads.wireframe_request(r)                      # seed 1005 + r, 512^3, 1e4..1e6 edges
+        reqs.append(serving.Request(r, w["segs"], w["dims"], float(arrivals[r])))
+    assert max(r.n for r in reqs) > 500_000
+    ex, chunks = _executor((512, 512, 512), 48, 2_000_000, 32)
+    budget = ex.admission_budget()
+    assert budget > sum(r.seg_bytes for r in reqs)
+    sched = serving.Scheduler(n_slots=48, budget_bytes=budget, max_batch_segments=2_000_000,
+                              max_batch_scenes=32)
+    bad = []
+
+    def check(r, executor):
+        if r.failed or not np.array_equal(grid_host(executor.grid(r)), oracle.grid(r.segs, r.dims)):
+            bad.append(r.rid)
+
+    stats = serving.run(reqs, ex, sched, on_done=check)
+    assert ex.status() == 0
+    assert stats["requests"] == n_req and stats["failed_requests"] == 0 and not bad, bad
+    assert stats["batches"] > 1 and stats["latency_p99_ms"] >= stats["latency_p50_ms"] > 0
+    assert max(chunks.values()) > 1                             # a request was cut into chunks
+    assert sched.peak_bytes <= budget
+
+
+def test_small_slots_and_budget():
+    """Few slots and a small segment budget: requests wait for both."""
     reqs = []
     arrivals = serving.poisson_arrivals(24, rate=400.0, seed=7)
     for r in range(24):
@@ -19,7 +64,7 @@ def test_mixed_requests_match_alone():
         reqs.append(serving.Request(r, w["segs"], w["dims"], float(arrivals[r])))
     sched = serving.Scheduler(n_slots=6, budget_bytes=24 * 40_000, max_batch_segments=25_000,
                               max_batch_scenes=5)
-    ex = serving.GpuExecutor((256, 256, 256), n_slots=6)
+    ex, _ = _executor((256, 256, 256), 6, 25_000, 5)
     bad = []
 
     def check(r, executor):
@@ -29,5 +74,29 @@ def test_mixed_requests_match_alone():
     stats = serving.run(reqs, ex, sched, on_done=check)
     assert ex.status() == 0
     assert stats["requests"] == 24 and not bad, bad
-    assert stats["batches"] > 1 and stats["latency_p99_ms"] >= stats["latency_p50_ms"] > 0
     assert sched.peak_bytes <= 24 * 40_000
+
+
+def test_failed_batch_fails_its_requests_only():
+    """Request 3 holds an end point outside the volume: the batch serving it
+    reports the error in its own status copy, its requests are failed, and
+    every request of the other batches equals the oracle."""
+    reqs = []
+    for r in range(8):
+        w = workloads.wireframe_request(r, volume=256, e_lo=1e3, e_hi=2e4)
+        segs = w["segs"].copy()
+        if r == 3:
+            segs[10] = [0, 0, 0, 256, 5, 5]
+        reqs.append(serving.Request(r, segs, w["dims"], 0.0))
+    sched = serving.Scheduler(n_slots=8, budget_bytes=1 << 30, max_batch_segments=30_000, max_batch_scenes=2)
+    ex, _ = _executor((256, 256, 256), 8, 30_000, 2)
+    seen = {}
+
+    def check(r, executor):
+        seen[r.rid] = (r.failed, r.failed or
+                       np.array_equal(grid_host(executor.grid(r)), oracle.grid(r.segs, r.dims)))
+
+    stats = serving.run(reqs, ex, sched, on_done=check)
+    assert seen[3][0] and stats["failed_requests"] >= 1
+    assert all(ok for failed, ok in seen.values() if not failed)
+    assert sum(not f for f, _ in seen.values()) >= 4

@@ -62,11 +62,13 @@ def test_full_scenes_one_batch(oracle_jobs_dir):
     grids = [torch.empty(binding.grid_words(x["dims"]), dtype=torch.int32, device=dev())
              for x in sc]
     segs = [to_dev(x["segs"]) for x in sc]
-    table, launch = binding.vox_batch_plan([(s, x["dims"], g, None, binding.VOX_GRID_CLEAR)
-                                            for s, x, g in zip(segs, sc, grids)])
-    work = binding.workspace(launch.work_bytes, dev())
-    binding.vox_batch_scenes(torch.from_numpy(table).to(dev()), launch, work)
+    table = binding.scene_table([(s, x["dims"], g, None, binding.VOX_GRID_CLEAR)
+                                 for s, x, g in zip(segs, sc, grids)])
+    total = sum(int(s.shape[0]) for s in segs)
+    work = binding.workspace(binding.batch_workspace_bytes(total, len(sc)), dev())
+    binding.vox_batch_scenes(torch.from_numpy(table).to(dev()), len(sc), total, work)
     assert binding.vox_read_status(work) == binding.VOX_OK
+    assert not binding.vox_read_batch_info(work)[1]          # the brick kernels served every scene
     exp = oracle_jobs.wait_result(oracle_jobs_dir, "scenes", timeout=100)
     bad = [s for s, g in enumerate(grids)
            if oracle_jobs.block_digests(grid_host(g)) != exp["digests"][s]]

@@ -22,9 +22,10 @@ class SimExecutor:
     """Runs batches one after another like a single GPU queue: a batch takes
     `fixed + per_seg * segments` seconds from when the previous one ends."""
 
-    def __init__(self, clock, sched, fixed=1e-4, per_seg=1e-8):
+    def __init__(self, clock, sched, fixed=1e-4, per_seg=1e-8, failing_batches=()):
         self.clock, self.sched = clock, sched
         self.fixed, self.per_seg = fixed, per_seg
+        self.failing = set(failing_batches)   # indices of batches whose status reports an error
         self.busy_until = 0.0
         self.uploaded = []
         self.batches = []
@@ -47,10 +48,13 @@ class SimExecutor:
         start = max(self.busy_until, self.clock())
         self.busy_until = start + self.fixed + self.per_seg * segs
         self.batches.append(chunks)
-        return self.busy_until
+        return (self.busy_until, len(self.batches) - 1)
 
     def poll(self, handle):
-        return self.clock() >= handle
+        return self.clock() >= handle[0]
+
+    def batch_status(self, handle):
+        return 1 if handle[1] in self.failing else 0
 
     def release(self, r):
         del self.slot_owner[r.slot]
@@ -159,3 +163,21 @@ def test_poisson_arrivals():
     t = serving.poisson_arrivals(20_000, rate=250.0, seed=3)
     assert np.all(np.diff(t) > 0)
     assert abs(np.mean(np.diff(t)) - 1 / 250.0) < 0.05 / 250.0
+
+
+def test_failed_batch_fails_only_its_requests():
+    """A batch whose device status reports an error (copied per batch) fails
+    every request with a chunk in it, including a chunked request whose last
+    chunk comes later; the requests of the other batches complete normally."""
+    clock = SimClock()
+    sizes = [300, 40, 40, 40, 40, 40, 40, 40]
+    reqs = make_requests(sizes, [0.0] * len(sizes))
+    sched = serving.Scheduler(n_slots=8, budget_bytes=1 << 30, max_batch_segments=100, max_batch_scenes=3)
+    ex = SimExecutor(clock, sched, failing_batches={1})
+    stats = serving.run(reqs, ex, sched, clock=clock, sleep=clock.sleep)
+    bad = {c.req.rid for c in ex.batches[1]}
+    assert bad and len(ex.batches) > 2
+    assert {r.rid for r in reqs if r.failed} == bad
+    assert all(r.done is not None for r in reqs)
+    assert 0 in bad and len(ex.chunks[0]) > 2   # the long request: failed mid-stream, finished later
+    assert stats["failed_requests"] == len(bad) and stats["requests"] == len(reqs)
