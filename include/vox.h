@@ -128,6 +128,23 @@ vox_status vox_segments_to_list32(const vox_segment *d_segs, int64_t n,
                                   int64_t capacity, int64_t *h_total,
                                   void *d_work, size_t work_bytes, void *stream);
 
+/* The lists of vox_segments_to_list with no workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  The workspace is
+ * a 32 MiB device array the library holds on each GPU it runs on (from
+ * module load to the end of the process); the call allocates nothing.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on
+ * one GPU (different streams, or threads without ordering) race: order
+ * them.  Arguments, output, errors and the h_total synchronisation are those
+ * of vox_segments_to_list; device-found errors are reported only through
+ * h_total (the status word lives in the library's array).  Calls whose
+ * workspace, vox_list_workspace_bytes(n, capacity), exceeds 32 MiB (about
+ * 7 million segments, fewer with a large capacity) return VOX_ERR_WORKSPACE
+ * and launch nothing. */
+vox_status vox_segments_to_list_noalloc(const vox_segment *d_segs, int64_t n,
+                                        int64_t *d_offsets, int16_t *d_voxels,
+                                        int64_t capacity, int64_t *h_total, void *stream);
+
 /* ----------------------------------------------------------------- grids */
 
 /* Workspace bytes for vox_segments_to_grid with n segments and the given

@@ -108,6 +108,8 @@ def load(path: str | None = None):
     lib.vox_segments_to_list_euclid.restype = ctypes.c_int
     lib.vox_segments_to_list32.argtypes = [P, i64, P, P, i64, P, P, sz, P]
     lib.vox_segments_to_list32.restype = ctypes.c_int
+    lib.vox_segments_to_list_noalloc.argtypes = [P, i64, P, P, i64, P, P]
+    lib.vox_segments_to_list_noalloc.restype = ctypes.c_int
     lib.vox_grid_workspace_bytes.argtypes = [i64, i32, i32, i32]
     lib.vox_grid_workspace_bytes.restype = sz
     lib.vox_segments_to_grid.argtypes = [P, i64, i32, i32, i32, P, P, u32, P, sz, P]
@@ -199,6 +201,22 @@ def vox_segments_to_list(segs, offsets, voxels, capacity: int, work, want_total:
     st = fn(_ptr(segs), segs.shape[0], _ptr(offsets), _ptr(voxels),
             int(capacity), ctypes.byref(total) if want_total else None,
             _ptr(work), work.numel() * work.element_size(), _stream(stream))
+    if want_total and st in (VOX_ERR_CAPACITY, VOX_ERR_OUT_OF_RANGE):
+        raise VoxError(st, lib.vox_last_error().decode())
+    _check(lib, st)
+    return int(total.value) if want_total else None
+
+
+def vox_segments_to_list_noalloc(segs, offsets, voxels, capacity: int, want_total: bool = False,
+                                 stream=None):
+    """Calls vox_segments_to_list_noalloc (no workspace argument); returns
+    the total if want_total."""
+    lib = load()
+    _check_segs(segs)
+    total = ctypes.c_int64(-1)
+    st = lib.vox_segments_to_list_noalloc(_ptr(segs), segs.shape[0], _ptr(offsets), _ptr(voxels),
+                                          int(capacity), ctypes.byref(total) if want_total else None,
+                                          _stream(stream))
     if want_total and st in (VOX_ERR_CAPACITY, VOX_ERR_OUT_OF_RANGE):
         raise VoxError(st, lib.vox_last_error().decode())
     _check(lib, st)
