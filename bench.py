@@ -147,11 +147,19 @@ def counter_bound(kernel: str, workload: str, sources, avg_ms: float, traffic):
 
 
 def bench_grid(args, torch, binding, workloads, dev, stream):
+    import tempfile
+    from paper_2009_09500_amd import autotune
     c = workloads.arbitrary_length()
     segs_np = c["segs"]
     dims = c["dims"]
     n = segs_np.shape[0]
     segs = torch.from_numpy(segs_np).to(dev)
+    # Launch shape: the autotuner times every candidate on this workload and
+    # installs the fastest for this volume and segment count.
+    with tempfile.TemporaryDirectory() as d:
+        best, times = autotune.tune_grid(segs, dims, reps=2, cache=autotune.TuneCache(os.path.join(d, "t.json")))
+    tuned = {"choice": {"brick_lg": list(best[:3]), "fill_wgs_per_cu": best[3]},
+             "ms_per_candidate": {"%d,%d,%d,%d" % k: round(v, 4) for k, v in times.items()}}
     grid = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev)
     counts = torch.empty(n, dtype=torch.int32, device=dev)
     work = binding.workspace(binding.vox_grid_workspace_bytes(n, dims), dev)
@@ -175,7 +183,7 @@ def bench_grid(args, torch, binding, workloads, dev, stream):
     algo_bytes = 24 * n + 4 * n + grid_bytes
     return {
         "n": n, "dims": dims, "voxels": voxels, "ms_total": ms, "prof": prof,
-        "algo_bytes": algo_bytes, "grid_bytes": grid_bytes, "segs_np": segs_np,
+        "algo_bytes": algo_bytes, "grid_bytes": grid_bytes, "segs_np": segs_np, "tuning": tuned,
     }
 
 
@@ -645,6 +653,7 @@ def main():
                         "2048^3 packed bit-volume + per-segment counts",
             "segments": r["n"], "voxels": r["voxels"], "volume": list(r["dims"]),
             "parallelism": "single GPU",
+            "tuning": r["tuning"],
         },
         "hbm_gbs_algorithmic": r["algo_bytes"] / (ms_step * 1e-3) / 1e9,
         # The whole step (all kernels) on its algorithmic bytes.

@@ -704,6 +704,15 @@ __device__ __forceinline__ Digest digest_piece(const u32x4& rec, const int32_t o
     return g;
 }
 
+// Word of the LDS brick holding bit index idx.  A valid piece stays inside
+// its brick; the mask keeps every LDS access inside the brick whatever a
+// record holds (the address computation needs a mask anyway, so this costs
+// no instruction).
+template <int LGX, int LGY, int LGZ>
+__device__ __forceinline__ uint32_t brick_word(int32_t idx) {
+    return ((uint32_t)idx >> 5) & (BrickShape<LGX, LGY, LGZ>::kWords - 1u);
+}
+
 // Sets the bits of chunk j (voxels klo + j*kChunk ... , at most kChunk of
 // them; exactly kChunk when kFull) of the piece with digest g.
 //
@@ -743,7 +752,7 @@ __device__ __forceinline__ void run_chunk(uint32_t* brick, const Digest& g, uint
     if constexpr (kFull) {
 #pragma unroll 8
         for (int k = 0; k < kChunk; ++k) {
-            atomicOr(&brick[(uint32_t)idx >> 5], 1u << ((uint32_t)idx & 31u));
+            atomicOr(&brick[brick_word<LGX, LGY, LGZ>(idx)], 1u << ((uint32_t)idx & 31u));
             E = E + T;
             const i16x2 C = __builtin_bit_cast(i16x2, E) >> k15;  // -1 where the axis advances
             E = E + __builtin_bit_cast(u16x2, C) * N2;
@@ -753,7 +762,7 @@ __device__ __forceinline__ void run_chunk(uint32_t* brick, const Digest& g, uint
         const uint32_t len = (g.w >> DB::kIdxBits) + 1u;
         const int n = (int)(len - koff < (uint32_t)kChunk ? len - koff : (uint32_t)kChunk);
         for (int k = 0; k < n; ++k) {
-            atomicOr(&brick[(uint32_t)idx >> 5], 1u << ((uint32_t)idx & 31u));
+            atomicOr(&brick[brick_word<LGX, LGY, LGZ>(idx)], 1u << ((uint32_t)idx & 31u));
             E = E + T;
             const i16x2 C = __builtin_bit_cast(i16x2, E) >> k15;
             E = E + __builtin_bit_cast(u16x2, C) * N2;
