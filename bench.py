@@ -155,11 +155,16 @@ def bench_grid(args, torch, binding, workloads, dev, stream):
     n = segs_np.shape[0]
     segs = torch.from_numpy(segs_np).to(dev)
     # Launch shape: the autotuner times every candidate on this workload and
-    # installs the fastest for this volume and segment count.
-    with tempfile.TemporaryDirectory() as d:
-        best, times = autotune.tune_grid(segs, dims, reps=2, cache=autotune.TuneCache(os.path.join(d, "t.json")))
-    tuned = {"choice": {"brick_lg": list(best[:3]), "fill_wgs_per_cu": best[3]},
-             "ms_per_candidate": {"%d,%d,%d,%d" % k: round(v, 4) for k, v in times.items()}}
+    # installs the fastest for this volume and segment count (--no-tune: the
+    # library default, as in the profiler runs).
+    if args.no_tune:
+        tuned = {"choice": "library default (not tuned in this run)"}
+    else:
+        with tempfile.TemporaryDirectory() as d:
+            best, times = autotune.tune_grid(segs, dims, reps=2,
+                                             cache=autotune.TuneCache(os.path.join(d, "t.json")))
+        tuned = {"choice": {"brick_lg": list(best[:3]), "fill_wgs_per_cu": best[3]},
+                 "ms_per_candidate": {"%d,%d,%d,%d" % k: round(v, 4) for k, v in times.items()}}
     grid = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev)
     counts = torch.empty(n, dtype=torch.int32, device=dev)
     work = binding.workspace(binding.vox_grid_workspace_bytes(n, dims), dev)
@@ -444,7 +449,7 @@ def bench_serving(args, torch, binding, workloads, dev, n_requests=1000):
     r of every run is the icosphere of seed 1005 + r."""
     from paper_2009_09500_amd import serving
     pool = _wireframe_pool(n_requests)
-    pinned = [torch.from_numpy(w["segs"]).pin_memory() for w in pool]
+    pinned = [serving.GpuExecutor.pin(w["segs"]) for w in pool]
     dims = pool[0]["dims"]
     vox = [int((np.abs(w["segs"][:, 3:].astype(np.int64) - w["segs"][:, :3]).max(1) + 1).sum())
            for w in pool]
@@ -480,6 +485,8 @@ def bench_serving(args, torch, binding, workloads, dev, n_requests=1000):
                     "%d..%d edges) into resident 512^3 grids" % (n_requests, min(edges), max(edges)),
         "requests_per_rate": n_requests,
         "admission_budget_bytes": budget,
+        "upload": "segments as int16 over PCIe (coordinates < 512), widened to int32 on the device",
+        "upload_bytes_total": int(sum(p.numel() * p.element_size() for p in pinned)),
         "batch_workspace_bytes": int(ex.work.numel()),
         "saturation": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sat.items()},
         "poisson_sweep": sweep,
@@ -593,6 +600,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuning (profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()

@@ -86,13 +86,18 @@ typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
 __host__ __device__ constexpr uint64_t up256(uint64_t v) { return (v + 255u) & ~uint64_t(255); }
 
-// Piece record (16 bytes): start point, direction and the k-window inside
-// its brick; everything the fill needs, so it reads records and never
-// gathers segments.
+// Piece record (16 bytes): the stepping state of a piece at its first voxel
+// (k = klo), made by the scatter, which has the segment at hand, so that the
+// fill only unpacks it and never gathers segments.  Minor axes a < b in axis
+// order, m the dominant axis (the first of the longest ones):
+//   e  the minor axes' error terms as biased 16-bit halves u = r - 2N + 32768
+//      (r the remainder of eq. (3)'s division at k = klo)
+//   t  their increments, 2a | 2b << 16
+//   v  m | nega << 2 | negb << 3 | negm << 4 | 2N << 16 (2N = 2 when N = 0)
+//   w  the bit index of the voxel at klo inside the brick
+//      | (voxels - 1) << (log2 of the brick's voxel count)
 struct Piece {
-    uint16_t p0[3];
-    int16_t d[3];
-    uint16_t klo, khi;  // inclusive
+    uint32_t e, t, v, w;
 };
 static_assert(sizeof(Piece) == 16, "16-byte piece records");
 
@@ -417,8 +422,8 @@ __device__ __forceinline__ void walk_init(WalkState& w, const StagedSeg& g, cons
 
 // Walks the ordered staged segments: each wave takes the next 64 in order
 // and steps all of them one brick at a time until the wave's last segment
-// ends.  emit(brick id, klo, khi, staged index) per piece, [klo, khi] being
-// the segment's k-window inside the brick.
+// ends.  emit(brick id, klo, khi, staged index, brick x, y, z) per piece,
+// [klo, khi] being the segment's k-window inside the brick.
 template <int kN, typename Emit>
 __device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeom& bg, Emit emit) {
     const uint32_t lane = __lane_id();
@@ -440,7 +445,7 @@ __device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeo
                 emit(__umul24(__umul24((uint32_t)w.c[2].b, (uint32_t)bg.nb[1]) + (uint32_t)w.c[1].b,
                               (uint32_t)bg.nb[0]) +
                          (uint32_t)w.c[0].b,
-                     w.klo, km == kNever ? w.N : km - 1u, j);
+                     w.klo, km == kNever ? w.N : km - 1u, j, w.c[0].b, w.c[1].b, w.c[2].b);
             // The rest with selects only (lanes step different segments).
             const bool go = active && km != kNever;
 #pragma unroll
@@ -464,7 +469,9 @@ __device__ __forceinline__ void hist_row(const BrickScene& sc, uint32_t g, Stage
     for (int64_t base = lo; base < hi; base += kN) {
         const uint32_t cnt = (uint32_t)(hi - base < kN ? hi - base : kN);
         stage_segments(sc.segs, base, cnt, bg, st, sc.counts, bad);
-        walk_ordered(st, bg, [&](uint32_t b, uint32_t, uint32_t, uint32_t) { atomicAdd(&lh[b], 1u); });
+        walk_ordered(st, bg, [&](uint32_t b, uint32_t, uint32_t, uint32_t, int32_t, int32_t, int32_t) {
+            atomicAdd(&lh[b], 1u);
+        });
         lds_barrier();
     }
     if (bad) atomicOr(wv.status, kStatusOutOfRange);
@@ -584,6 +591,46 @@ __global__ __launch_bounds__(kBaseBlock) void k_brick_base(uint8_t* __restrict__
     }
 }
 
+// The record of the piece of staged segment g with k-window [klo, khi] in
+// brick (bx, by, bz).  Every volume side is at most 16384, so N < 2^15 and
+// eq. (3)'s numerator 2 klo a + N stays below 2^31 (divmod_down's domain).
+__device__ __forceinline__ Piece piece_record(const StagedSeg& g, uint32_t klo, uint32_t khi, int32_t bx,
+                                              int32_t by, int32_t bz, const BrickGeom& bg) {
+    int32_t p0[3], d[3];
+    uint32_t ad[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        p0[ax] = g.p0[ax];
+        d[ax] = (int32_t)g.p1[ax] - p0[ax];
+        ad[ax] = (uint32_t)(d[ax] < 0 ? -d[ax] : d[ax]);
+    }
+    const uint32_t N = ad[0] > ad[1] ? (ad[0] > ad[2] ? ad[0] : ad[2]) : (ad[1] > ad[2] ? ad[1] : ad[2]);
+    const uint32_t m = ad[0] == N ? 0u : (ad[1] == N ? 1u : 2u);
+    const uint32_t aa = m == 0 ? ad[1] : ad[0], ab = m == 2 ? ad[1] : ad[2];
+    const int32_t da = m == 0 ? d[1] : d[0], db = m == 2 ? d[1] : d[2];
+    const int32_t dm = m == 0 ? d[0] : (m == 1 ? d[1] : d[2]);
+    const uint32_t nega = da < 0, negb = db < 0, negm = dm < 0;
+    const uint32_t two_n = N > 0 ? 2u * N : 2u;
+    uint32_t qa = 0, ra = 0, qb = 0, rb = 0;
+    if (N > 0) {
+        const float rcpd = rcp_down(two_n);
+        divmod_down(2u * __umul24(klo, aa) + N - nega, two_n, rcpd, qa, ra);
+        divmod_down(2u * __umul24(klo, ab) + N - negb, two_n, rcpd, qb, rb);
+    }
+    const int32_t vm = negm ? -(int32_t)klo : (int32_t)klo;
+    const int32_t va = nega ? -(int32_t)qa : (int32_t)qa, vb = negb ? -(int32_t)qb : (int32_t)qb;
+    const int32_t x = p0[0] + (m == 0 ? vm : va) - (bx << bg.lg[0]);
+    const int32_t y = p0[1] + (m == 1 ? vm : (m == 0 ? va : vb)) - (by << bg.lg[1]);
+    const int32_t z = p0[2] + (m == 2 ? vm : vb) - (bz << bg.lg[2]);
+    Piece pc;
+    pc.e = ((ra + 32768u - two_n) & 0xFFFFu) | ((rb + 32768u - two_n) << 16);
+    pc.t = (2u * aa) | ((2u * ab) << 16);
+    pc.v = m | (nega << 2) | (negb << 3) | (negm << 4) | (two_n << 16);
+    pc.w = (uint32_t)(x + (y << bg.lg[0]) + (z << (bg.lg[0] + bg.lg[1]))) |
+           ((khi - klo) << (bg.lg[0] + bg.lg[1] + bg.lg[2]));
+    return pc;
+}
+
 __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restrict__ work) {
     extern __shared__ uint32_t cur[];
     __shared__ Stage<kStage> st;
@@ -605,18 +652,10 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restric
     for (int64_t base = lo; base < hi; base += kStage) {
         const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
         stage_segments(sc.segs, base, cnt, bg, st, nullptr, bad);
-        walk_ordered(st, bg, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j) {
+        walk_ordered(st, bg, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j, int32_t bx, int32_t by,
+                                 int32_t bz) {
             const uint32_t pos = atomicAdd(&cur[b], 1u);
-            const StagedSeg sg = st.seg[j];
-            Piece pc;
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                pc.p0[ax] = sg.p0[ax];
-                pc.d[ax] = (int16_t)((int32_t)sg.p1[ax] - (int32_t)sg.p0[ax]);
-            }
-            pc.klo = (uint16_t)klo;
-            pc.khi = (uint16_t)khi;
-            recs[pos] = pc;
+            recs[pos] = piece_record(st.seg[j], klo, khi, bx, by, bz, bg);
         });
         lds_barrier();
     }
@@ -657,38 +696,11 @@ struct DigestBits {
                   "bit index and length share a word");
 };
 
+// The stepping state of a record's piece (the record holds it but for the
+// strides, which follow from the axes, the signs and the brick shape).
 template <int LGX, int LGY, int LGZ>
-__device__ __forceinline__ Digest digest_piece(const u32x4& rec, const int32_t org[3]) {
-    using DB = DigestBits<LGX, LGY, LGZ>;
-    // Record words: x0|y0<<16, z0|dx<<16, dy|dz<<16, klo|khi<<16.
-    const int32_t p0[3] = {(int32_t)(rec.x & 0xFFFFu), (int32_t)(rec.x >> 16), (int32_t)(rec.y & 0xFFFFu)};
-    const int32_t d[3] = {(int32_t)(int16_t)(rec.y >> 16), (int32_t)(int16_t)(rec.z & 0xFFFFu),
-                          (int32_t)(int16_t)(rec.z >> 16)};
-    const uint32_t klo = rec.w & 0xFFFFu, len = (rec.w >> 16) - klo + 1u;
-    const uint32_t a0 = (uint32_t)(d[0] < 0 ? -d[0] : d[0]);
-    const uint32_t a1 = (uint32_t)(d[1] < 0 ? -d[1] : d[1]);
-    const uint32_t a2 = (uint32_t)(d[2] < 0 ? -d[2] : d[2]);
-    const uint32_t N = a0 > a1 ? (a0 > a2 ? a0 : a2) : (a1 > a2 ? a1 : a2);
-    // Dominant axis m (first of the maximal ones); minor axes a < b.
-    const uint32_t m = a0 == N ? 0u : (a1 == N ? 1u : 2u);
-    const uint32_t aa = m == 0 ? a1 : a0, ab = m == 2 ? a1 : a2;
-    const int32_t da = m == 0 ? d[1] : d[0], db = m == 2 ? d[1] : d[2], dm = m == 0 ? d[0] : (m == 1 ? d[1] : d[2]);
-    const uint32_t nega = da < 0, negb = db < 0, negm = dm < 0;
-    // A single-voxel piece (N = 0) is given 2N = 2: its minor axes never
-    // advance (a = b = 0), and every division below stays defined.
-    const uint32_t two_n = N > 0 ? 2u * N : 2u;
-    uint32_t qa = 0, ra = 0, qb = 0, rb = 0;
-    if (N > 0) {
-        const float rcpd = rcp_down(two_n);
-        divmod_down(2u * __umul24(klo, aa) + N - nega, two_n, rcpd, qa, ra);
-        divmod_down(2u * __umul24(klo, ab) + N - negb, two_n, rcpd, qb, rb);
-    }
-    // Voxel at klo, relative to the brick origin.
-    const int32_t vm = negm ? -(int32_t)klo : (int32_t)klo;
-    const int32_t va = nega ? -(int32_t)qa : (int32_t)qa, vb = negb ? -(int32_t)qb : (int32_t)qb;
-    const int32_t x = p0[0] - org[0] + (m == 0 ? vm : va);
-    const int32_t y = p0[1] - org[1] + (m == 1 ? vm : (m == 0 ? va : vb));
-    const int32_t z = p0[2] - org[2] + (m == 2 ? vm : vb);
+__device__ __forceinline__ Digest digest_record(const u32x4& rec) {
+    const uint32_t m = rec.z & 3u, nega = (rec.z >> 2) & 1u, negb = (rec.z >> 3) & 1u, negm = (rec.z >> 4) & 1u;
     // Strides are powers of two: log2 of the dominant axis' and of the
     // minor axes' strides.
     const uint32_t shm = m == 0 ? 0u : (m == 1 ? (uint32_t)LGX : (uint32_t)(LGX + LGY));
@@ -696,11 +708,11 @@ __device__ __forceinline__ Digest digest_piece(const u32x4& rec, const int32_t o
     const int32_t sm = negm ? -(1 << shm) : (1 << shm);
     const int32_t sa = nega ? (1 << sha) : -(1 << sha), sb = negb ? (1 << shb) : -(1 << shb);
     Digest g;
-    g.e = ((ra + 32768u - two_n) & 0xFFFFu) | ((rb + 32768u - two_n) << 16);
-    g.t = (2u * aa) | ((2u * ab) << 16);
+    g.e = rec.x;
+    g.t = rec.y;
     g.s = ((uint32_t)sa & 0xFFFFu) | ((uint32_t)sb << 16);
-    g.v = ((uint32_t)sm & 0xFFFFu) | (two_n << 16);
-    g.w = (uint32_t)(x + (y << LGX) + (z << (LGX + LGY))) | ((len - 1u) << DB::kIdxBits);
+    g.v = ((uint32_t)sm & 0xFFFFu) | (rec.z & 0xFFFF0000u);
+    g.w = rec.w;
     return g;
 }
 
@@ -771,15 +783,15 @@ __device__ __forceinline__ void run_chunk(uint32_t* brick, const Digest& g, uint
     }
 }
 
-// Voxels of a piece record (its k-window klo | khi << 16).  A piece lies in
-// one brick and its dominant coordinate moves by one voxel per k, so it has
-// at most as many voxels as the brick's longest side; a record outside that
-// (which the scatter never writes) counts as empty, so that every loop of
-// the fill stays bounded whatever the workspace holds.
-template <int kMaxLg>
+// Voxels of a piece record (from its last word).  A piece lies in one brick
+// and its dominant coordinate moves by one voxel per k, so it has at most as
+// many voxels as the brick's longest side; a record outside that (which the
+// scatter never writes) counts as empty, so that every loop of the fill
+// stays bounded whatever the workspace holds.
+template <int LGX, int LGY, int LGZ>
 __device__ __forceinline__ uint32_t record_length(uint32_t w) {
-    const uint32_t klo = w & 0xFFFFu, khi = w >> 16;
-    return (khi >= klo && khi - klo < (1u << kMaxLg)) ? khi - klo + 1u : 0u;
+    const uint32_t len = (w >> DigestBits<LGX, LGY, LGZ>::kIdxBits) + 1u;
+    return len <= (1u << BrickShape<LGX, LGY, LGZ>::kMaxLg) ? len : 0u;
 }
 
 // A piece record, read once: a non-temporal load, so that the stream of
@@ -922,8 +934,8 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         u32x4 rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
         while (gbase < q_hi) {
             const u32x4 r0 = rn0, r1 = rn1;
-            const uint32_t len0 = gbase + lane < q_hi ? record_length<Shape::kMaxLg>(r0.w) : 0u;
-            const uint32_t len1 = gbase + kWave + lane < q_hi ? record_length<Shape::kMaxLg>(r1.w) : 0u;
+            const uint32_t len0 = gbase + lane < q_hi ? record_length<LGX, LGY, LGZ>(r0.w) : 0u;
+            const uint32_t len1 = gbase + kWave + lane < q_hi ? record_length<LGX, LGY, LGZ>(r1.w) : 0u;
             // The records have arrived (len0/len1 are made from them); the next
             // group's loads are issued only now, so no later wait for these
             // records waits for them too.
@@ -935,8 +947,8 @@ void k_brick_fill(uint8_t* __restrict__ work) {
 
             // This lane's pieces as stepping states (read by the lanes that
             // run their chunks).
-            const Digest d0 = digest_piece<LGX, LGY, LGZ>(r0, org);
-            const Digest d1 = digest_piece<LGX, LGY, LGZ>(r1, org);
+            const Digest d0 = digest_record<LGX, LGY, LGZ>(r0);
+            const Digest d1 = digest_record<LGX, LGY, LGZ>(r1);
             const uint32_t nf0 = len0 / kChunk, pl0 = len0 % kChunk;
             const uint32_t nf1 = len1 / kChunk, pl1 = len1 % kChunk;
             // Length class of a partial chunk: 3 (longest) ... 0, or 4 (none).

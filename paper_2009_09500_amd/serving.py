@@ -296,17 +296,37 @@ class GpuExecutor:
         free, _ = self.torch.cuda.mem_get_info(self.device)
         return max(int(free) - self.reserve, 0)
 
+    @staticmethod
+    def pin(segs: np.ndarray):
+        """Pinned host copy of a request's segments for upload: int16 when
+        every coordinate fits (half the bytes over PCIe; volumes up to 32768
+        a side), else int32."""
+        import torch
+        a = np.ascontiguousarray(segs)
+        if a.size and a.min() >= -32768 and a.max() <= 32767:
+            a = a.astype(np.int16)
+        return torch.from_numpy(a).pin_memory()
+
     def upload(self, r: Request):
+        """Copies the request's segments to the device on the copy stream.
+        int16 uploads are widened to the library's int32 segments on the
+        device (a dtype conversion on the copy stream)."""
         torch = self.torch
         host = r.dev.get("pinned")
         if host is None:
-            host = torch.from_numpy(np.ascontiguousarray(r.segs)).pin_memory()
+            host = self.pin(r.segs)
         with torch.cuda.stream(self.copy_stream):
             d = torch.empty((max(r.n, 1), 6), dtype=torch.int32, device=self.device)
-            d[:r.n].copy_(host, non_blocking=True)
+            if host.dtype == torch.int16:
+                staged = torch.empty((max(r.n, 1), 6), dtype=torch.int16, device=self.device)
+                staged[:r.n].copy_(host, non_blocking=True)
+                d[:r.n].copy_(staged[:r.n])
+                r.dev["staged"] = staged
+            else:
+                d[:r.n].copy_(host, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.copy_stream)
-        r.dev.update(d_segs=d, uploaded=ev, host=host)
+        r.dev.update(d_segs=d, uploaded=ev, host=host, upload_bytes=host.numel() * host.element_size())
 
     def launch(self, chunks):
         torch, binding = self.torch, self.binding
@@ -348,6 +368,7 @@ class GpuExecutor:
 
     def release(self, r: Request):
         r.dev.pop("d_segs", None)
+        r.dev.pop("staged", None)
         r.dev.pop("uploaded", None)
 
     def grid(self, r: Request):
