@@ -190,8 +190,10 @@ vox_status vox_segments_to_grid(const vox_segment *d_segs, int64_t n,
  * axis a; all zero selects the library default.  The choice changes only
  * speed and workspace size, never the output.  Supported shapes:
  * 2^8 x 2^6 x 2^5, 2^8 x 2^6 x 2^6, 2^7 x 2^6 x 2^6, 2^7 x 2^7 x 2^6.
- * fill_wgs_per_cu: fill workgroups per compute unit (0 = the shape's
- * default; 1 or 2 for 64 KiB bricks, 1 for 128 KiB bricks).  reserved: zero. */
+ * fill_wgs_per_cu: fill workgroups per compute unit: 1 (one of 1024
+ * threads) or 2 (two of 512) for 64 KiB bricks, 1 for 128 KiB bricks; 0 =
+ * the default (64 KiB bricks: 2, or 1 when the launch has fewer bricks than
+ * two per compute unit).  reserved: zero. */
 typedef struct vox_tuning {
     int32_t brick_lg[3];
     int32_t fill_wgs_per_cu;

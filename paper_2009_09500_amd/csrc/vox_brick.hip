@@ -174,14 +174,33 @@ __device__ __forceinline__ WorkView work_of(uint8_t* work, const TableView& tv) 
 // from its own XCD's queue first and then from the others.
 constexpr int kXcds = 8;
 
+// Brick of the c-th claim on queue x.
+__device__ __forceinline__ uint32_t queue_brick(uint32_t x, uint32_t c) {
+    return (c >> 3) * (8u * kXcds) + x * 8u + (c & 7u);
+}
+
+// A device-scope atomic costs a full memory round trip, so once its own queue
+// is empty a workgroup reads all the other counters at once (one round trip)
+// and claims only from queues that still hold bricks, rather than trying
+// each in turn; it stops when every queue is empty (counters only grow, so
+// every pass either claims or finds fewer queues open).
 __device__ __forceinline__ uint32_t claim_brick(uint32_t* queues, uint32_t xcd, uint32_t NB) {
-    for (uint32_t k = 0; k < (uint32_t)kXcds; ++k) {
-        const uint32_t x = (xcd + k) & (kXcds - 1);
-        const uint32_t c = atomicAdd(&queues[x], 1u);
-        const uint32_t g = (c >> 3) * (8u * kXcds) + x * 8u + (c & 7u);
-        if (g < NB) return g;
+    uint32_t g = queue_brick(xcd, atomicAdd(&queues[xcd], 1u));
+    if (g < NB) return g;
+    for (;;) {
+        uint32_t c[kXcds];
+#pragma unroll
+        for (int x = 0; x < kXcds; ++x) c[x] = __hip_atomic_load(&queues[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool open = false;
+#pragma unroll
+        for (uint32_t x = 0; x < (uint32_t)kXcds; ++x) {
+            if (x == xcd || queue_brick(x, c[x]) >= NB) continue;
+            open = true;
+            g = queue_brick(x, atomicAdd(&queues[x], 1u));
+            if (g < NB) return g;
+        }
+        if (!open) return NB;
     }
-    return NB;
 }
 
 // Histogram row of workgroup w out of G.  Each XCD takes a contiguous block
@@ -230,7 +249,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_brick_plan(const vox_scene* __re
         uint64_t hist = 0, n = 0;
         if (i < L.n_scenes) {
             const vox_scene in = has_one ? one : scenes[i];
-            if (!plan_scene(in, L.lg, b)) atomicOr(&bad_s, 1u);
+            if (!plan_scene(in, L.lg, L.segs_per_row, b)) atomicOr(&bad_s, 1u);
             isd = (b.flags & kSceneDirect) ? 1u : 0u;
             rows = b.rows;
             nb = isd ? 0u : b.bg.nbricks;
@@ -350,8 +369,8 @@ __device__ __forceinline__ uint32_t order_bin(const StagedSeg& g, const BrickGeo
 // of the in-volume ones.
 template <int kN>
 __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs, int64_t base, uint32_t cnt,
-                                               const BrickGeom& bg, Stage<kN>& st, int32_t* __restrict__ counts,
-                                               bool& bad) {
+                                               const BrickGeom& bg, bool euclid, Stage<kN>& st,
+                                               int32_t* __restrict__ counts, bool& bad) {
     if (threadIdx.x < kOrderBins) st.bins[threadIdx.x] = 0;
     lds_barrier();
     // Bit t of `mine` marks this thread's t-th segment as in the volume.
@@ -359,9 +378,17 @@ __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs,
     int slot = 0;
     for (uint32_t t = threadIdx.x; t < cnt; t += kHistBlock, ++slot) {
         const Seg g = load_seg<true>(segs, base + t);
+        const bool inside = in_volume(g, bg);
         if (counts) {
-            const int64_t c = seg_length(g) + 1;
-            counts[base + t] = (int32_t)(c > 0x7FFFFFFFll ? 0x7FFFFFFFll : c);
+            // Counts: N + 1 for the Chebyshev N; with the Euclidean N 0
+            // outside the volume here, the voxels after duplicate removal
+            // inside it from the histogram's wave pass (euclid_count_wave).
+            if (euclid) {
+                if (!inside) counts[base + t] = 0;
+            } else {
+                const int64_t c = seg_length(g) + 1;
+                counts[base + t] = (int32_t)(c > 0x7FFFFFFFll ? 0x7FFFFFFFll : c);
+            }
         }
         StagedSeg s;
 #pragma unroll
@@ -370,7 +397,7 @@ __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs,
             s.p1[ax] = (uint16_t)g.p1[ax];
         }
         st.seg[t] = s;
-        if (in_volume(g, bg)) {
+        if (inside) {
             mine |= 1u << slot;
             atomicAdd(&st.bins[order_bin(s, bg)], 1u);
         } else {
@@ -399,12 +426,19 @@ static_assert(kStage / kHistBlock <= 32 && kStageBig / kHistBlock <= 32 && kStag
 
 struct WalkState {
     AxisCross c[3];
-    uint32_t N, klo;  // Chebyshev length, first k inside the current brick
+    uint32_t N, klo;  // length (Chebyshev or Euclidean), first k inside the current brick
 };
 
-__device__ __forceinline__ void walk_init(WalkState& w, const StagedSeg& g, const BrickGeom& bg) {
+// floor(sqrt(s)) for s < 2^31: the double square root is correctly rounded,
+// so its integer part is exact in this range.
+__device__ __forceinline__ uint32_t isqrt31(uint32_t s) { return (uint32_t)__dsqrt_rn((double)s); }
+
+// Walk state at k = 0.  Every coordinate of eq. (3) is monotone in k for any
+// N >= max |d_a|, so the brick crossings follow the same rules under the
+// Euclidean N of eq. (1) (N = floor |P1 - P0| >= max |d_a|).
+__device__ __forceinline__ void walk_init(WalkState& w, const StagedSeg& g, const BrickGeom& bg, bool euclid) {
     int32_t p0[3], p1[3];
-    uint32_t a[3], neg[3], N = 0;
+    uint32_t a[3], neg[3], N = 0, ss = 0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         p0[ax] = g.p0[ax];
@@ -413,19 +447,62 @@ __device__ __forceinline__ void walk_init(WalkState& w, const StagedSeg& g, cons
         neg[ax] = d < 0;
         a[ax] = (uint32_t)(d < 0 ? -d : d);
         N = a[ax] > N ? a[ax] : N;
+        ss += a[ax] * a[ax];
     }
+    if (euclid) N = isqrt31(ss);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) cross_init(w.c[ax], p0[ax], p1[ax], a[ax], neg[ax], N, bg.lg[ax]);
     w.N = N;
     w.klo = 0;
 }
 
+// Voxels of an in-volume segment under the Euclidean N (consecutive
+// duplicates removed), counted by the 64 lanes of a wave together: 1 + the
+// steps k = 1..N at which some axis moves.  With r_a(k) = (2k a + N - neg_a)
+// mod 2N, the remainder of eq. (3)'s division, axis a moves at step k
+// exactly when r_a(k) < 2a (r_a(k) = r_a(k-1) + 2a, less 2N when it moves).
+// Lane l takes k = 1 + l, 65 + l, ...: its remainders advance by
+// (128 a) mod 2N a round.  N <= 16384 in a brick scene, inside the
+// divisions' domain.  Every lane returns the count.
+__device__ __forceinline__ uint32_t euclid_count_wave(const StagedSeg& g, uint32_t lane) {
+    uint32_t a[3], neg[3], ss = 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int32_t d = (int32_t)g.p1[ax] - (int32_t)g.p0[ax];
+        neg[ax] = d < 0;
+        a[ax] = (uint32_t)(d < 0 ? -d : d);
+        ss += a[ax] * a[ax];
+    }
+    const uint32_t N = isqrt31(ss);
+    if (N == 0) return 1u;
+    const uint32_t two_n = 2u * N;
+    const float rcpd = rcp_down(two_n);
+    uint32_t r[3], D[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        uint32_t q;
+        divmod_down(2u * a[ax] * (1u + lane) + N - neg[ax], two_n, rcpd, q, r[ax]);
+        divmod_down(128u * a[ax], two_n, rcpd, q, D[ax]);
+    }
+    uint32_t moves = 0;
+    for (uint32_t k = 1u + lane; k - lane <= N; k += kWave) {
+        const bool mv = k <= N && (r[0] < 2u * a[0] || r[1] < 2u * a[1] || r[2] < 2u * a[2]);
+        moves += (uint32_t)__popcll(__ballot(mv));
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const uint32_t t = r[ax] + D[ax];
+            r[ax] = t >= two_n ? t - two_n : t;
+        }
+    }
+    return 1u + moves;
+}
+
 // Walks the ordered staged segments: each wave takes the next 64 in order
 // and steps all of them one brick at a time until the wave's last segment
-// ends.  emit(brick id, klo, khi, staged index, brick x, y, z) per piece,
+// ends.  emit(brick id, klo, khi, staged index, brick x, y, z, N) per piece,
 // [klo, khi] being the segment's k-window inside the brick.
 template <int kN, typename Emit>
-__device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeom& bg, Emit emit) {
+__device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeom& bg, bool euclid, Emit emit) {
     const uint32_t lane = __lane_id();
     const uint32_t nvalid = st.nvalid;
     for (uint32_t base = threadIdx.x - lane; base < nvalid; base += kHistBlock) {
@@ -435,7 +512,7 @@ __device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeo
         WalkState w = {};
         if (active) {
             j = st.order[i];
-            walk_init(w, st.seg[j], bg);
+            walk_init(w, st.seg[j], bg, euclid);
         }
         while (__ballot(active)) {
             uint32_t km = w.c[0].kn < w.c[1].kn ? w.c[0].kn : w.c[1].kn;
@@ -445,7 +522,7 @@ __device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeo
                 emit(__umul24(__umul24((uint32_t)w.c[2].b, (uint32_t)bg.nb[1]) + (uint32_t)w.c[1].b,
                               (uint32_t)bg.nb[0]) +
                          (uint32_t)w.c[0].b,
-                     w.klo, km == kNever ? w.N : km - 1u, j, w.c[0].b, w.c[1].b, w.c[2].b);
+                     w.klo, km == kNever ? w.N : km - 1u, j, w.c[0].b, w.c[1].b, w.c[2].b, w.N);
             // The rest with selects only (lanes step different segments).
             const bool go = active && km != kNever;
 #pragma unroll
@@ -465,13 +542,24 @@ __device__ __forceinline__ void hist_row(const BrickScene& sc, uint32_t g, Stage
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) lh[b] = 0;
     int64_t lo, hi;
     seg_range(sc.n, (int)g, (int)sc.rows, lo, hi);
+    const bool euclid = (sc.flags & kSceneEuclid) != 0;
     bool bad = false;
     for (int64_t base = lo; base < hi; base += kN) {
         const uint32_t cnt = (uint32_t)(hi - base < kN ? hi - base : kN);
-        stage_segments(sc.segs, base, cnt, bg, st, sc.counts, bad);
-        walk_ordered(st, bg, [&](uint32_t b, uint32_t, uint32_t, uint32_t, int32_t, int32_t, int32_t) {
-            atomicAdd(&lh[b], 1u);
-        });
+        stage_segments(sc.segs, base, cnt, bg, euclid, st, sc.counts, bad);
+        walk_ordered(st, bg, euclid,
+                     [&](uint32_t b, uint32_t, uint32_t, uint32_t, int32_t, int32_t, int32_t, uint32_t) {
+                         atomicAdd(&lh[b], 1u);
+                     });
+        if (euclid && sc.counts) {
+            // The in-volume segments' counts, one segment per wave at a time.
+            const uint32_t lane = __lane_id();
+            for (uint32_t i = threadIdx.x / kWave; i < st.nvalid; i += kHistBlock / kWave) {
+                const uint32_t j = st.order[i];
+                const uint32_t c = euclid_count_wave(st.seg[j], lane);
+                if (lane == 0) sc.counts[base + j] = (int32_t)c;
+            }
+        }
         lds_barrier();
     }
     if (bad) atomicOr(wv.status, kStatusOutOfRange);
@@ -631,6 +719,49 @@ __device__ __forceinline__ Piece piece_record(const StagedSeg& g, uint32_t klo, 
     return pc;
 }
 
+// The record of a piece under the Euclidean N of eq. (1), where every axis,
+// the dominant one too, may stay put at a step: as piece_record, but the
+// first word holds klo | 2 a_m << 16 (a_m = |d| of the dominant axis), from
+// which the fill derives the three axes' remainders at klo, and the length
+// counts the piece's samples k = klo ... khi (duplicates included).  N is at
+// most 16384 (the scene's diagonal is below 16385), so 2 klo a + N < 2^31.
+__device__ __forceinline__ Piece piece_record_euclid(const StagedSeg& g, uint32_t N, uint32_t klo, uint32_t khi,
+                                                     int32_t bx, int32_t by, int32_t bz, const BrickGeom& bg) {
+    int32_t p0[3], d[3];
+    uint32_t ad[3], c[3] = {0u, 0u, 0u};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        p0[ax] = g.p0[ax];
+        d[ax] = (int32_t)g.p1[ax] - p0[ax];
+        ad[ax] = (uint32_t)(d[ax] < 0 ? -d[ax] : d[ax]);
+    }
+    const uint32_t amax = ad[0] > ad[1] ? (ad[0] > ad[2] ? ad[0] : ad[2]) : (ad[1] > ad[2] ? ad[1] : ad[2]);
+    const uint32_t m = ad[0] == amax ? 0u : (ad[1] == amax ? 1u : 2u);
+    const uint32_t aa = m == 0 ? ad[1] : ad[0], ab = m == 2 ? ad[1] : ad[2];
+    const uint32_t am = m == 0 ? ad[0] : (m == 1 ? ad[1] : ad[2]);
+    const int32_t da = m == 0 ? d[1] : d[0], db = m == 2 ? d[1] : d[2];
+    const int32_t dm = m == 0 ? d[0] : (m == 1 ? d[1] : d[2]);
+    const uint32_t two_n = N > 0 ? 2u * N : 2u;
+    if (N > 0) {
+        const float rcpd = rcp_down(two_n);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            uint32_t r;
+            divmod_down(2u * __umul24(klo, ad[ax]) + N - (d[ax] < 0 ? 1u : 0u), two_n, rcpd, c[ax], r);
+        }
+    }
+    const int32_t x = p0[0] + (d[0] < 0 ? -(int32_t)c[0] : (int32_t)c[0]) - (bx << bg.lg[0]);
+    const int32_t y = p0[1] + (d[1] < 0 ? -(int32_t)c[1] : (int32_t)c[1]) - (by << bg.lg[1]);
+    const int32_t z = p0[2] + (d[2] < 0 ? -(int32_t)c[2] : (int32_t)c[2]) - (bz << bg.lg[2]);
+    Piece pc;
+    pc.e = klo | ((2u * am) << 16);
+    pc.t = (2u * aa) | ((2u * ab) << 16);
+    pc.v = m | ((uint32_t)(da < 0) << 2) | ((uint32_t)(db < 0) << 3) | ((uint32_t)(dm < 0) << 4) | (two_n << 16);
+    pc.w = (uint32_t)(x + (y << bg.lg[0]) + (z << (bg.lg[0] + bg.lg[1]))) |
+           ((khi - klo) << (bg.lg[0] + bg.lg[1] + bg.lg[2]));
+    return pc;
+}
+
 __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restrict__ work) {
     extern __shared__ uint32_t cur[];
     __shared__ Stage<kStage> st;
@@ -648,15 +779,24 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restric
     int64_t lo, hi;
     seg_range(sc.n, (int)g, (int)sc.rows, lo, hi);
     Piece* __restrict__ recs = wv.recs;
+    const bool euclid = (sc.flags & kSceneEuclid) != 0;
     bool bad = false;
     for (int64_t base = lo; base < hi; base += kStage) {
         const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
-        stage_segments(sc.segs, base, cnt, bg, st, nullptr, bad);
-        walk_ordered(st, bg, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j, int32_t bx, int32_t by,
-                                 int32_t bz) {
-            const uint32_t pos = atomicAdd(&cur[b], 1u);
-            recs[pos] = piece_record(st.seg[j], klo, khi, bx, by, bz, bg);
-        });
+        stage_segments(sc.segs, base, cnt, bg, euclid, st, nullptr, bad);
+        if (euclid) {
+            walk_ordered(st, bg, true, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j, int32_t bx,
+                                           int32_t by, int32_t bz, uint32_t N) {
+                const uint32_t pos = atomicAdd(&cur[b], 1u);
+                recs[pos] = piece_record_euclid(st.seg[j], N, klo, khi, bx, by, bz, bg);
+            });
+        } else {
+            walk_ordered(st, bg, false, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j, int32_t bx,
+                                            int32_t by, int32_t bz, uint32_t) {
+                const uint32_t pos = atomicAdd(&cur[b], 1u);
+                recs[pos] = piece_record(st.seg[j], klo, khi, bx, by, bz, bg);
+            });
+        }
         lds_barrier();
     }
 }
@@ -681,8 +821,11 @@ struct BrickShape {
 //      halves (minor axes a < b in axis order)
 //   v: the dominant axis' signed stride (low half) | 2N << 16 (2 when N = 0)
 //   w: bit index of the voxel at k = klo inside the brick | (len - 1) << kIdxBits
+// and, with the Euclidean N only, where the dominant axis need not move at
+// every step:
+//   m: its error term as a biased 16-bit half | its increment 2a_m << 16
 struct Digest {
-    uint32_t e, t, s, v, w;
+    uint32_t e, t, s, v, w, m;
 };
 
 template <int LGX, int LGY, int LGZ>
@@ -713,6 +856,29 @@ __device__ __forceinline__ Digest digest_record(const u32x4& rec) {
     g.s = ((uint32_t)sa & 0xFFFFu) | ((uint32_t)sb << 16);
     g.v = ((uint32_t)sm & 0xFFFFu) | (rec.z & 0xFFFF0000u);
     g.w = rec.w;
+    g.m = 0u;
+    return g;
+}
+
+// The same under the Euclidean N (records of piece_record_euclid): the
+// remainders of eq. (3)'s divisions at k = klo, for the two minor axes and
+// the dominant one, from klo and the increments.  A record holds 2N >= 2 and
+// klo, 2a <= 2N <= 32768, so the numerators stay below 2^31.
+template <int LGX, int LGY, int LGZ>
+__device__ __forceinline__ Digest digest_record_euclid(const u32x4& rec) {
+    Digest g = digest_record<LGX, LGY, LGZ>(rec);
+    const uint32_t nega = (rec.z >> 2) & 1u, negb = (rec.z >> 3) & 1u, negm = (rec.z >> 4) & 1u;
+    const uint32_t two_n = rec.z >> 16 > 1u ? rec.z >> 16 : 2u;
+    const uint32_t n = two_n >> 1;
+    const uint32_t klo = rec.x & 0xFFFFu, two_am = rec.x >> 16;
+    const uint32_t two_a = rec.y & 0xFFFFu, two_b = rec.y >> 16;
+    const float rcpd = rcp_down(two_n);
+    uint32_t q, ra, rb, rm;
+    divmod_down(__umul24(klo, two_a) + n - nega, two_n, rcpd, q, ra);
+    divmod_down(__umul24(klo, two_b) + n - negb, two_n, rcpd, q, rb);
+    divmod_down(__umul24(klo, two_am) + n - negm, two_n, rcpd, q, rm);
+    g.e = ((ra + 32768u - two_n) & 0xFFFFu) | ((rb + 32768u - two_n) << 16);
+    g.m = ((rm + 32768u - two_n) & 0xFFFFu) | (two_am << 16);
     return g;
 }
 
@@ -783,15 +949,75 @@ __device__ __forceinline__ void run_chunk(uint32_t* brick, const Digest& g, uint
     }
 }
 
-// Voxels of a piece record (from its last word).  A piece lies in one brick
-// and its dominant coordinate moves by one voxel per k, so it has at most as
-// many voxels as the brick's longest side; a record outside that (which the
-// scatter never writes) counts as empty, so that every loop of the fill
-// stays bounded whatever the workspace holds.
-template <int LGX, int LGY, int LGZ>
+// As run_chunk, under the Euclidean N of eq. (1): the dominant axis moves
+// only when its own error term carries, so it takes a second packed pair
+// (its biased half and a zero half that never carries), whose carry adds
+// its stride through a second dot product.  A step that moves no axis sets
+// the same bit again.  The chunk's start needs a third division.
+template <bool kFull, int kChunk, int LGX, int LGY, int LGZ>
+__device__ __forceinline__ void run_chunk_euclid(uint32_t* brick, const Digest& g, uint32_t j) {
+    using DB = DigestBits<LGX, LGY, LGZ>;
+    const uint32_t two_n = g.v >> 16;
+    const int32_t sm = (int32_t)(int16_t)(g.v & 0xFFFFu);
+    const uint32_t koff = j * (uint32_t)kChunk;
+    const uint32_t ge = g.e, gt = g.t, gs = g.s, gm = g.m;
+    const u16x2 E0 = __builtin_bit_cast(u16x2, ge);
+    const u16x2 T = __builtin_bit_cast(u16x2, gt);
+    const i16x2 S = __builtin_bit_cast(i16x2, gs);
+    const uint32_t em0 = gm & 0xFFFFu, two_am = gm >> 16;
+    const float rcpd = rcp_down(two_n);
+    uint32_t qa, ra, qb, rb, qm, rm;
+    divmod_down((uint32_t)E0.x + two_n - 32768u + __umul24(koff, (uint32_t)T.x), two_n, rcpd, qa, ra);
+    divmod_down((uint32_t)E0.y + two_n - 32768u + __umul24(koff, (uint32_t)T.y), two_n, rcpd, qb, rb);
+    divmod_down(em0 + two_n - 32768u + __umul24(koff, two_am), two_n, rcpd, qm, rm);
+    u16x2 E = {(uint16_t)(ra + 32768u - two_n), (uint16_t)(rb + 32768u - two_n)};
+    u16x2 Em = {(uint16_t)(rm + 32768u - two_n), 0};
+    const u16x2 Tm = {(uint16_t)two_am, 0};
+    const i16x2 Sm = {(int16_t)(-sm), 0};  // negated, as S
+    const u16x2 Q = {(uint16_t)qa, (uint16_t)qb};
+    const u16x2 Z = {0, 0};
+    int32_t idx = __builtin_amdgcn_sdot2(__builtin_bit_cast(i16x2, Z - Q), S,
+                                         (int32_t)(g.w & DB::kIdxMask) + (int32_t)qm * sm, false);
+    const u16x2 N2 = {(uint16_t)two_n, (uint16_t)two_n};
+    const i16x2 k15 = {15, 15};
+    const uint32_t len = (g.w >> DB::kIdxBits) + 1u;
+    const int n = kFull ? kChunk : (int)(len - koff < (uint32_t)kChunk ? len - koff : (uint32_t)kChunk);
+#pragma unroll 8
+    for (int k = 0; k < n; ++k) {
+        atomicOr(&brick[brick_word<LGX, LGY, LGZ>(idx)], 1u << ((uint32_t)idx & 31u));
+        E = E + T;
+        const i16x2 C = __builtin_bit_cast(i16x2, E) >> k15;
+        E = E + __builtin_bit_cast(u16x2, C) * N2;
+        Em = Em + Tm;
+        const i16x2 Cm = __builtin_bit_cast(i16x2, Em) >> k15;
+        Em = Em + __builtin_bit_cast(u16x2, Cm) * N2;
+        idx = __builtin_amdgcn_sdot2(Cm, Sm, __builtin_amdgcn_sdot2(C, S, idx, false), false);
+    }
+}
+
+// Most samples of one piece.  A piece lies in one brick.  With the Chebyshev
+// N its dominant coordinate moves by one voxel per k, so it has at most as
+// many samples as the brick's longest side L.  With the Euclidean N
+// (N <= sqrt(3) a_m) the dominant coordinate moves by more than
+// (khi - klo) a_m / N - 1 between klo and khi and by at most L - 1 inside
+// the brick, so khi - klo < sqrt(3) L and a piece has at most 7L/4 samples
+// (L >= 32).
+template <bool kEuclid, int LGX, int LGY, int LGZ>
+struct MaxSamples {
+    static constexpr uint32_t kSide = 1u << BrickShape<LGX, LGY, LGZ>::kMaxLg;
+    static constexpr uint32_t kValue = kEuclid ? kSide * 7u / 4u : kSide;
+    static_assert(kSide >= 32, "7L/4 bounds sqrt(3) L + 1");
+    static_assert(DigestBits<LGX, LGY, LGZ>::kIdxBits + BrickShape<LGX, LGY, LGZ>::kMaxLg + 1 <= 32,
+                  "bit index and length share a word");
+};
+
+// Samples of a piece record (from its last word); a record outside the
+// bound above (which the scatter never writes) counts as empty, so that
+// every loop of the fill stays bounded whatever the workspace holds.
+template <bool kEuclid, int LGX, int LGY, int LGZ>
 __device__ __forceinline__ uint32_t record_length(uint32_t w) {
     const uint32_t len = (w >> DigestBits<LGX, LGY, LGZ>::kIdxBits) + 1u;
-    return len <= (1u << BrickShape<LGX, LGY, LGZ>::kMaxLg) ? len : 0u;
+    return len <= MaxSamples<kEuclid, LGX, LGY, LGZ>::kValue ? len : 0u;
 }
 
 // A piece record, read once: a non-temporal load, so that the stream of
@@ -812,18 +1038,156 @@ __device__ __forceinline__ void set_quarters(uint32_t* cursors, uint32_t lo, uin
     for (uint32_t k = 0; k < (uint32_t)kQuarters; ++k) cursors[k] = quarter_bound(lo, hi, k);
 }
 
-// Launch shape of the fill kernel per brick shape: threads, voxels per chunk
-// and workgroups per CU.  A 128 KiB brick takes a whole CU (one workgroup of
-// 1024 threads); 64 KiB bricks run two workgroups of 512 threads per CU, so
-// that one workgroup's brick start and flush overlap the other's voxel work.
-template <int LGX, int LGY, int LGZ>
+// Launch shape of the fill kernel: kWgs workgroups per CU, of 1024 threads
+// (one per CU) or 512 (two per CU).  A 128 KiB brick takes a whole CU; 64 KiB
+// bricks run either way: two workgroups per CU, so that one workgroup's brick
+// start and flush overlap the other's voxel work, or, when the volume has
+// fewer bricks than that gives slots, one with all 16 waves on its brick.
+constexpr int kFillChunk = 32;  // samples per chunk
+template <int LGX, int LGY, int LGZ, int kWgs>
 struct FillCfg {
-    static constexpr bool kBig = (LGX + LGY + LGZ) >= 20;
-    static constexpr int kBlock = kBig ? 1024 : 512;
-    static constexpr int kChunk = 32;
-    static constexpr int kWgsPerCu = kBig ? 1 : 2;
+    static_assert(kWgs == 1 || (kWgs == 2 && LGX + LGY + LGZ < 20), "two workgroups per CU: 64 KiB bricks");
+    static constexpr int kBlock = kWgs == 1 ? 1024 : 512;
+    static constexpr int kWgsPerCu = kWgs;
 };
 constexpr int kSets = 2;  // piece records per lane in a wave group
+
+// The pieces of one brick that this wave runs: groups of 128 records (two
+// per lane: sets 0 and 1), taken from its SIMD's quarter qu of the brick's
+// records [p_lo, p_hi) (waves w and w + 4k share a SIMD), so the four SIMDs
+// get even shares of the brick's work; the next group is claimed and loaded
+// before the current one runs.  kEuclid: the brick's scene uses the
+// Euclidean N of eq. (1).
+template <bool kEuclid, int LGX, int LGY, int LGZ, int kEntCap>
+__device__ __forceinline__ void fill_records(uint32_t* brick, uint16_t* my_ent, const u32x4* recv,
+                                             uint32_t* cursor_s, uint32_t qu, uint32_t p_lo, uint32_t p_hi,
+                                             uint32_t lane) {
+    constexpr int kChunk = kFillChunk;
+    constexpr int kGroup = kWave * kSets;  // records per wave group
+    constexpr int kMaxChunks = (MaxSamples<kEuclid, LGX, LGY, LGZ>::kValue + kChunk - 1) / kChunk;  // per piece
+    // A group with more chunks than the table holds runs its two record sets
+    // one after the other.
+    constexpr bool kSplit = kEntCap < kGroup * kMaxChunks;
+    static_assert(kMaxChunks <= 512, "chunk entries: lane | set << 6 | j << 7");
+    static_assert(kEntCap >= kWave * kMaxChunks, "one record set's chunks always fit the table");
+    const uint32_t q_hi = quarter_bound(p_lo, p_hi, qu + 1u);
+    uint32_t gbase = 0;
+    if (lane == 0) gbase = atomicAdd(&cursor_s[qu], (uint32_t)kGroup);
+    gbase = __builtin_amdgcn_readfirstlane(gbase);
+    u32x4 rn0 = (gbase + lane < q_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
+    u32x4 rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
+    while (gbase < q_hi) {
+        const u32x4 r0 = rn0, r1 = rn1;
+        const uint32_t len0 = gbase + lane < q_hi ? record_length<kEuclid, LGX, LGY, LGZ>(r0.w) : 0u;
+        const uint32_t len1 = gbase + kWave + lane < q_hi ? record_length<kEuclid, LGX, LGY, LGZ>(r1.w) : 0u;
+        // The records have arrived (len0/len1 are made from them); the next
+        // group's loads are issued only now, so no later wait for these
+        // records waits for them too.
+        asm volatile("" ::"v"(len0), "v"(len1) : "memory");
+        if (lane == 0) gbase = atomicAdd(&cursor_s[qu], (uint32_t)kGroup);
+        gbase = __builtin_amdgcn_readfirstlane(gbase);
+        rn0 = (gbase + lane < q_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
+        rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
+
+        // This lane's pieces as stepping states (read by the lanes that
+        // run their chunks).
+        const Digest d0 = kEuclid ? digest_record_euclid<LGX, LGY, LGZ>(r0) : digest_record<LGX, LGY, LGZ>(r0);
+        const Digest d1 = kEuclid ? digest_record_euclid<LGX, LGY, LGZ>(r1) : digest_record<LGX, LGY, LGZ>(r1);
+        const uint32_t nf0 = len0 / kChunk, pl0 = len0 % kChunk;
+        const uint32_t nf1 = len1 / kChunk, pl1 = len1 % kChunk;
+        // Length class of a partial chunk: 3 (longest) ... 0, or 4 (none).
+        const uint32_t k0 = pl0 == 0 ? 4u : pl0 * 4u / kChunk, k1 = pl1 == 0 ? 4u : pl1 * 4u / kChunk;
+
+        // Chunks of this lane's pieces: their full chunks, then their
+        // partial chunks.  The wave's table lists all full chunks first,
+        // then the partial ones in four length classes, longest first, so
+        // that most rounds run chunks of one length.  Two packed DPP scans
+        // count all five lists.  Sets 0 and 1 share one table, or take
+        // turns when their chunks overflow it.
+        uint32_t sets = 3u;
+        for (;;) {
+            const uint32_t u0 = sets & 1u, u1 = sets >> 1;
+            const uint32_t f0 = u0 ? nf0 : 0u, f1 = u1 ? nf1 : 0u;
+            const uint32_t q0 = u0 ? k0 : 4u, q1 = u1 ? k1 : 4u;
+            const uint32_t c3 = (q0 == 3u) + (q1 == 3u), c2 = (q0 == 2u) + (q1 == 2u);
+            const uint32_t c1 = (q0 == 1u) + (q1 == 1u), c0 = (q0 == 0u) + (q1 == 0u);
+            const uint32_t ia = wave_inclusive_sum_dpp((f0 + f1) | (c3 << 16));
+            const uint32_t ib = wave_inclusive_sum_dpp(c2 | (c1 << 10) | (c0 << 20));
+            const uint32_t ta = __builtin_amdgcn_readlane(ia, kWave - 1);
+            const uint32_t tb = __builtin_amdgcn_readlane(ib, kWave - 1);
+            const uint32_t tf = ta & 0xFFFFu;                      // full chunks
+            const uint32_t o2 = tf + (ta >> 16);                   // start of class 2
+            const uint32_t o1 = o2 + (tb & 0x3FFu);
+            const uint32_t o0 = o1 + ((tb >> 10) & 0x3FFu);
+            const uint32_t tt = o0 + (tb >> 20);
+            if (kSplit && tt > (uint32_t)kEntCap) {
+                sets = 1u;  // set 0 now, set 1 next
+                continue;
+            }
+            {
+                const uint32_t fb = (ia & 0xFFFFu) - f0 - f1;
+                for (uint32_t j = 0; j < f0; ++j) my_ent[fb + j] = (uint16_t)(lane | (j << 7));
+                for (uint32_t j = 0; j < f1; ++j) my_ent[fb + f0 + j] = (uint16_t)(lane | 64u | (j << 7));
+                // End of this lane's run in each class list.
+                const uint32_t e3 = tf + (ia >> 16), e2 = o2 + (ib & 0x3FFu);
+                const uint32_t e1 = o1 + ((ib >> 10) & 0x3FFu), e0 = o0 + (ib >> 20);
+                if (q0 < 4u) {
+                    const uint32_t pos = q0 == 3u ? e3 - c3 : q0 == 2u ? e2 - c2 : q0 == 1u ? e1 - c1 : e0 - c0;
+                    my_ent[pos] = (uint16_t)(lane | (nf0 << 7));
+                }
+                if (q1 < 4u) {
+                    const uint32_t pos = q1 == 3u ? e3 - 1u : q1 == 2u ? e2 - 1u : q1 == 1u ? e1 - 1u : e0 - 1u;
+                    my_ent[pos] = (uint16_t)(lane | 64u | (nf1 << 7));
+                }
+            }
+            // Make the table writes visible to the wave's own reads below.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+            for (uint32_t q = 0; q < tt; q += kWave) {
+                const uint32_t c = q + lane;
+                const uint32_t e = c < tt ? my_ent[c] : 0u;
+                const int src = (int)((e & 63u) << 2);
+                const bool s1 = (e & 64u) != 0u;
+                const uint32_t ge0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.e);
+                const uint32_t ge1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.e);
+                const uint32_t gt0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.t);
+                const uint32_t gt1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.t);
+                const uint32_t gs0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.s);
+                const uint32_t gs1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.s);
+                const uint32_t gv0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.v);
+                const uint32_t gv1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.v);
+                const uint32_t gw0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.w);
+                const uint32_t gw1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.w);
+                Digest g = {s1 ? ge1 : ge0, s1 ? gt1 : gt0, s1 ? gs1 : gs0, s1 ? gv1 : gv0, s1 ? gw1 : gw0, 0u};
+                if constexpr (kEuclid) {
+                    const uint32_t gm0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.m);
+                    const uint32_t gm1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.m);
+                    g.m = s1 ? gm1 : gm0;
+                    if (q + kWave <= tf) {
+                        run_chunk_euclid<true, kChunk, LGX, LGY, LGZ>(brick, g, e >> 7);
+                    } else if (c < tt) {
+                        run_chunk_euclid<false, kChunk, LGX, LGY, LGZ>(brick, g, e >> 7);
+                    }
+                } else {
+                    if (q + kWave <= tf) {
+                        run_chunk<true, kChunk, LGX, LGY, LGZ>(brick, g, e >> 7);
+                    } else if (c < tt) {
+                        run_chunk<false, kChunk, LGX, LGY, LGZ>(brick, g, e >> 7);
+                    }
+                }
+            }
+            // The table is rewritten by the next pass or group.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (sets != 1u) break;
+            sets = 2u;
+        }
+    }
+}
+
 
 // Persistent fill.  Workgroups take bricks from the brick queues (work
 // stealing: bricks differ a lot in work).  Inside a brick the waves work
@@ -834,25 +1198,22 @@ constexpr int kSets = 2;  // piece records per lane in a wave group
 // and runs them in rounds of 64, one chunk per lane, reading each chunk's
 // digest from the owning lane with ds_bpermute.  The next 128 records are
 // loaded while the current ones run.
-template <int LGX, int LGY, int LGZ>
-__global__ __launch_bounds__((FillCfg<LGX, LGY, LGZ>::kBlock), (FillCfg<LGX, LGY, LGZ>::kWgsPerCu))
+template <int LGX, int LGY, int LGZ, int kWgs>
+__global__ __launch_bounds__((FillCfg<LGX, LGY, LGZ, kWgs>::kBlock), kWgs)
 void k_brick_fill(uint8_t* __restrict__ work) {
     using Shape = BrickShape<LGX, LGY, LGZ>;
-    using Cfg = FillCfg<LGX, LGY, LGZ>;
-    constexpr int kBlock = Cfg::kBlock, kChunk = Cfg::kChunk;
+    using Cfg = FillCfg<LGX, LGY, LGZ, kWgs>;
+    constexpr int kBlock = Cfg::kBlock, kChunk = kFillChunk;
     constexpr int kWaves = kBlock / kWave;
-    constexpr int kMaxChunks = ((1 << Shape::kMaxLg) + kChunk - 1) / kChunk;  // per piece
+    constexpr int kMaxChunks = ((int)MaxSamples<true, LGX, LGY, LGZ>::kValue + kChunk - 1) / kChunk;  // per piece
     constexpr int kUpr = Shape::kBXw / 4;  // 16-byte units per brick row
     constexpr int kGroup = kWave * kSets;  // records per wave group
     // Chunk table entries per wave: all chunks of a group when the LDS left
-    // by the brick holds them, else a multiple of 64 below that (a group
-    // with more chunks runs its two record sets one after the other).
+    // by the brick holds them, else a multiple of 64 below that.
     constexpr int kLdsWg = 163840 / Cfg::kWgsPerCu;
     constexpr int kEntFit = ((kLdsWg - (int)Shape::kBytes - 64) / (2 * kWaves)) / kWave * kWave;
     constexpr int kEntCap = kGroup * kMaxChunks < kEntFit ? kGroup * kMaxChunks : kEntFit;
-    constexpr bool kSplit = kEntCap < kGroup * kMaxChunks;
-    static_assert(kWave == 64 && kSets == 2 && kMaxChunks <= 512, "chunk entries: lane | set << 6 | j << 7");
-    static_assert(kEntCap >= kWave * kMaxChunks, "one record set's chunks always fit the table");
+    static_assert(kWave == 64 && kSets == 2, "chunk entries: lane | set << 6 | j << 7");
     // The brick first, so its addresses need no base offset.
     __shared__ __align__(16) uint32_t brick[Shape::kWords];
     __shared__ uint16_t ent[kWaves][kEntCap];  // per-wave chunk tables
@@ -920,117 +1281,12 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         // (The brick is zero and the cursors set: done before the barrier that
         // ended the previous brick.)
 
-        // This wave's groups of 128 records (two per lane: sets 0 and 1),
-        // taken from its SIMD's quarter of the brick's records (waves w and
-        // w + 4k share a SIMD), so the four SIMDs get even shares of the
-        // brick's work; the next group is claimed and loaded before the
-        // current one runs.
+        // This wave's pieces of the brick.
         const uint32_t qu = wave % kQuarters;
-        const uint32_t q_hi = quarter_bound(p_lo, p_hi, qu + 1u);
-        uint32_t gbase = 0;
-        if (lane == 0) gbase = atomicAdd(&cursor_s[qu], (uint32_t)kGroup);
-        gbase = __builtin_amdgcn_readfirstlane(gbase);
-        u32x4 rn0 = (gbase + lane < q_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
-        u32x4 rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
-        while (gbase < q_hi) {
-            const u32x4 r0 = rn0, r1 = rn1;
-            const uint32_t len0 = gbase + lane < q_hi ? record_length<LGX, LGY, LGZ>(r0.w) : 0u;
-            const uint32_t len1 = gbase + kWave + lane < q_hi ? record_length<LGX, LGY, LGZ>(r1.w) : 0u;
-            // The records have arrived (len0/len1 are made from them); the next
-            // group's loads are issued only now, so no later wait for these
-            // records waits for them too.
-            asm volatile("" ::"v"(len0), "v"(len1) : "memory");
-            if (lane == 0) gbase = atomicAdd(&cursor_s[qu], (uint32_t)kGroup);
-            gbase = __builtin_amdgcn_readfirstlane(gbase);
-            rn0 = (gbase + lane < q_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
-            rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
-
-            // This lane's pieces as stepping states (read by the lanes that
-            // run their chunks).
-            const Digest d0 = digest_record<LGX, LGY, LGZ>(r0);
-            const Digest d1 = digest_record<LGX, LGY, LGZ>(r1);
-            const uint32_t nf0 = len0 / kChunk, pl0 = len0 % kChunk;
-            const uint32_t nf1 = len1 / kChunk, pl1 = len1 % kChunk;
-            // Length class of a partial chunk: 3 (longest) ... 0, or 4 (none).
-            const uint32_t k0 = pl0 == 0 ? 4u : pl0 * 4u / kChunk, k1 = pl1 == 0 ? 4u : pl1 * 4u / kChunk;
-
-            // Chunks of this lane's pieces: their full chunks, then their
-            // partial chunks.  The wave's table lists all full chunks first,
-            // then the partial ones in four length classes, longest first, so
-            // that most rounds run chunks of one length.  Two packed DPP scans
-            // count all five lists.  Sets 0 and 1 share one table, or take
-            // turns when their chunks overflow it.
-            uint32_t sets = 3u;
-            for (;;) {
-                const uint32_t u0 = sets & 1u, u1 = sets >> 1;
-                const uint32_t f0 = u0 ? nf0 : 0u, f1 = u1 ? nf1 : 0u;
-                const uint32_t q0 = u0 ? k0 : 4u, q1 = u1 ? k1 : 4u;
-                const uint32_t c3 = (q0 == 3u) + (q1 == 3u), c2 = (q0 == 2u) + (q1 == 2u);
-                const uint32_t c1 = (q0 == 1u) + (q1 == 1u), c0 = (q0 == 0u) + (q1 == 0u);
-                const uint32_t ia = wave_inclusive_sum_dpp((f0 + f1) | (c3 << 16));
-                const uint32_t ib = wave_inclusive_sum_dpp(c2 | (c1 << 10) | (c0 << 20));
-                const uint32_t ta = __builtin_amdgcn_readlane(ia, kWave - 1);
-                const uint32_t tb = __builtin_amdgcn_readlane(ib, kWave - 1);
-                const uint32_t tf = ta & 0xFFFFu;                      // full chunks
-                const uint32_t o2 = tf + (ta >> 16);                   // start of class 2
-                const uint32_t o1 = o2 + (tb & 0x3FFu);
-                const uint32_t o0 = o1 + ((tb >> 10) & 0x3FFu);
-                const uint32_t tt = o0 + (tb >> 20);
-                if (kSplit && tt > (uint32_t)kEntCap) {
-                    sets = 1u;  // set 0 now, set 1 next
-                    continue;
-                }
-                {
-                    const uint32_t fb = (ia & 0xFFFFu) - f0 - f1;
-                    for (uint32_t j = 0; j < f0; ++j) my_ent[fb + j] = (uint16_t)(lane | (j << 7));
-                    for (uint32_t j = 0; j < f1; ++j) my_ent[fb + f0 + j] = (uint16_t)(lane | 64u | (j << 7));
-                    // End of this lane's run in each class list.
-                    const uint32_t e3 = tf + (ia >> 16), e2 = o2 + (ib & 0x3FFu);
-                    const uint32_t e1 = o1 + ((ib >> 10) & 0x3FFu), e0 = o0 + (ib >> 20);
-                    if (q0 < 4u) {
-                        const uint32_t pos = q0 == 3u ? e3 - c3 : q0 == 2u ? e2 - c2 : q0 == 1u ? e1 - c1 : e0 - c0;
-                        my_ent[pos] = (uint16_t)(lane | (nf0 << 7));
-                    }
-                    if (q1 < 4u) {
-                        const uint32_t pos = q1 == 3u ? e3 - 1u : q1 == 2u ? e2 - 1u : q1 == 1u ? e1 - 1u : e0 - 1u;
-                        my_ent[pos] = (uint16_t)(lane | 64u | (nf1 << 7));
-                    }
-                }
-                // Make the table writes visible to the wave's own reads below.
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-                for (uint32_t q = 0; q < tt; q += kWave) {
-                    const uint32_t c = q + lane;
-                    const uint32_t e = c < tt ? my_ent[c] : 0u;
-                    const int src = (int)((e & 63u) << 2);
-                    const bool s1 = (e & 64u) != 0u;
-                    const uint32_t ge0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.e);
-                    const uint32_t ge1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.e);
-                    const uint32_t gt0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.t);
-                    const uint32_t gt1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.t);
-                    const uint32_t gs0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.s);
-                    const uint32_t gs1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.s);
-                    const uint32_t gv0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.v);
-                    const uint32_t gv1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.v);
-                    const uint32_t gw0 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d0.w);
-                    const uint32_t gw1 = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)d1.w);
-                    const Digest g = {s1 ? ge1 : ge0, s1 ? gt1 : gt0, s1 ? gs1 : gs0, s1 ? gv1 : gv0, s1 ? gw1 : gw0};
-                    if (q + kWave <= tf) {
-                        run_chunk<true, kChunk, LGX, LGY, LGZ>(brick, g, e >> 7);
-                    } else if (c < tt) {
-                        run_chunk<false, kChunk, LGX, LGY, LGZ>(brick, g, e >> 7);
-                    }
-                }
-                // The table is rewritten by the next pass or group.
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (sets != 1u) break;
-                sets = 2u;
-            }
-        }
+        if (sc.flags & kSceneEuclid)
+            fill_records<true, LGX, LGY, LGZ, kEntCap>(brick, my_ent, recv, cursor_s, qu, p_lo, p_hi, lane);
+        else
+            fill_records<false, LGX, LGY, LGZ, kEntCap>(brick, my_ent, recv, cursor_s, qu, p_lo, p_hi, lane);
         // Hand over the next brick (read by all after the barrier).
         if (threadIdx.x == 0) {
             next_s[0] = nb;
@@ -1228,6 +1484,7 @@ BrickLaunch batch_launch(uint32_t n_scenes, uint64_t total_segments, const int l
     for (int a = 0; a < 3; ++a) L.lg[a] = lg[a];
     L.table_bytes = table_bytes(n_scenes, L.rows, L.bricks);
     L.direct_kernels = true;
+    L.segs_per_row = (uint32_t)kSegsPerRow;
     return L;
 }
 
@@ -1242,7 +1499,8 @@ BrickLaunch plain_launch(int64_t n, const BrickGeom& bg) {
     BrickLaunch L;
     L.n_scenes = 1;
     L.total_segments = (uint64_t)n;
-    L.rows = hist_rows(n);
+    L.rows = hist_rows(n, kSegsPerRowPlain);
+    L.segs_per_row = (uint32_t)kSegsPerRowPlain;
     L.bricks = bg.nbricks;
     for (int a = 0; a < 3; ++a) L.lg[a] = bg.lg[a];
     L.table_bytes = table_bytes(1, L.rows, L.bricks);
@@ -1266,15 +1524,25 @@ static int device_cus() {
     return cus;
 }
 
-// Persistent fill workgroups: wgs_per_cu per compute unit (at most the
-// shape's default, which its LDS allows).
+// Persistent fill workgroups: wgs_per_cu per compute unit (0: for 64 KiB
+// bricks two, unless the launch has fewer bricks than two per CU, then one
+// of 1024 threads), and no more than the launch has bricks (a workgroup
+// without a brick would only take a CU slot).
 template <int LGX, int LGY, int LGZ>
-static hipError_t launch_fill(uint8_t* work, int wgs_per_cu, hipStream_t stream) {
-    constexpr int kBlock = FillCfg<LGX, LGY, LGZ>::kBlock;
-    constexpr int kMax = FillCfg<LGX, LGY, LGZ>::kWgsPerCu;
-    const int per = wgs_per_cu >= 1 && wgs_per_cu <= kMax ? wgs_per_cu : kMax;
-    const int wgs = device_cus() * per;
-    k_brick_fill<LGX, LGY, LGZ><<<wgs, kBlock, 0, stream>>>(work);
+static hipError_t launch_fill(uint8_t* work, int wgs_per_cu, uint32_t max_bricks, hipStream_t stream) {
+    const int cus = device_cus();
+    int per = 1;
+    if constexpr (LGX + LGY + LGZ < 20)
+        per = wgs_per_cu == 1 || wgs_per_cu == 2 ? wgs_per_cu : (max_bricks < 2u * (uint32_t)cus ? 1 : 2);
+    int wgs = cus * per;
+    if ((uint32_t)wgs > max_bricks) wgs = (int)max_bricks;
+    if constexpr (LGX + LGY + LGZ < 20) {
+        if (per == 2) {
+            k_brick_fill<LGX, LGY, LGZ, 2><<<wgs, FillCfg<LGX, LGY, LGZ, 2>::kBlock, 0, stream>>>(work);
+            return hipGetLastError();
+        }
+    }
+    k_brick_fill<LGX, LGY, LGZ, 1><<<wgs, FillCfg<LGX, LGY, LGZ, 1>::kBlock, 0, stream>>>(work);
     return hipGetLastError();
 }
 
@@ -1333,10 +1601,10 @@ hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunc
     {
         KernelTimer t("brick_fill", stream);
         const int* lg = L.lg;
-        if (lg[0] == 8 && lg[1] == 6 && lg[2] == 5) e = launch_fill<8, 6, 5>(work, fill_wgs_per_cu, stream);
-        else if (lg[0] == 8 && lg[1] == 6 && lg[2] == 6) e = launch_fill<8, 6, 6>(work, fill_wgs_per_cu, stream);
-        else if (lg[0] == 7 && lg[1] == 6 && lg[2] == 6) e = launch_fill<7, 6, 6>(work, fill_wgs_per_cu, stream);
-        else if (lg[0] == 7 && lg[1] == 7 && lg[2] == 6) e = launch_fill<7, 7, 6>(work, fill_wgs_per_cu, stream);
+        if (lg[0] == 8 && lg[1] == 6 && lg[2] == 5) e = launch_fill<8, 6, 5>(work, fill_wgs_per_cu, L.bricks, stream);
+        else if (lg[0] == 8 && lg[1] == 6 && lg[2] == 6) e = launch_fill<8, 6, 6>(work, fill_wgs_per_cu, L.bricks, stream);
+        else if (lg[0] == 7 && lg[1] == 6 && lg[2] == 6) e = launch_fill<7, 6, 6>(work, fill_wgs_per_cu, L.bricks, stream);
+        else if (lg[0] == 7 && lg[1] == 7 && lg[2] == 6) e = launch_fill<7, 7, 6>(work, fill_wgs_per_cu, L.bricks, stream);
         else e = hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;

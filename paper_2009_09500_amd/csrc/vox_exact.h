@@ -237,12 +237,23 @@ __host__ __device__ inline bool scene_valid(const vox_scene& in) {
     return (in.flags & ~(uint32_t)(VOX_GRID_CLEAR | VOX_GRID_EUCLID)) == 0;
 }
 
+// With the Euclidean N of eq. (1), the brick path needs N <= 16384 for every
+// segment (the fill keeps error terms below 2N in biased 16-bit halves); an
+// in-volume segment's N is at most the volume's diagonal, so the volume's
+// diagonal decides.
+__host__ __device__ inline bool euclid_bricks_ok(int32_t dx, int32_t dy, int32_t dz) {
+    const int64_t sx = dx - 1, sy = dy - 1, sz = dz - 1;
+    return sx * sx + sy * sy + sz * sz < (int64_t)16385 * 16385;
+}
+
 // One scene of a launch, as the plan kernel enters it in the table (bases
 // left zero): the brick path serves it when its segment array is 8-byte
-// aligned, it uses the Chebyshev N and its volume takes bricks of 2^lg;
-// otherwise it is flagged for the direct kernels.  False (and a direct entry
+// aligned and its volume takes bricks of 2^lg (and, with the Euclidean N,
+// when its diagonal is below 16385); otherwise it is flagged for the direct
+// kernels.  False (and a direct entry
 // with no segments) when the scene breaks an argument rule.
-__host__ __device__ inline bool plan_scene(const vox_scene& in, const int32_t lg[3], BrickScene& out) {
+__host__ __device__ inline bool plan_scene(const vox_scene& in, const int32_t lg[3], int64_t segs_per_row,
+                                           BrickScene& out) {
     const bool valid = scene_valid(in);
     out = BrickScene{};
     out.segs = reinterpret_cast<const int32_t*>(in.segs);
@@ -258,9 +269,10 @@ __host__ __device__ inline bool plan_scene(const vox_scene& in, const int32_t lg
     if (((uintptr_t)in.segs & 7u) == 0) f |= kSceneA8;
     const int lgi[3] = {lg[0], lg[1], lg[2]};
     BrickGeom bg;
-    if (valid && (f & kSceneA8) && !(f & kSceneEuclid) && brick_geometry(in.dim_x, in.dim_y, in.dim_z, lgi, bg)) {
+    if (valid && (f & kSceneA8) && (!(f & kSceneEuclid) || euclid_bricks_ok(in.dim_x, in.dim_y, in.dim_z)) &&
+        brick_geometry(in.dim_x, in.dim_y, in.dim_z, lgi, bg)) {
         out.bg = bg;
-        out.rows = hist_rows(in.n);
+        out.rows = hist_rows(in.n, segs_per_row);
     } else {
         f |= kSceneDirect;
         out.rows = 0;

@@ -44,8 +44,9 @@ constexpr int64_t kDirectMaxSegments = 16384;
 // The brick path serves calls with more segments than that, on volumes whose
 // rows are whole words and whose piece ids fit 32 bits; everything else takes
 // the direct path.
-static bool use_bricks(int64_t n, int32_t dx, int32_t dy, int32_t dz, BrickGeom& bg, Tuning& t) {
+static bool use_bricks(int64_t n, int32_t dx, int32_t dy, int32_t dz, bool euclid, BrickGeom& bg, Tuning& t) {
     if (n <= kDirectMaxSegments) return false;
+    if (euclid && !euclid_bricks_ok(dx, dy, dz)) return false;
     if (!tuning_cache_lookup(dx, dy, dz, n, t)) {
         default_brick_lg(dx, dy, dz, t.lg);
         t.fill_wgs_per_cu = 0;
@@ -59,7 +60,9 @@ static bool use_bricks(int64_t n, int32_t dx, int32_t dy, int32_t dz, BrickGeom&
 size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz) {
     BrickGeom bg;
     Tuning t;
-    if (use_bricks(n, dx, dy, dz, bg, t)) return brick_workspace_bytes(n, bg);
+    // (The Euclidean N takes the brick path under the same rules, but for the
+    // volume's diagonal; the workspace bound covers both.)
+    if (use_bricks(n, dx, dy, dz, false, bg, t)) return brick_workspace_bytes(n, bg);
     return kAlign;
 }
 
@@ -78,15 +81,15 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
     Tuning t;
     // The brick path reads segments with 8-byte loads; arrays that are only
     // 4-byte aligned take the direct path.
-    const bool euclid = (flags & 2u) != 0;  // VOX_GRID_EUCLID: the direct path only
-    if (!euclid && aligned8 && use_bricks(n, dx, dy, dz, bg, t)) {
+    const bool euclid = (flags & 2u) != 0;  // VOX_GRID_EUCLID
+    if (aligned8 && use_bricks(n, dx, dy, dz, euclid, bg, t)) {
         vox_scene one{};
         one.segs = reinterpret_cast<const vox_segment*>(segs);
         one.n = n;
         one.dim_x = dx;
         one.dim_y = dy;
         one.dim_z = dz;
-        one.flags = flags & 1u;
+        one.flags = flags & 3u;
         one.grid = grid;
         one.counts = counts;
         return launch_bricks(nullptr, &one, plain_launch(n, bg), t.fill_wgs_per_cu, w.status, w.bytes,

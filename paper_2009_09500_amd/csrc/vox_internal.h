@@ -104,7 +104,13 @@ struct BrickGeom {
 constexpr uint32_t kMaxBricks = 16384;  // LDS histogram of 64 KiB
 constexpr int kHistBlock = 1024;
 constexpr int kHistRows = 256;
-constexpr int64_t kSegsPerRow = 4096;   // segments staged per histogram round
+// Segments per histogram row (one workgroup of the histogram and scatter
+// kernels): a batch has the parallelism of its many scenes and keeps its
+// workspace bound small with 4096; a plain call of one volume takes rows of
+// 512, so that a call of a few hundred thousand segments still spreads over
+// the CUs (both reach the 256 rows a scene may have at large n).
+constexpr int64_t kSegsPerRow = 4096;
+constexpr int64_t kSegsPerRowPlain = 512;
 
 // One volume of a launch as the kernels read it from the device scene table
 // (written by the plan kernel from the caller's vox_scene entries).
@@ -123,7 +129,7 @@ struct BrickScene {
 };
 constexpr uint32_t kSceneClear = 1;    // zero the volume first
 constexpr uint32_t kSceneDirect = 2;   // the direct kernels serve this scene (no bricks)
-constexpr uint32_t kSceneEuclid = 4;   // Euclidean N of eq. (1) (direct kernels only)
+constexpr uint32_t kSceneEuclid = 4;   // Euclidean N of eq. (1)
 constexpr uint32_t kSceneA8 = 8;       // segment array 8-byte aligned
 
 // Device scene table, written into the workspace by the plan kernel: this
@@ -167,11 +173,12 @@ struct BrickLaunch {
     int32_t lg[3];
     uint64_t table_bytes;     // table region (bound)
     bool direct_kernels;      // launch the direct kernels (some scene may need them)
+    uint32_t segs_per_row;    // kSegsPerRow or kSegsPerRowPlain
 };
 
-// Histogram rows of a brick scene of n segments.
-__host__ __device__ inline uint32_t hist_rows(int64_t n) {
-    int64_t g = (n + kSegsPerRow - 1) / kSegsPerRow;
+// Histogram rows of a brick scene of n segments, per_row segments a row.
+__host__ __device__ inline uint32_t hist_rows(int64_t n, int64_t per_row) {
+    int64_t g = (n + per_row - 1) / per_row;
     if (g > kHistRows) g = kHistRows;
     if (g < 1) g = 1;
     return (uint32_t)g;

@@ -3,7 +3,7 @@
 // kernel runs for each scene of a batch): prints what the plan enters in the
 // scene table.  Built and run by tests/test_batch_plan.py (CPU only).
 //
-// stdin:  lgx lgy lgz count, then count lines
+// stdin:  lgx lgy lgz segs_per_row count, then count lines
 //         "segs n dim_x dim_y dim_z flags grid counts" (addresses as integers)
 // stdout: per scene "valid flags rows nbricks nbx nby nbz dimx dimy dimz n"
 #include <cstdio>
@@ -13,7 +13,8 @@
 int main() {
     int lg[3];
     int count;
-    if (scanf("%d %d %d %d", &lg[0], &lg[1], &lg[2], &count) != 4) return 2;
+    long long per_row;
+    if (scanf("%d %d %d %lld %d", &lg[0], &lg[1], &lg[2], &per_row, &count) != 5) return 2;
     for (int i = 0; i < count; ++i) {
         unsigned long long segs, grid, counts;
         long long n;
@@ -32,7 +33,7 @@ int main() {
         in.counts = reinterpret_cast<int32_t*>((uintptr_t)counts);
         const int32_t lgi[3] = {lg[0], lg[1], lg[2]};
         vox::BrickScene b;
-        const bool valid = vox::plan_scene(in, lgi, b);
+        const bool valid = vox::plan_scene(in, lgi, per_row, b);
         printf("%d %u %u %u %d %d %d %d %d %d %lld\n", valid ? 1 : 0, b.flags, b.rows, b.bg.nbricks, b.bg.nb[0],
                b.bg.nb[1], b.bg.nb[2], b.bg.dim[0], b.bg.dim[1], b.bg.dim[2], (long long)b.n);
     }

@@ -34,9 +34,11 @@ def planner(tmp_path_factory):
     subprocess.check_call([hipcc, "-O1", "-std=c++17", "-I", os.path.join(ROOT, "include"),
                            "-I", os.path.join(ROOT, "paper_2009_09500_amd", "csrc"), "-o", out, SRC])
 
-    def run(lg, scenes):
-        """scenes: dicts with n, dims and optional flags, segs, grid, counts."""
-        lines = ["%d %d %d %d" % (lg[0], lg[1], lg[2], len(scenes))]
+    def run(lg, scenes, per_row=4096):
+        """scenes: dicts with n, dims and optional flags, segs, grid, counts;
+        per_row: segments per histogram row (4096 in batches, 512 in plain
+        calls)."""
+        lines = ["%d %d %d %d %d" % (lg[0], lg[1], lg[2], per_row, len(scenes))]
         for sc in scenes:
             lines.append("%d %d %d %d %d %d %d %d" % (
                 sc.get("segs", SEGS), sc["n"], sc["dims"][0], sc["dims"][1], sc["dims"][2],
@@ -52,8 +54,8 @@ def planner(tmp_path_factory):
     return run
 
 
-def expected_rows(n):
-    return min(256, max(1, -(-n // 4096)))
+def expected_rows(n, per_row=4096):
+    return min(256, max(1, -(-n // per_row)))
 
 
 def test_brick_scenes(planner):
@@ -66,15 +68,19 @@ def test_brick_scenes(planner):
         assert out["valid"] and out["nb"] == nb and out["nbricks"] == nb[0] * nb[1] * nb[2]
         assert out["flags"] == (F_CLEAR if sc.get("flags", CLEAR) else 0) | F_A8
         assert out["rows"] == expected_rows(sc["n"]) and out["dim"] == sc["dims"] and out["n"] == sc["n"]
+    # Plain calls: rows of 512 segments, at most 256.
+    plain = planner(lg, specs, per_row=512)
+    assert [o["rows"] for o in plain] == [2, 1, 256, 10, 256]
 
 
 def test_direct_scenes(planner):
     """Scenes the bricks cannot serve go to the direct kernels: rows not
-    whole words, sides beyond 16384, too many bricks, the Euclidean N, a
-    segment array that is only 4-byte aligned."""
+    whole words, sides beyond 16384, too many bricks, the Euclidean N in a
+    volume whose diagonal reaches 16385 (N up to 16384 keeps 2N within the
+    fill's 16-bit halves), a segment array that is only 4-byte aligned."""
     lg = (8, 6, 5)
     specs = [dict(n=10, dims=(48, 64, 64)), dict(n=10, dims=(32768, 32, 32)),
-             dict(n=10, dims=(16384, 16384, 64)), dict(n=10, dims=(64, 64, 64), flags=CLEAR | EUCLID),
+             dict(n=10, dims=(16384, 16384, 64)), dict(n=10, dims=(16384, 512, 64), flags=CLEAR | EUCLID),
              dict(n=10, dims=(64, 64, 64), segs=SEGS + 4)]
     res = planner(lg, specs)
     for sc, out in zip(specs, res):
@@ -82,6 +88,20 @@ def test_direct_scenes(planner):
         assert out["dim"] == sc["dims"] and out["n"] == 10
     assert res[3]["flags"] & F_EUCLID and res[3]["flags"] & F_A8
     assert not res[4]["flags"] & F_A8
+
+
+def test_euclid_brick_scenes(planner):
+    """The Euclidean N takes the bricks while the volume's diagonal
+    (sqrt of the sum of (side - 1)^2) stays below 16385; the same volumes
+    with the Chebyshev N take them regardless."""
+    lg = (8, 6, 5)
+    # 16383^2 + 127^2 + 63^2 < 16385^2 <= 16383^2 + 511^2 + 63^2
+    specs = [dict(n=10, dims=(64, 64, 64), flags=CLEAR | EUCLID), dict(n=10, dims=(16384, 128, 64), flags=EUCLID),
+             dict(n=10, dims=(16384, 512, 64), flags=EUCLID), dict(n=10, dims=(16384, 512, 64), flags=0)]
+    res = planner(lg, specs)
+    assert [bool(o["flags"] & F_DIRECT) for o in res] == [False, False, True, False]
+    assert res[0]["flags"] == F_CLEAR | F_EUCLID | F_A8 and res[0]["rows"] == expected_rows(10)
+    assert res[1]["flags"] == F_EUCLID | F_A8 and res[1]["nb"] == (64, 2, 2)
 
 
 def test_invalid_scenes(planner):

@@ -157,10 +157,11 @@ def test_batch_every_tuning(cand):
 
 
 def test_direct_scenes_in_batch():
-    """Scenes the bricks do not serve (rows not whole words, the Euclidean N
-    of eq. (1), a volume of 1 x 128 x 129 bricks, more than one histogram
-    holds, and an OR-mode Euclidean scene) run on the
-    direct kernels inside the same call, beside brick scenes."""
+    """Scenes the bricks do not serve (rows not whole words, a volume of
+    1 x 128 x 129 bricks, more than one histogram holds, the Euclidean N of
+    eq. (1) in a volume whose diagonal reaches 16385) run on the direct
+    kernels inside the same call, beside brick scenes, Euclidean ones among
+    them (cleared and ORed)."""
     rng = np.random.default_rng(7)
     specs = [(random_in((100, 50, 30), 4000, 70), (100, 50, 30), binding.VOX_GRID_CLEAR, None, True),
              (random_in((256, 128, 64), 20000, 71), (256, 128, 64), binding.VOX_GRID_CLEAR, None, True),
@@ -169,6 +170,8 @@ def test_direct_scenes_in_batch():
              (random_in((32, 8192, 4128), 3000, 73), (32, 8192, 4128), binding.VOX_GRID_CLEAR, None, False)]
     base = rng.integers(0, 2**32, size=binding.grid_words((96, 40, 20)), dtype=np.uint32)
     specs.append((random_in((96, 40, 20), 500, 74), (96, 40, 20), binding.VOX_GRID_EUCLID, base, True))
+    specs.append((random_in((16384, 512, 64), 200, 75), (16384, 512, 64),
+                  binding.VOX_GRID_CLEAR | binding.VOX_GRID_EUCLID, None, True))
     b = Batch(specs)
     status, _ = run_batch(b)
     assert status == binding.VOX_OK

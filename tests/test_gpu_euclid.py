@@ -9,6 +9,7 @@ from oracle import oracle
 from paper_2009_09500_amd import binding, workloads
 from tests import pins
 from tests.gpu_helpers import canaries_intact, dev, grid_host, to_dev, to_host
+from tests.test_gpu_grid import SHAPES, random_in, tuned
 from tests.test_gpu_list import _prepared
 
 pytestmark = pytest.mark.gpu
@@ -127,6 +128,77 @@ def test_grid_out_of_volume_segment():
     assert binding.vox_read_status(work) == binding.VOX_ERR_OUT_OF_RANGE
     ok = segs[[0, 2]]
     assert np.array_equal(grid_host(g), oracle.grid_euclid(ok, dims))
+
+
+@pytest.mark.parametrize("lg", SHAPES)
+def test_grid_brick_shapes(lg):
+    """The Euclidean N on the brick path, each compiled brick shape (taken
+    from the autotune cache): arbitrary-length segments into a cleared 512^3
+    volume, random segments ORed into a 96 x 64 x 32 volume."""
+    c = workloads.arbitrary_length(n=40_000, volume=512)
+    dims = (96, 64, 32)
+    rng = np.random.default_rng(81)
+    base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+    segs = random_in(dims, 30_000, 82)
+    with tuned(lg, [(c["dims"], 40_000), (dims, 30_000)]):
+        assert_grid(c["segs"], c["dims"])
+        assert_grid(segs, dims, base=base)
+
+
+def corner_to_corner(dims, n, seed, jitter=3):
+    """Segments from near one corner of the volume to near the opposite one,
+    every axis flipped at random: pieces with up to sqrt(3) times as many
+    samples as voxels along their longest axis."""
+    rng = np.random.default_rng(seed)
+    hi = np.array(dims) - 1
+    p0 = rng.integers(0, jitter + 1, (n, 3))
+    p1 = hi - rng.integers(0, jitter + 1, (n, 3))
+    flip = rng.integers(0, 2, (n, 3)).astype(bool)
+    a, b = np.where(flip, hi - p0, p0), np.where(flip, hi - p1, p1)
+    swap = rng.integers(0, 2, n).astype(bool)
+    a[swap], b[swap] = b[swap], a[swap].copy()
+    return np.concatenate([a, b], 1).astype(np.int32)
+
+
+@pytest.mark.parametrize("lg,dims", [((8, 6, 6), (512, 64, 64)), ((8, 6, 5), (512, 64, 64)),
+                                     ((7, 7, 6), (256, 256, 64)), ((7, 6, 6), (128, 128, 128))])
+def test_grid_long_pieces(lg, dims):
+    """Pieces with more samples than the brick's longest side (a piece of a
+    (255, 63, 63) diagonal has about 271): more chunks than any Chebyshev
+    piece, so the fill's chunk tables overflow and a group's two record sets
+    run in turn."""
+    segs = corner_to_corner(dims, 20_000, 84 + lg[2])
+    with tuned(lg, [(dims, 20_000)]):
+        assert_grid(segs, dims)
+
+
+@pytest.mark.parametrize("n", [16384, 16385])
+def test_grid_direct_brick_boundary(n):
+    """Plain calls of at most 16384 segments take the direct path, larger
+    ones the brick path, with the Euclidean N too: both sides, cleared and
+    ORed into a volume."""
+    dims = (256, 128, 64)
+    segs = random_in(dims, n, 700 + n)
+    assert_grid(segs, dims)
+    rng = np.random.default_rng(n + 1)
+    base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+    assert_grid(segs, dims, base=base)
+
+
+def test_grid_longest_brick_length():
+    """N = 16384, the longest the brick path takes (2N = 32768 fills the
+    fill's biased 16-bit halves): a 16384 x 192 x 64 volume, whose diagonal
+    is just below 16385, with 300 segments along its length (the corner to
+    corner ones have N = 16384) among 16 100 short ones."""
+    dims = (16384, 192, 64)
+    rng = np.random.default_rng(85)
+    long = corner_to_corner(dims, 300, 86, jitter=2)
+    long[0] = [0, 0, 0, 16383, 191, 63]
+    p0 = np.stack([rng.integers(0, d, 16_100) for d in dims], 1)
+    p1 = np.clip(p0 + rng.integers(-40, 41, p0.shape), 0, np.array(dims) - 1)
+    segs = np.concatenate([long, np.concatenate([p0, p1], 1).astype(np.int32)])
+    assert oracle.default().length_euclid(long[0]) == 16384
+    assert_grid(segs, dims)
 
 
 def test_list_full_fixed_length_sampled():
