@@ -216,6 +216,37 @@ __device__ __forceinline__ uint32_t xcd_row(uint32_t w, uint32_t G) {
 
 constexpr int kPlanBlock = 1024;
 
+// The table header, status word, flags and brick queues of a launch whose
+// scenes have been numbered (one lane).
+__device__ __forceinline__ void write_table(uint8_t* work, const BrickLaunch& L, uint64_t work_bytes, uint32_t rows_c,
+                                            uint32_t bricks_c, uint32_t direct_c, uint32_t max_nb, uint64_t hist_c,
+                                            uint64_t segs_c, uint64_t dsegs_c, bool bad) {
+    uint8_t* tb = work + kWorkTable;
+    BrickTable t{};
+    t.magic = kTableMagic;
+    t.n_scenes = L.n_scenes;
+    t.rows = rows_c;
+    t.bricks = bricks_c;
+    for (int a = 0; a < 3; ++a) t.lg[a] = L.lg[a];
+    t.max_nb = max_nb;
+    t.hist_words = hist_c;
+    t.data_off = kWorkTable + L.table_bytes;
+    t.n_direct = direct_c;
+    t.row_cap = L.rows;
+    t.direct_segs = dsegs_c;
+    *reinterpret_cast<BrickTable*>(tb) = t;
+    const bool fits = segs_c <= L.total_segments && rows_c <= L.rows && bricks_c <= L.bricks;
+    const WorkView wv = work_view(work, t.data_off, t.hist_words, t.bricks);
+    const bool room = wv.rec_off <= work_bytes;
+    uint32_t* w = reinterpret_cast<uint32_t*>(work);
+    const int32_t st = bad ? kStatusInvalid : (fits ? 0 : kStatusLaunch);
+    w[kWStatus] = (uint32_t)st;
+    w[kWOk] = (st == 0 && room && bricks_c > 0) ? 1u : 0u;
+    w[kWDirectAll] = room ? 0u : 1u;
+    for (int x = 0; x < kXcds; ++x) w[kWQueues + x] = 0u;
+    *wv.pieces = 0;
+}
+
 // The plan: one block reads the caller's scenes (the device vox_scene array,
 // or the one scene of a plain call passed by value), checks each against the
 // argument rules, decides which scenes the brick kernels serve (8-byte-aligned
@@ -281,29 +312,27 @@ __global__ __launch_bounds__(kPlanBlock) void k_brick_plan(const vox_scene* __re
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    BrickTable t{};
-    t.magic = kTableMagic;
-    t.n_scenes = L.n_scenes;
-    t.rows = rows_c;
-    t.bricks = bricks_c;
-    for (int a = 0; a < 3; ++a) t.lg[a] = L.lg[a];
-    t.max_nb = max_nb_s;
-    t.hist_words = hist_c;
-    t.data_off = kWorkTable + L.table_bytes;
-    t.n_direct = direct_c;
-    t.row_cap = L.rows;
-    t.direct_segs = dsegs_c;
-    *reinterpret_cast<BrickTable*>(tb) = t;
-    const bool fits = segs_c <= L.total_segments && rows_c <= L.rows && bricks_c <= L.bricks;
-    const WorkView wv = work_view(work, t.data_off, t.hist_words, t.bricks);
-    const bool room = wv.rec_off <= work_bytes;
-    uint32_t* w = reinterpret_cast<uint32_t*>(work);
-    const int32_t st = bad_s ? kStatusInvalid : (fits ? 0 : kStatusLaunch);
-    w[kWStatus] = (uint32_t)st;
-    w[kWOk] = (st == 0 && room && bricks_c > 0) ? 1u : 0u;
-    w[kWDirectAll] = room ? 0u : 1u;
-    for (int x = 0; x < kXcds; ++x) w[kWQueues + x] = 0u;
-    *wv.pieces = 0;
+    write_table(work, L, work_bytes, rows_c, bricks_c, direct_c, max_nb_s, hist_c, segs_c, dsegs_c, bad_s != 0);
+}
+
+// The plan of a plain call (its one scene passed by value): the table
+// k_brick_plan writes for a single scene, by one lane, with no block scans.
+__global__ __launch_bounds__(kWave) void k_brick_plan_one(vox_scene one, BrickLaunch L, uint8_t* __restrict__ work,
+                                                         uint64_t work_bytes) {
+    if (threadIdx.x != 0) return;
+    BrickScene b;
+    const bool valid = plan_scene(one, L.lg, L.segs_per_row, b);
+    const bool isd = (b.flags & kSceneDirect) != 0;
+    b.row_base = 0;
+    b.brick_base = 0;
+    b.hist_off = 0;
+    uint8_t* tb = work + kWorkTable;
+    BrickScene* out = reinterpret_cast<BrickScene*>(tb + kTableScenes);
+    out[0] = b;
+    if (isd) reinterpret_cast<uint32_t*>(out + 1)[0] = 0u;
+    const uint32_t nb = isd ? 0u : b.bg.nbricks;
+    const uint64_t n = b.n > 0 ? (uint64_t)b.n : 0u;
+    write_table(work, L, work_bytes, b.rows, nb, isd ? 1u : 0u, nb, (uint64_t)b.rows * nb, n, isd ? n : 0u, !valid);
 }
 
 // Scene of every histogram row and of every brick (tables of several
@@ -382,7 +411,7 @@ __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs,
         if (counts) {
             // Counts: N + 1 for the Chebyshev N; with the Euclidean N 0
             // outside the volume here, the voxels after duplicate removal
-            // inside it from the histogram's wave pass (euclid_count_wave).
+            // inside it from the histogram's count pass (euclid_counts).
             if (euclid) {
                 if (!inside) counts[base + t] = 0;
             } else {
@@ -456,45 +485,116 @@ __device__ __forceinline__ void walk_init(WalkState& w, const StagedSeg& g, cons
     w.klo = 0;
 }
 
-// Voxels of an in-volume segment under the Euclidean N (consecutive
-// duplicates removed), counted by the 64 lanes of a wave together: 1 + the
-// steps k = 1..N at which some axis moves.  With r_a(k) = (2k a + N - neg_a)
-// mod 2N, the remainder of eq. (3)'s division, axis a moves at step k
-// exactly when r_a(k) < 2a (r_a(k) = r_a(k-1) + 2a, less 2N when it moves).
-// Lane l takes k = 1 + l, 65 + l, ...: its remainders advance by
-// (128 a) mod 2N a round.  N <= 16384 in a brick scene, inside the
-// divisions' domain.  Every lane returns the count.
-__device__ __forceinline__ uint32_t euclid_count_wave(const StagedSeg& g, uint32_t lane) {
-    uint32_t a[3], neg[3], ss = 0;
+// Steps k0 + 1 ... k0 + len (k0 + len <= N) of an in-volume segment under
+// the Euclidean N at which some axis moves.  With r_a(k) = (2k a + N - neg_a)
+// mod 2N, the remainder of eq. (3)'s division, axis a moves at step k exactly
+// when r_a(k - 1) + 2a reaches 2N (a <= N).  One division per axis gives
+// r_a(k0); the steps then run on biased 16-bit halves as in the fill
+// (N <= 16384 in a brick scene).
+__device__ __forceinline__ uint32_t euclid_moves(const StagedSeg& g, uint32_t N, uint32_t k0, uint32_t len) {
+    uint32_t a[3], neg[3], r[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const int32_t d = (int32_t)g.p1[ax] - (int32_t)g.p0[ax];
         neg[ax] = d < 0;
         a[ax] = (uint32_t)(d < 0 ? -d : d);
-        ss += a[ax] * a[ax];
     }
-    const uint32_t N = isqrt31(ss);
-    if (N == 0) return 1u;
     const uint32_t two_n = 2u * N;
     const float rcpd = rcp_down(two_n);
-    uint32_t r[3], D[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         uint32_t q;
-        divmod_down(2u * a[ax] * (1u + lane) + N - neg[ax], two_n, rcpd, q, r[ax]);
-        divmod_down(128u * a[ax], two_n, rcpd, q, D[ax]);
+        divmod_down(2u * __umul24(k0, a[ax]) + N - neg[ax], two_n, rcpd, q, r[ax]);
     }
+    u16x2 E = {(uint16_t)(r[0] + 32768u - two_n), (uint16_t)(r[1] + 32768u - two_n)};
+    u16x2 Ez = {(uint16_t)(r[2] + 32768u - two_n), 0};
+    const u16x2 T = {(uint16_t)(2u * a[0]), (uint16_t)(2u * a[1])};
+    const u16x2 Tz = {(uint16_t)(2u * a[2]), 0};
+    const u16x2 N2 = {(uint16_t)two_n, (uint16_t)two_n};
+    const i16x2 k15 = {15, 15};
     uint32_t moves = 0;
-    for (uint32_t k = 1u + lane; k - lane <= N; k += kWave) {
-        const bool mv = k <= N && (r[0] < 2u * a[0] || r[1] < 2u * a[1] || r[2] < 2u * a[2]);
-        moves += (uint32_t)__popcll(__ballot(mv));
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const uint32_t t = r[ax] + D[ax];
-            r[ax] = t >= two_n ? t - two_n : t;
-        }
+#pragma unroll 4
+    for (uint32_t t = 0; t < len; ++t) {
+        E = E + T;
+        const i16x2 C = __builtin_bit_cast(i16x2, E) >> k15;  // -1 where the axis moves
+        E = E + __builtin_bit_cast(u16x2, C) * N2;
+        Ez = Ez + Tz;
+        const i16x2 Cz = __builtin_bit_cast(i16x2, Ez) >> k15;
+        Ez = Ez + __builtin_bit_cast(u16x2, Cz) * N2;
+        moves += (__builtin_bit_cast(uint32_t, C) | __builtin_bit_cast(uint32_t, Cz)) != 0u ? 1u : 0u;
     }
-    return 1u + moves;
+    return moves;
+}
+
+// Per-wave LDS of the Euclidean counts: the wave's 64 segments' first chunk
+// numbers, lengths N and move counts.
+struct CountScratch {
+    uint32_t pre[kWave], n[kWave], cnt[kWave];
+};
+constexpr size_t kCountScratch = (size_t)(kHistBlock / kWave) * sizeof(CountScratch);
+
+// Voxels (after duplicate removal) of the staged in-volume segments under
+// the Euclidean N: 1 + the steps at which some axis moves.  Each wave takes
+// 32 segments in walk order (so that a row of 512 segments keeps all 16
+// waves busy), one per lane of its first half, cuts them into chunks of 64
+// steps (a prefix over the lanes numbers the chunks), and runs the chunks 64
+// at a time, one per lane, each lane finding its chunk's segment by binary
+// search over the prefix; a segment's moves are summed with LDS atomics.
+// counts: the stage's first segment's slot.
+constexpr uint32_t kCountGroup = 32;
+template <int kN>
+__device__ __forceinline__ void euclid_counts(const Stage<kN>& st, int32_t* __restrict__ counts,
+                                              CountScratch* scratch) {
+    const uint32_t lane = __lane_id();
+    CountScratch& w = scratch[threadIdx.x / kWave];
+    const uint32_t nvalid = st.nvalid;
+    for (uint32_t g0 = (threadIdx.x / kWave) * kCountGroup; g0 < nvalid;
+         g0 += (kHistBlock / kWave) * kCountGroup) {
+        const uint32_t i = g0 + lane;
+        const bool mine = lane < kCountGroup && i < nvalid;
+        uint32_t j = 0, N = 0;
+        if (mine) {
+            j = st.order[i];
+            const StagedSeg& g = st.seg[j];
+            uint32_t ss = 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int32_t d = (int32_t)g.p1[ax] - (int32_t)g.p0[ax];
+                ss += (uint32_t)(d * d);
+            }
+            N = isqrt31(ss);
+        }
+        const uint32_t ch = (N + kWave - 1) / kWave;
+        const uint32_t incl = wave_inclusive_sum(ch);
+        const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+        w.pre[lane] = incl - ch;
+        w.n[lane] = N;
+        w.cnt[lane] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t q0 = 0; q0 < total; q0 += kWave) {
+            const uint32_t q = q0 + lane;
+            if (q < total) {
+                // The last lane whose first chunk is at most q owns chunk q.
+                uint32_t o = 0;
+#pragma unroll
+                for (uint32_t step = kWave / 2; step > 0; step >>= 1) o += w.pre[o + step] <= q ? step : 0u;
+                const uint32_t n = w.n[o];
+                const uint32_t k0 = (q - w.pre[o]) * (uint32_t)kWave;
+                const uint32_t len = n - k0 < (uint32_t)kWave ? n - k0 : (uint32_t)kWave;
+                atomicAdd(&w.cnt[o], euclid_moves(st.seg[st.order[g0 + o]], n, k0, len));
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (mine) counts[j] = (int32_t)(1u + w.cnt[lane]);
+        // The scratch is rewritten by the wave's next 64 segments.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // Walks the ordered staged segments: each wave takes the next 64 in order
@@ -536,7 +636,7 @@ __device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeo
 // Histogram of one row: its segments' pieces per brick of its scene.
 template <int kN>
 __device__ __forceinline__ void hist_row(const BrickScene& sc, uint32_t g, Stage<kN>& st, uint32_t* lh,
-                                         const WorkView& wv) {
+                                         CountScratch* cscratch, const WorkView& wv) {
     const BrickGeom& bg = sc.bg;
     const uint32_t NB = bg.nbricks;
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) lh[b] = 0;
@@ -551,18 +651,13 @@ __device__ __forceinline__ void hist_row(const BrickScene& sc, uint32_t g, Stage
                      [&](uint32_t b, uint32_t, uint32_t, uint32_t, int32_t, int32_t, int32_t, uint32_t) {
                          atomicAdd(&lh[b], 1u);
                      });
-        if (euclid && sc.counts) {
-            // The in-volume segments' counts, one segment per wave at a time.
-            const uint32_t lane = __lane_id();
-            for (uint32_t i = threadIdx.x / kWave; i < st.nvalid; i += kHistBlock / kWave) {
-                const uint32_t j = st.order[i];
-                const uint32_t c = euclid_count_wave(st.seg[j], lane);
-                if (lane == 0) sc.counts[base + j] = (int32_t)c;
-            }
-        }
+        if (euclid && sc.counts) euclid_counts(st, sc.counts + base, cscratch);
         lds_barrier();
     }
-    if (bad) atomicOr(wv.status, kStatusOutOfRange);
+    // (Out-of-volume segments are reported by the scatter, or by the direct
+    // kernels when they serve the scene: the status word may still be
+    // written by this kernel's first workgroup in a plain call.)
+    (void)bad;
     lds_barrier();
     uint32_t* row = wv.hist + sc.hist_off + (size_t)g * NB;
     for (uint32_t b = threadIdx.x; b < NB; b += kHistBlock) row[b] = lh[b];
@@ -573,7 +668,8 @@ __device__ __forceinline__ void hist_row(const BrickScene& sc, uint32_t g, Stage
 // workgroup takes the layout its scene's brick count allows.
 constexpr size_t kHistLdsBig = sizeof(Stage<kStageBig>) + (size_t)kBigStageBricks * 4;
 constexpr size_t kHistLdsSmall = sizeof(Stage<kStage>) + (size_t)kMaxBricks * 4;
-constexpr size_t kHistLds = kHistLdsBig > kHistLdsSmall ? kHistLdsBig : kHistLdsSmall;
+// ... then the per-wave scratch of the Euclidean counts.
+constexpr size_t kHistLds = (kHistLdsBig > kHistLdsSmall ? kHistLdsBig : kHistLdsSmall) + kCountScratch;
 static_assert(kHistLds <= 163840, "histogram LDS fits a workgroup");
 
 __global__ __launch_bounds__(kHistBlock) void k_brick_hist(uint8_t* __restrict__ work) {
@@ -586,10 +682,80 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_hist(uint8_t* __restrict__
     const uint32_t g = r - sc.row_base;
     if (sc.bg.nbricks <= kBigStageBricks) {
         auto* st = reinterpret_cast<Stage<kStageBig>*>(hist_lds);
-        hist_row(sc, g, *st, reinterpret_cast<uint32_t*>(hist_lds + sizeof(Stage<kStageBig>)), wv);
+        hist_row(sc, g, *st, reinterpret_cast<uint32_t*>(hist_lds + sizeof(Stage<kStageBig>)),
+                 reinterpret_cast<CountScratch*>(hist_lds + kHistLdsBig), wv);
     } else {
         auto* st = reinterpret_cast<Stage<kStage>*>(hist_lds);
-        hist_row(sc, g, *st, reinterpret_cast<uint32_t*>(hist_lds + sizeof(Stage<kStage>)), wv);
+        hist_row(sc, g, *st, reinterpret_cast<uint32_t*>(hist_lds + sizeof(Stage<kStage>)),
+                 reinterpret_cast<CountScratch*>(hist_lds + kHistLdsSmall), wv);
+    }
+}
+
+// A plain call's plan and histogram in one launch: every workgroup plans the
+// call's one scene (passed by value) itself, the first one also writes the
+// table and header words for the kernels that follow (k_brick_plan_one's
+// output), and the workgroups go on to their histogram rows when the brick
+// kernels may run.
+__global__ __launch_bounds__(kHistBlock) void k_brick_plan_hist(vox_scene one, BrickLaunch L,
+                                                               uint8_t* __restrict__ work, uint64_t work_bytes) {
+    extern __shared__ __align__(16) uint8_t hist_lds[];
+    BrickScene sc;
+    const bool valid = plan_scene(one, L.lg, L.segs_per_row, sc);
+    const bool isd = (sc.flags & kSceneDirect) != 0;
+    sc.row_base = 0;
+    sc.brick_base = 0;
+    sc.hist_off = 0;
+    const uint32_t nb = isd ? 0u : sc.bg.nbricks;
+    const uint64_t n = sc.n > 0 ? (uint64_t)sc.n : 0u;
+    const uint64_t hist_c = (uint64_t)sc.rows * nb;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        BrickScene* out = reinterpret_cast<BrickScene*>(work + kWorkTable + kTableScenes);
+        out[0] = sc;
+        if (isd) reinterpret_cast<uint32_t*>(out + 1)[0] = 0u;
+        write_table(work, L, work_bytes, sc.rows, nb, isd ? 1u : 0u, nb, hist_c, n, isd ? n : 0u, !valid);
+    }
+    // The same decision as the ok word written above.
+    const WorkView wv = work_view(work, kWorkTable + L.table_bytes, hist_c, nb);
+    const bool fits = n <= L.total_segments && sc.rows <= L.rows && nb <= L.bricks;
+    if (!valid || !fits || wv.rec_off > work_bytes || nb == 0) return;
+    const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
+    if (r >= sc.rows) return;
+    if (nb <= kBigStageBricks) {
+        auto* st = reinterpret_cast<Stage<kStageBig>*>(hist_lds);
+        hist_row(sc, r, *st, reinterpret_cast<uint32_t*>(hist_lds + sizeof(Stage<kStageBig>)),
+                 reinterpret_cast<CountScratch*>(hist_lds + kHistLdsBig), wv);
+    } else {
+        auto* st = reinterpret_cast<Stage<kStage>*>(hist_lds);
+        hist_row(sc, r, *st, reinterpret_cast<uint32_t*>(hist_lds + sizeof(Stage<kStage>)),
+                 reinterpret_cast<CountScratch*>(hist_lds + kHistLdsSmall), wv);
+    }
+}
+
+constexpr int kBaseBlock = 1024;
+
+// bin_base[b] = sum of totals before global brick b, bin_base[NB] = total,
+// by one block of kBlock threads: each thread sums a run of consecutive
+// totals, one block scan of the run sums (64-bit; lds: kBlock / 64 entries),
+// then each thread writes its run's offsets.  The direct kernels take over
+// when the records do not fit the workspace (or reach 2^32 - 1).
+template <int kBlock>
+__device__ __forceinline__ void scan_totals(const WorkView& wv, uint32_t NB, uint64_t work_bytes, uint64_t* lds) {
+    const uint32_t per = (NB + kBlock - 1) / kBlock;
+    const uint32_t lo = threadIdx.x * per < NB ? threadIdx.x * per : NB;
+    const uint32_t hi = lo + per < NB ? lo + per : NB;
+    uint64_t run = 0;
+    for (uint32_t i = lo; i < hi; ++i) run += wv.totals[i];
+    uint64_t total;
+    uint64_t off = block_exclusive_sum<kBlock>(run, lds, total);
+    for (uint32_t i = lo; i < hi; ++i) {
+        wv.bin_base[i] = (uint32_t)off;
+        off += wv.totals[i];
+    }
+    if (threadIdx.x == 0) {
+        wv.bin_base[NB] = (uint32_t)total;
+        *wv.pieces = total;
+        const uint64_t cap = work_bytes > wv.rec_off ? (work_bytes - wv.rec_off) / sizeof(Piece) : 0u;
+        if (total > cap || total >= 0xFFFFFFFFull) *wv.direct_all = 1u;
     }
 }
 
@@ -650,33 +816,17 @@ __global__ __launch_bounds__(256) void k_brick_colscan(uint8_t* __restrict__ wor
     }
 }
 
-constexpr int kBaseBlock = 1024;
 
 // One block: bin_base[b] = sum of totals before global brick b;
 // bin_base[bricks] = total.  When the records do not fit the rest of the
 // workspace (or their count reaches 2^32 - 1), the direct kernels serve
 // every scene instead of the scatter and the fill.
 __global__ __launch_bounds__(kBaseBlock) void k_brick_base(uint8_t* __restrict__ work, uint64_t work_bytes) {
-    __shared__ uint32_t lds[kBaseBlock / kWave];
+    __shared__ uint64_t lds[kBaseBlock / kWave];
     const TableView tv = table_view(work + kWorkTable);
     const WorkView wv = work_of(work, tv);
     if (*wv.ok == 0) return;
-    const uint32_t NB = tv.h.bricks;
-    uint64_t carry = 0;
-    for (uint32_t c0 = 0; c0 < NB; c0 += kBaseBlock) {
-        const uint32_t i = c0 + threadIdx.x;
-        const uint32_t v = i < NB ? wv.totals[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_sum<kBaseBlock>(v, lds, tot);
-        if (i < NB) wv.bin_base[i] = (uint32_t)carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        wv.bin_base[NB] = (uint32_t)carry;
-        *wv.pieces = carry;
-        const uint64_t cap = work_bytes > wv.rec_off ? (work_bytes - wv.rec_off) / sizeof(Piece) : 0u;
-        if (carry > cap || carry >= 0xFFFFFFFFull) *wv.direct_all = 1u;
-    }
+    scan_totals<kBaseBlock>(wv, tv.h.bricks, work_bytes, lds);
 }
 
 // The record of the piece of staged segment g with k-window [klo, khi] in
@@ -799,6 +949,7 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restric
         }
         lds_barrier();
     }
+    if (bad) atomicOr(wv.status, kStatusOutOfRange);
 }
 
 // ------------------------------------------------------------------- fill
@@ -1028,14 +1179,29 @@ __device__ __forceinline__ u32x4 load_stream(const u32x4* p) {
 
 // A brick's records [lo, hi) in four quarters, one per SIMD of the CU.
 constexpr int kQuarters = 4;
+constexpr int kSets = 2;  // piece records per lane in a wave group
 
 __device__ __forceinline__ uint32_t quarter_bound(uint32_t lo, uint32_t hi, uint32_t k) {
     return lo + (uint32_t)(((uint64_t)(hi - lo) * k) / kQuarters);
 }
 
-__device__ __forceinline__ void set_quarters(uint32_t* cursors, uint32_t lo, uint32_t hi) {
+// Cursors of the quarters' groups after the first `skip` records of each,
+// which the waves take without a claim (first_group).
+__device__ __forceinline__ void set_quarters(uint32_t* cursors, uint32_t lo, uint32_t hi, uint32_t skip) {
 #pragma unroll
-    for (uint32_t k = 0; k < (uint32_t)kQuarters; ++k) cursors[k] = quarter_bound(lo, hi, k);
+    for (uint32_t k = 0; k < (uint32_t)kQuarters; ++k) cursors[k] = quarter_bound(lo, hi, k) + skip;
+}
+
+// The first group of a wave in a brick with records [lo, hi): group `slot`
+// of its SIMD's quarter qu (the waves of a SIMD take slots 0, 1, ...), its
+// records loaded now.  q_hi: the end of the quarter.
+__device__ __forceinline__ void first_group(const u32x4* recv, uint32_t lo, uint32_t hi, uint32_t qu, uint32_t slot,
+                                            uint32_t lane, uint32_t& gbase, uint32_t& q_hi, u32x4& r0, u32x4& r1) {
+    constexpr uint32_t kGroup = kWave * kSets;
+    q_hi = quarter_bound(lo, hi, qu + 1u);
+    gbase = quarter_bound(lo, hi, qu) + slot * kGroup;
+    r0 = (gbase + lane < q_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
+    r1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
 }
 
 // Launch shape of the fill kernel: kWgs workgroups per CU, of 1024 threads
@@ -1050,18 +1216,18 @@ struct FillCfg {
     static constexpr int kBlock = kWgs == 1 ? 1024 : 512;
     static constexpr int kWgsPerCu = kWgs;
 };
-constexpr int kSets = 2;  // piece records per lane in a wave group
 
 // The pieces of one brick that this wave runs: groups of 128 records (two
 // per lane: sets 0 and 1), taken from its SIMD's quarter qu of the brick's
-// records [p_lo, p_hi) (waves w and w + 4k share a SIMD), so the four SIMDs
-// get even shares of the brick's work; the next group is claimed and loaded
-// before the current one runs.  kEuclid: the brick's scene uses the
-// Euclidean N of eq. (1).
+// records (waves w and w + 4k share a SIMD), so the four SIMDs get even
+// shares of the brick's work.  The first group (gbase, records rn0 and rn1)
+// comes loaded (first_group); each next group is claimed and loaded before
+// the current one runs.  q_hi: the end of the quarter.  kEuclid: the brick's
+// scene uses the Euclidean N of eq. (1).
 template <bool kEuclid, int LGX, int LGY, int LGZ, int kEntCap>
 __device__ __forceinline__ void fill_records(uint32_t* brick, uint16_t* my_ent, const u32x4* recv,
-                                             uint32_t* cursor_s, uint32_t qu, uint32_t p_lo, uint32_t p_hi,
-                                             uint32_t lane) {
+                                             uint32_t* cursor_s, uint32_t qu, uint32_t q_hi, uint32_t gbase,
+                                             u32x4 rn0, u32x4 rn1, uint32_t lane) {
     constexpr int kChunk = kFillChunk;
     constexpr int kGroup = kWave * kSets;  // records per wave group
     constexpr int kMaxChunks = (MaxSamples<kEuclid, LGX, LGY, LGZ>::kValue + kChunk - 1) / kChunk;  // per piece
@@ -1070,12 +1236,6 @@ __device__ __forceinline__ void fill_records(uint32_t* brick, uint16_t* my_ent, 
     constexpr bool kSplit = kEntCap < kGroup * kMaxChunks;
     static_assert(kMaxChunks <= 512, "chunk entries: lane | set << 6 | j << 7");
     static_assert(kEntCap >= kWave * kMaxChunks, "one record set's chunks always fit the table");
-    const uint32_t q_hi = quarter_bound(p_lo, p_hi, qu + 1u);
-    uint32_t gbase = 0;
-    if (lane == 0) gbase = atomicAdd(&cursor_s[qu], (uint32_t)kGroup);
-    gbase = __builtin_amdgcn_readfirstlane(gbase);
-    u32x4 rn0 = (gbase + lane < q_hi) ? load_stream(recv + gbase + lane) : (u32x4){0u, 0u, 0u, 0u};
-    u32x4 rn1 = (gbase + kWave + lane < q_hi) ? load_stream(recv + gbase + kWave + lane) : (u32x4){0u, 0u, 0u, 0u};
     while (gbase < q_hi) {
         const u32x4 r0 = rn0, r1 = rn1;
         const uint32_t len0 = gbase + lane < q_hi ? record_length<kEuclid, LGX, LGY, LGZ>(r0.w) : 0u;
@@ -1231,6 +1391,10 @@ void k_brick_fill(uint8_t* __restrict__ work) {
     uint16_t* my_ent = ent[wave];
     const u32x4* recv = reinterpret_cast<const u32x4*>(wv.recs);
 
+    // The waves of a SIMD take the first kWaves / 4 groups of its quarter
+    // without a claim (first_group); the cursors start after them.
+    constexpr uint32_t kSkip = (uint32_t)(kWaves / kQuarters) * (uint32_t)kGroup;
+    const uint32_t qu = wave % kQuarters, slot = wave / kQuarters;
     // The next brick and its bin range are claimed by thread 0 at the start
     // of the current one, so their memory latency overlaps this brick's work.
     if (threadIdx.x == 0) {
@@ -1238,7 +1402,7 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         next_s[0] = nb;
         next_s[1] = nb < NB ? bin_base[nb] : 0u;
         next_s[2] = nb < NB ? bin_base[nb + 1] : 0u;
-        set_quarters(cursor_s, next_s[1], next_s[2]);
+        set_quarters(cursor_s, next_s[1], next_s[2], kSkip);
     }
     {
         u32x4* b4 = reinterpret_cast<u32x4*>(brick);
@@ -1247,6 +1411,9 @@ void k_brick_fill(uint8_t* __restrict__ work) {
     lds_barrier();
     uint32_t b = next_s[0];
     uint32_t p_lo = next_s[1], p_hi = next_s[2];
+    uint32_t gbase = 0, q_hi = 0;
+    u32x4 rn0 = {0u, 0u, 0u, 0u}, rn1 = {0u, 0u, 0u, 0u};
+    if (b < NB) first_group(recv, p_lo, p_hi, qu, slot, lane, gbase, q_hi, rn0, rn1);
 
     while (b < NB) {
         uint32_t nb = 0, nlo = 0, nhi = 0;
@@ -1282,11 +1449,12 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         // ended the previous brick.)
 
         // This wave's pieces of the brick.
-        const uint32_t qu = wave % kQuarters;
         if (sc.flags & kSceneEuclid)
-            fill_records<true, LGX, LGY, LGZ, kEntCap>(brick, my_ent, recv, cursor_s, qu, p_lo, p_hi, lane);
+            fill_records<true, LGX, LGY, LGZ, kEntCap>(brick, my_ent, recv, cursor_s, qu, q_hi, gbase, rn0, rn1,
+                                                       lane);
         else
-            fill_records<false, LGX, LGY, LGZ, kEntCap>(brick, my_ent, recv, cursor_s, qu, p_lo, p_hi, lane);
+            fill_records<false, LGX, LGY, LGZ, kEntCap>(brick, my_ent, recv, cursor_s, qu, q_hi, gbase, rn0, rn1,
+                                                        lane);
         // Hand over the next brick (read by all after the barrier).
         if (threadIdx.x == 0) {
             next_s[0] = nb;
@@ -1294,6 +1462,12 @@ void k_brick_fill(uint8_t* __restrict__ work) {
             next_s[2] = nhi;
         }
         lds_barrier();  // every wave done with this brick
+        const uint32_t b_next = next_s[0], lo_next = next_s[1], hi_next = next_s[2];
+        // The next brick's first group is loaded before the flush's stores:
+        // a wait for a load also waits for every store issued before it, so
+        // loaded after the flush its records would arrive only once the
+        // whole brick had been written.
+        if (b_next < NB) first_group(recv, lo_next, hi_next, qu, slot, lane, gbase, q_hi, rn0, rn1);
 
         // Flush: brick rows -> volume words, zeroing the brick on the way.
         // The owner writes every word of its brick, so a clearing call needs
@@ -1367,10 +1541,10 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         }
         // Every word that can hold a bit (inside the volume) was read and
         // zeroed above; the others were never set.  Next brick:
-        b = next_s[0];
-        p_lo = next_s[1];
-        p_hi = next_s[2];
-        if (threadIdx.x == 0) set_quarters(cursor_s, p_lo, p_hi);
+        b = b_next;
+        p_lo = lo_next;
+        p_hi = hi_next;
+        if (threadIdx.x == 0) set_quarters(cursor_s, p_lo, p_hi, kSkip);
         lds_barrier();
     }
 }
@@ -1556,30 +1730,47 @@ hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunc
             hipError_t r = hipFuncSetAttribute((const void*)k_brick_hist, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                (int)kHistLds);
             if (r != hipSuccess) return r;
+            r = hipFuncSetAttribute((const void*)k_brick_plan_hist, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kHistLds);
+            if (r != hipSuccess) return r;
             return hipFuncSetAttribute((const void*)k_brick_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(kMaxBricks * sizeof(uint32_t)));
         }();
         if (attr != hipSuccess) return attr;
     }
-    {
-        KernelTimer t("brick_plan", stream);
-        vox_scene os{};
-        if (one) os = *static_cast<const vox_scene*>(one);
-        k_brick_plan<<<1, kPlanBlock, 0, stream>>>(static_cast<const vox_scene*>(d_scenes), os, one ? 1u : 0u, L,
-                                                   work, (uint64_t)work_bytes);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (L.n_scenes > 1) {
-        KernelTimer t("brick_expand", stream);
-        const uint32_t wgs = L.n_scenes < 2048u ? L.n_scenes : 2048u;
-        k_brick_expand<<<wgs, 256, 0, stream>>>(work);
+    // A plain call (one scene by value, at most kMaxBricks bricks): the plan
+    // runs inside the histogram launch, five launches in all; a batch takes
+    // seven or more.
+    const bool plain = one != nullptr && L.n_scenes == 1 && L.bricks <= kMaxBricks;
+    if (plain) {
+        KernelTimer t("brick_plan_hist", stream);
+        k_brick_plan_hist<<<L.rows, kHistBlock, kHistLds, stream>>>(*static_cast<const vox_scene*>(one), L, work,
+                                                                    (uint64_t)work_bytes);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        {
+            KernelTimer t("brick_plan", stream);
+            vox_scene os{};
+            if (one) os = *static_cast<const vox_scene*>(one);
+            if (one && L.n_scenes == 1)
+                k_brick_plan_one<<<1, kWave, 0, stream>>>(os, L, work, (uint64_t)work_bytes);
+            else
+                k_brick_plan<<<1, kPlanBlock, 0, stream>>>(static_cast<const vox_scene*>(d_scenes), os,
+                                                           one ? 1u : 0u, L, work, (uint64_t)work_bytes);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (L.n_scenes > 1) {
+            KernelTimer t("brick_expand", stream);
+            const uint32_t wgs = L.n_scenes < 2048u ? L.n_scenes : 2048u;
+            k_brick_expand<<<wgs, 256, 0, stream>>>(work);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        {
+            KernelTimer t("brick_hist", stream);
+            k_brick_hist<<<L.rows, kHistBlock, kHistLds, stream>>>(work);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    {
-        KernelTimer t("brick_hist", stream);
-        k_brick_hist<<<L.rows, kHistBlock, kHistLds, stream>>>(work);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         KernelTimer t("brick_colscan", stream);
         uint32_t blocks = (L.bricks + kColBins - 1) / kColBins;

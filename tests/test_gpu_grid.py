@@ -88,6 +88,37 @@ def test_out_of_volume_segment_is_skipped():
     assert np.array_equal(grid_host(g), oracle.grid(keep, dims))
 
 
+@pytest.mark.parametrize("euclid", [False, True])
+def test_out_of_volume_segments_brick_path(euclid):
+    """Segments with an end point outside the volume in a brick-path call
+    (20 000 segments): the status reports them, the volume holds the others'
+    voxels, and a second call on the same workspace without them reports OK
+    (the status word starts from zero in every call)."""
+    torch = pytest.importorskip("torch")
+    dims = (256, 128, 64)
+    segs = random_in(dims, 20_000, 15)
+    bad = segs.copy()
+    bad[17] = [0, 0, 0, 256, 10, 10]
+    bad[9_999] = [-1, 3, 3, 5, 5, 5]
+    bad[19_999] = [5, 5, 5, 5, 5, 64]
+    flags = binding.VOX_GRID_CLEAR | (binding.VOX_GRID_EUCLID if euclid else 0)
+    g = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev())
+    c = torch.empty(len(bad), dtype=torch.int32, device=dev())
+    work = binding.workspace(binding.vox_grid_workspace_bytes(len(bad), dims), dev())
+    binding.vox_segments_to_grid(to_dev(bad), dims, g, c, flags, work)
+    assert binding.vox_read_status(work) == binding.VOX_ERR_OUT_OF_RANGE
+    keep = np.delete(segs, [17, 9_999, 19_999], axis=0)
+    grid_fn, counts_fn = (oracle.grid_euclid, oracle.counts_euclid) if euclid else (oracle.grid, oracle.counts)
+    assert np.array_equal(grid_host(g), grid_fn(keep, dims))
+    exp_c = counts_fn(bad)
+    if euclid:
+        exp_c[[17, 9_999, 19_999]] = 0   # a grid segment outside the volume counts 0 with the Euclidean N
+    assert np.array_equal(to_host(c), exp_c)
+    binding.vox_segments_to_grid(to_dev(keep), dims, g, None, flags, work)
+    assert binding.vox_read_status(work) == binding.VOX_OK
+    assert np.array_equal(grid_host(g), grid_fn(keep, dims))
+
+
 def test_unaligned_segment_array():
     """A 4-byte (not 8-byte) aligned segment array takes the direct path."""
     torch = pytest.importorskip("torch")
