@@ -142,6 +142,15 @@ def counter_fields(path: str, sources):
 CUS = 256
 CLOCK_HZ = 2.4e9
 VALU_PEAK = CUS * CLOCK_HZ        # wave64 VALU instructions per second (one per CU per clock)
+# 32-bit VALU lane operations per second: 4 SIMDs of 16 lanes per CU, one
+# operation per lane per clock (the fp32 vector peak of 157.3 TFLOP/s counts
+# an FMA as two and packed fp32 as two more).
+ALU_PEAK_TOPS = CUS * 64 * CLOCK_HZ / 1e12
+# The fill's algorithmic ALU work per voxel: the stepping of eq. (3) with the
+# minor error terms in packed halves (packed add, packed shift, packed
+# multiply-add, dot product, dominant stride) and the LDS word and bit of the
+# voxel (shift, mask, shift): 8 lane operations; the LDS OR is not ALU work.
+FILL_OPS_PER_VOXEL = 8
 
 
 def counter_bound(kernel: str, workload: str, sources, avg_ms: float, traffic):
@@ -160,6 +169,28 @@ def counter_bound(kernel: str, workload: str, sources, avg_ms: float, traffic):
     return {"bound": "alu" if valu_ms > hbm_ms else "hbm", "valu_wave_instructions": row["INSTS_VALU"],
             "valu_ms_at_peak_issue": valu_ms, "hbm_ms_at_peak": hbm_ms,
             "valu_issue_frac": valu_ms / avg_ms if avg_ms > 0 else None}
+
+
+def _roofline_line(kernel, algo_bytes, achieved_gbs, avg_ms, traffic, bound, voxels):
+    """The dominant kernel's roofline.  Its bound comes from the committed
+    counters while they match the kernel sources ("hbm" otherwise): against
+    HBM, its algorithmic bytes per launch / launch time vs 8 TB/s; against
+    the ALU, its algorithmic lane operations per launch (FILL_OPS_PER_VOXEL a
+    voxel) / launch time vs ALU_PEAK_TOPS.  Both are given; the top-level
+    fields are those of the bound."""
+    hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_launch": algo_bytes}
+    ops = voxels * FILL_OPS_PER_VOXEL if kernel == "brick_fill" else None
+    alu = None
+    if ops is not None and avg_ms > 0:
+        a = ops / (avg_ms * 1e-3) / 1e12
+        alu = {"achieved": a, "peak": ALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": a / ALU_PEAK_TOPS,
+               "algorithmic_lane_ops_per_launch": ops, "lane_ops_per_voxel": FILL_OPS_PER_VOXEL}
+    kind = bound["bound"] if bound else "hbm"
+    top = alu if (kind == "alu" and alu is not None) else hbm
+    return {"kernel": kernel, "bound": kind if top is alu else "hbm", "achieved": top["achieved"],
+            "peak": top["peak"], "unit": top["unit"], "frac": top["frac"], "traffic": traffic,
+            "avg_launch_ms": avg_ms, "hbm": hbm, "alu": alu, "bound_from_counters": bound}
 
 
 def bench_grid(args, torch, binding, workloads, dev, stream):
@@ -673,20 +704,7 @@ def main():
         "hbm_frac_algorithmic": r["algo_bytes"] / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "algorithmic_bytes_per_step": r["algo_bytes"],
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
-        "roofline": {
-            "kernel": dom_name,
-            # From the committed counters while they match the kernel sources;
-            # "hbm" (the roofline the line is priced against) otherwise.
-            "bound": bound["bound"] if bound else "hbm",
-            "bound_from_counters": bound,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": dom_algo,
-            "avg_launch_ms": dom_avg_ms,
-        },
+        "roofline": _roofline_line(dom_name, dom_algo, achieved, dom_avg_ms, traffic, bound, r["voxels"]),
     }
     if not args.no_extra:
         line["extra"] = {
