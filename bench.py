@@ -214,7 +214,12 @@ def bench_grid(args, torch, binding, workloads, dev, stream):
                  "ms_per_candidate": {"%d,%d,%d,%d" % k: round(v, 4) for k, v in times.items()}}
     grid = torch.empty(binding.grid_words(dims), dtype=torch.int32, device=dev)
     counts = torch.empty(n, dtype=torch.int32, device=dev)
-    work = binding.workspace(binding.vox_grid_workspace_bytes(n, dims), dev)
+    # The compact workspace (16 piece records a segment, about 1 GiB here,
+    # against 4.4 GiB for the worst case of every segment crossing the whole
+    # volume); the call would fall back to the direct kernels if its records
+    # did not fit.
+    work_bytes = binding.vox_workspace_bytes(binding.VOX_OP_GRID, n, 1)
+    work = binding.workspace(work_bytes, dev)
     voxels = int((np.abs(segs_np[:, 3:].astype(np.int64) - segs_np[:, :3]).max(1) + 1).sum())
 
     def step():
@@ -230,11 +235,14 @@ def bench_grid(args, torch, binding, workloads, dev, stream):
     # launch over a second run of K steps.
     ms_call, prof = _time_then_profile(binding, stream, step, args.steps)
     ms = ms_call * args.steps
+    pieces, direct_all = binding.vox_read_batch_info(work, stream=stream)
+    assert not direct_all, "the piece records did not fit the compact workspace"
     grid_bytes = grid.numel() * 4
     algo_bytes = 24 * n + 4 * n + grid_bytes
     return {
         "n": n, "dims": dims, "voxels": voxels, "ms_total": ms, "prof": prof,
         "algo_bytes": algo_bytes, "grid_bytes": grid_bytes, "segs_np": segs_np, "tuning": tuned,
+        "workspace_bytes": work_bytes, "piece_records": pieces,
     }
 
 
@@ -698,6 +706,8 @@ def main():
             "segments": r["n"], "voxels": r["voxels"], "volume": list(r["dims"]),
             "parallelism": "single GPU",
             "tuning": r["tuning"],
+            "workspace_bytes": r["workspace_bytes"],
+            "piece_records": r["piece_records"],
         },
         "hbm_gbs_algorithmic": r["algo_bytes"] / (ms_step * 1e-3) / 1e9,
         # The whole step (all kernels) on its algorithmic bytes.

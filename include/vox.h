@@ -149,7 +149,8 @@ vox_status vox_segments_to_list_noalloc(const vox_segment *d_segs, int64_t n,
 
 /* Workspace bytes for vox_segments_to_grid with n segments and the given
  * volume (the bound covers the worst case of every segment crossing the
- * whole volume). */
+ * whole volume).  A call also accepts the smaller compact workspace of
+ * vox_workspace_bytes(VOX_OP_GRID, n, 1); see vox_segments_to_grid. */
 size_t vox_grid_workspace_bytes(int64_t n, int32_t dim_x, int32_t dim_y, int32_t dim_z);
 
 /* Packed occupancy bit-volume of all voxels of all segments (the "scene
@@ -165,8 +166,11 @@ size_t vox_grid_workspace_bytes(int64_t n, int32_t dim_x, int32_t dim_y, int32_t
  *              VOX_GRID_EUCLID: the voxels kept, 0 for a segment outside the
  *              volume).
  *   flags      VOX_GRID_CLEAR and/or VOX_GRID_EUCLID, or 0.
- *   d_work     workspace, >= vox_grid_workspace_bytes(...) bytes, 256-byte
- *              aligned.
+ *   d_work     workspace, 256-byte aligned: vox_grid_workspace_bytes(...)
+ *              bytes, or at least vox_workspace_bytes(VOX_OP_GRID, n, 1)
+ *              (compact: room for 16 piece records a segment; a call whose
+ *              records need more is served by the direct kernels instead,
+ *              with the same output, and reports no error).
  *
  * Device-checked: both end points of a segment must lie inside the volume
  * (then every voxel does, as each coordinate is rounded from a value between
@@ -233,9 +237,13 @@ typedef struct vox_scene {
 } vox_scene;
 
 /* Operation codes of vox_workspace_bytes. */
+#define VOX_OP_GRID 2
 #define VOX_OP_BATCH 3
 
 /* Workspace bytes for an operation, from the sizes known before the call:
+ *   VOX_OP_GRID   the compact workspace of vox_segments_to_grid with n
+ *                 segments in any volume (n_scenes must be 1): the
+ *                 one-scene case of VOX_OP_BATCH below.
  *   VOX_OP_BATCH  vox_batch_scenes with n_scenes scenes of at most
  *                 n_segments segments in all.  The bytes hold the scene
  *                 table, the brick histograms, brick totals and offsets for

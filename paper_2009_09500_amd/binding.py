@@ -70,6 +70,7 @@ class VoxScene(ctypes.Structure):
     ]
 
 
+VOX_OP_GRID = 2
 VOX_OP_BATCH = 3
 VOX_DEVICE_STATUS_OUT_OF_RANGE = 1
 VOX_DEVICE_STATUS_CAPACITY = 2

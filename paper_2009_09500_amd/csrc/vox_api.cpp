@@ -301,8 +301,13 @@ vox_status vox_segments_to_grid(const vox_segment* d_segs, int64_t n, int32_t di
     if (flags & ~(VOX_GRID_CLEAR | VOX_GRID_EUCLID)) return fail(VOX_ERR_INVALID_ARGUMENT, "unknown flag bits");
     if (d_work == nullptr || !aligned(d_work, vox::kAlign))
         return fail(VOX_ERR_WORKSPACE, "d_work NULL or not 256-byte aligned");
+    // The full workspace, or a compact one (vox_workspace_bytes(VOX_OP_GRID)):
+    // at least its table and histogram part, the records as far as they fit.
     const size_t need = vox::grid_workspace_bytes(n, dim_x, dim_y, dim_z);
-    if (work_bytes < need) return fail(VOX_ERR_WORKSPACE, "workspace %zu bytes, need %zu", work_bytes, need);
+    const size_t need_compact = vox::grid_compact_fixed_bytes(n, dim_x, dim_y, dim_z);
+    if (work_bytes < need && work_bytes < need_compact)
+        return fail(VOX_ERR_WORKSPACE, "workspace %zu bytes, need %zu (compact: at least %zu)", work_bytes, need,
+                    need_compact);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     vox::GridWork w = vox::grid_workspace(d_work, work_bytes, n, dim_x, dim_y, dim_z);
@@ -314,7 +319,8 @@ vox_status vox_segments_to_grid(const vox_segment* d_segs, int64_t n, int32_t di
 
 size_t vox_workspace_bytes(int op, int64_t n_segments, int32_t n_scenes) {
     if (n_segments < 0 || n_scenes < 1) return 0;
-    if (op == VOX_OP_BATCH) {
+    if (op == VOX_OP_GRID && n_scenes != 1) return 0;
+    if (op == VOX_OP_BATCH || op == VOX_OP_GRID) {
         if (n_scenes > kMaxBatchScenes || n_segments > kMaxBatchSegments) return 0;
         const int lg[3] = {8, 6, 5};
         const vox::BrickLaunch L = vox::batch_launch((uint32_t)n_scenes, (uint64_t)n_segments, lg);

@@ -66,6 +66,13 @@ size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz) {
     return kAlign;
 }
 
+size_t grid_compact_fixed_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz) {
+    BrickGeom bg;
+    Tuning t;
+    if (!use_bricks(n, dx, dy, dz, false, bg, t)) return kAlign;
+    return batch_fixed_bytes(batch_launch(1u, (uint64_t)n, bg.lg));
+}
+
 GridWork grid_workspace(void* d_work, size_t work_bytes, int64_t n, int32_t dx, int32_t dy, int32_t dz) {
     (void)n; (void)dx; (void)dy; (void)dz;
     GridWork w;
@@ -92,8 +99,12 @@ hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx
         one.flags = flags & 3u;
         one.grid = grid;
         one.counts = counts;
-        return launch_bricks(nullptr, &one, plain_launch(n, bg), t.fill_wgs_per_cu, w.status, w.bytes,
-                             stream);
+        // A workspace below the worst case of records: the call runs as a
+        // one-scene batch, whose direct kernels serve it when its records do
+        // not fit.
+        const BrickLaunch L = w.bytes >= brick_workspace_bytes(n, bg) ? plain_launch(n, bg)
+                                                                       : batch_launch(1u, (uint64_t)n, bg.lg);
+        return launch_bricks(nullptr, &one, L, t.fill_wgs_per_cu, w.status, w.bytes, stream);
     }
     hipError_t e = hipSuccess;
     const int64_t nwords = ((int64_t)dx * dy * dz + 31) / 32;

@@ -210,6 +210,9 @@ BrickLaunch plain_launch(int64_t n, const BrickGeom& bg);
 size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg);
 
 size_t grid_workspace_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz);
+// The part of a compact workspace a plain call needs before its records (the
+// brick path runs as a one-scene batch in a smaller workspace).
+size_t grid_compact_fixed_bytes(int64_t n, int32_t dx, int32_t dy, int32_t dz);
 GridWork grid_workspace(void* d_work, size_t work_bytes, int64_t n, int32_t dx, int32_t dy, int32_t dz);
 
 hipError_t launch_grid(const int32_t* segs, int64_t n, bool aligned8, int32_t dx, int32_t dy,

@@ -133,6 +133,23 @@ def test_batch_workspace_query(lib):
     assert lib.vox_workspace_bytes(99, 10, 1) == 0
 
 
+def test_grid_compact_workspace_query(lib):
+    """The compact grid workspace is the one-scene batch workspace; it is far
+    below the worst case for the arbitrary-length workload's shape, and a
+    workspace below its table and histogram part is refused before any
+    launch."""
+    g = lambda n: lib.vox_workspace_bytes(binding.VOX_OP_GRID, n, 1)
+    assert g(10**6) == lib.vox_workspace_bytes(binding.VOX_OP_BATCH, 10**6, 1)
+    assert lib.vox_workspace_bytes(binding.VOX_OP_GRID, 10**6, 2) == 0
+    n, dims = 4194304, (2048, 2048, 2048)
+    full = lib.vox_grid_workspace_bytes(n, *dims)
+    assert 0 < g(n) < full / 4
+    P = ctypes.c_void_p
+    fake = P(1 << 20)
+    st = lib.vox_segments_to_grid(fake, n, *dims, fake, None, binding.VOX_GRID_CLEAR, fake, 1 << 20, None)
+    assert st == binding.VOX_ERR_WORKSPACE
+
+
 def test_batch_host_errors(lib):
     P = ctypes.c_void_p
     fake = P(1 << 20)

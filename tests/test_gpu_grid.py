@@ -119,6 +119,36 @@ def test_out_of_volume_segments_brick_path(euclid):
     assert np.array_equal(grid_host(g), grid_fn(keep, dims))
 
 
+@pytest.mark.parametrize("euclid", [False, True])
+def test_compact_workspace(euclid):
+    """A plain brick-path call in the compact workspace (16 piece records a
+    segment) gives the oracle's volume and counts; in a compact workspace
+    with room for only 1 000 records the direct kernels serve it, with the
+    same output, cleared and ORed into a volume."""
+    torch = pytest.importorskip("torch")
+    c = workloads.arbitrary_length(n=40_000, volume=512)
+    segs, dims = c["segs"], c["dims"]
+    n = len(segs)
+    flags = binding.VOX_GRID_EUCLID if euclid else 0
+    grid_fn, counts_fn = (oracle.grid_euclid, oracle.counts_euclid) if euclid else (oracle.grid, oracle.counts)
+    compact = binding.vox_workspace_bytes(binding.VOX_OP_GRID, n, 1)
+    assert compact < binding.vox_grid_workspace_bytes(n, dims)
+    rng = np.random.default_rng(31)
+    base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+    for size, overflow in ((compact, False), (compact - 16 * (16 * n - 1000), True)):
+        work = binding.workspace(size, dev())
+        for clear in (True, False):
+            g = to_dev(base.view(np.int32))
+            c_ = torch.empty(n, dtype=torch.int32, device=dev())
+            binding.vox_segments_to_grid(to_dev(segs), dims, g, c_,
+                                         flags | (binding.VOX_GRID_CLEAR if clear else 0), work)
+            assert binding.vox_read_status(work) == binding.VOX_OK
+            pieces, direct_all = binding.vox_read_batch_info(work)
+            assert direct_all == overflow and pieces > 1000
+            assert np.array_equal(grid_host(g), grid_fn(segs, dims, base=None if clear else base))
+            assert np.array_equal(to_host(c_), counts_fn(segs))
+
+
 def test_unaligned_segment_array():
     """A 4-byte (not 8-byte) aligned segment array takes the direct path."""
     torch = pytest.importorskip("torch")
