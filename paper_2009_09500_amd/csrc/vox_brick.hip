@@ -1650,15 +1650,17 @@ BrickLaunch batch_launch(uint32_t n_scenes, uint64_t total_segments, const int l
     BrickLaunch L;
     L.n_scenes = n_scenes;
     L.total_segments = total_segments;
-    // Rows of scene s: min(256, max(1, ceil(n_s / 4096))) <= 1 + n_s / 4096.
-    uint64_t rows = (uint64_t)n_scenes + (total_segments + kSegsPerRow - 1) / kSegsPerRow;
+    // Rows of scene s: min(256, max(1, ceil(n_s / per_row))) <= 1 + n_s / per_row,
+    // with the plain calls' rows of 512 segments for a single scene.
+    const uint64_t per_row = n_scenes == 1 ? (uint64_t)kSegsPerRowPlain : (uint64_t)kSegsPerRow;
+    uint64_t rows = (uint64_t)n_scenes + (total_segments + per_row - 1) / per_row;
     const uint64_t rmax = (uint64_t)n_scenes * kHistRows;
     L.rows = (uint32_t)(rows < rmax ? rows : rmax);
     L.bricks = (uint32_t)((uint64_t)n_scenes * kMaxBricks);
     for (int a = 0; a < 3; ++a) L.lg[a] = lg[a];
     L.table_bytes = table_bytes(n_scenes, L.rows, L.bricks);
     L.direct_kernels = true;
-    L.segs_per_row = (uint32_t)kSegsPerRow;
+    L.segs_per_row = (uint32_t)per_row;
     return L;
 }
 

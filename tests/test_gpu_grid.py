@@ -119,24 +119,36 @@ def test_out_of_volume_segments_brick_path(euclid):
     assert np.array_equal(grid_host(g), grid_fn(keep, dims))
 
 
+def long_diagonals(dims, n, seed):
+    """Segments from near one corner of the volume to near the opposite one
+    (every axis flipped at random): about 24 pieces each in 512^3 with
+    256 x 64 x 32 bricks."""
+    rng = np.random.default_rng(seed)
+    hi = np.array(dims) - 1
+    p0 = rng.integers(0, 4, (n, 3))
+    p1 = hi - rng.integers(0, 4, (n, 3))
+    flip = rng.integers(0, 2, (n, 3)).astype(bool)
+    return np.concatenate([np.where(flip, hi - p0, p0), np.where(flip, hi - p1, p1)], 1).astype(np.int32)
+
+
 @pytest.mark.parametrize("euclid", [False, True])
 def test_compact_workspace(euclid):
-    """A plain brick-path call in the compact workspace (16 piece records a
-    segment) gives the oracle's volume and counts; in a compact workspace
-    with room for only 1 000 records the direct kernels serve it, with the
-    same output, cleared and ORed into a volume."""
+    """Plain brick-path calls in a compact workspace: with room for 16 piece
+    records a segment they take the bricks; with only the table and
+    histogram part (long diagonal segments: about 480 000 records, room for
+    far fewer) the direct kernels serve the call.  Both give the oracle's
+    volume and counts, cleared and ORed into a volume."""
     torch = pytest.importorskip("torch")
-    c = workloads.arbitrary_length(n=40_000, volume=512)
-    segs, dims = c["segs"], c["dims"]
-    n = len(segs)
+    dims = (512, 512, 512)
     flags = binding.VOX_GRID_EUCLID if euclid else 0
     grid_fn, counts_fn = (oracle.grid_euclid, oracle.counts_euclid) if euclid else (oracle.grid, oracle.counts)
-    compact = binding.vox_workspace_bytes(binding.VOX_OP_GRID, n, 1)
-    assert compact < binding.vox_grid_workspace_bytes(n, dims)
     rng = np.random.default_rng(31)
     base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
-    for size, overflow in ((compact, False), (compact - 16 * (16 * n - 1000), True)):
-        work = binding.workspace(size, dev())
+    cases = [(workloads.arbitrary_length(n=40_000, volume=512)["segs"], 0, False),
+             (long_diagonals(dims, 20_000, 32), 16 * 16 * 20_000, True)]
+    for segs, cut, overflow in cases:
+        n = len(segs)
+        work = binding.workspace(binding.vox_workspace_bytes(binding.VOX_OP_GRID, n, 1) - cut, dev())
         for clear in (True, False):
             g = to_dev(base.view(np.int32))
             c_ = torch.empty(n, dtype=torch.int32, device=dev())
@@ -144,7 +156,7 @@ def test_compact_workspace(euclid):
                                          flags | (binding.VOX_GRID_CLEAR if clear else 0), work)
             assert binding.vox_read_status(work) == binding.VOX_OK
             pieces, direct_all = binding.vox_read_batch_info(work)
-            assert direct_all == overflow and pieces > 1000
+            assert direct_all == overflow and pieces >= n
             assert np.array_equal(grid_host(g), grid_fn(segs, dims, base=None if clear else base))
             assert np.array_equal(to_host(c_), counts_fn(segs))
 
