@@ -83,6 +83,13 @@ def _time_then_profile(binding, stream, fn, reps):
     return ms, prof
 
 
+# The sources the brick kernels are compiled from (their translation unit):
+# committed counter summaries stay valid while these are unchanged.
+BRICK_SOURCES = ["include/vox.h"] + ["paper_2009_09500_amd/csrc/" + f for f in
+                                      ("vox_brick.hip", "vox_device.h", "vox_direct.h", "vox_exact.h",
+                                       "vox_internal.h")]
+
+
 def source_digest(files) -> str:
     h = hashlib.sha256()
     for f in sorted(files):
@@ -675,8 +682,7 @@ def main():
     dom = max(prof.items(), key=lambda kv: kv[1][0]) if prof else ("", (0.0, 1))
     dom_name, (dom_ms, dom_launches) = dom
     dom_avg_ms = dom_ms / max(dom_launches, 1)
-    sources = ["paper_2009_09500_amd/csrc/" + f for f in
-               sorted(os.listdir(os.path.join(ROOT, "paper_2009_09500_amd", "csrc")))]
+    sources = BRICK_SOURCES
     # Algorithmic bytes the dominant kernel must move per launch.
     # brick_fill writes the volume once (the clear is fused); grid_direct
     # reads the segments, writes the counts and sets the volume's words.
