@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define VOX_ABI_VERSION 5
+#define VOX_ABI_VERSION 6
 
 /* One segment: start point (x0,y0,z0) = S, end point (x1,y1,z1) = E.
  * Arrays of segments are dense, 24 bytes per segment, 4-byte aligned. */
