@@ -172,6 +172,50 @@ def test_grid_long_pieces(lg, dims):
         assert_grid(segs, dims)
 
 
+def edge_segments(dims, n, seed):
+    """Points, axis-aligned segments, segments along brick faces and edges
+    (coordinates on multiples of 32 and one below), and short diagonals
+    crossing brick corners, in both directions."""
+    rng = np.random.default_rng(seed)
+    hi = np.array(dims) - 1
+    edges = np.array(sorted({min(int(v), int(h)) for h in hi for v in (0, 31, 32, 63, 64, 127, 128, 255, 256, h)}))
+    out = []
+    for _ in range(n):
+        kind = rng.integers(0, 4)
+        p0 = np.array([rng.integers(0, d) for d in dims])
+        if kind == 0:                                  # a point
+            p1 = p0.copy()
+        elif kind == 1:                                # axis-aligned
+            p1 = p0.copy()
+            ax = rng.integers(0, 3)
+            p1[ax] = rng.integers(0, dims[ax])
+        elif kind == 2:                                # on brick faces / edges
+            p0 = np.array([rng.choice(edges[edges <= h]) for h in hi])
+            p1 = np.array([rng.choice(edges[edges <= h]) for h in hi])
+            keep = rng.integers(0, 2, 3).astype(bool)
+            p1[keep] = p0[keep]
+        else:                                          # short diagonal through a brick corner
+            c = np.array([rng.choice(edges[(edges > 0) & (edges <= h)]) for h in hi])
+            r = rng.integers(1, 6, 3)
+            p0, p1 = np.clip(c - r, 0, hi), np.clip(c + r, 0, hi)
+        out.append(np.concatenate([p0, p1]) if rng.integers(0, 2) else np.concatenate([p1, p0]))
+    return np.array(out, dtype=np.int32)
+
+
+@pytest.mark.parametrize("lg", SHAPES)
+def test_grid_edge_segments_brick_path(lg):
+    """Points, axis-aligned segments and segments on brick faces, edges and
+    corners on the brick path, with both lengths, into a 320 x 140 x 70
+    volume (partial bricks on every axis)."""
+    dims = (320, 140, 70)
+    segs = edge_segments(dims, 20_000, 90 + lg[2])
+    with tuned(lg, [(dims, 20_000)]):
+        assert_grid(segs, dims)
+        g, c = binding.segments_to_grid(to_dev(segs), dims, want_counts=True)
+        assert np.array_equal(grid_host(g), oracle.grid(segs, dims))
+        assert np.array_equal(to_host(c), oracle.counts(segs))
+
+
 @pytest.mark.parametrize("n", [16384, 16385])
 def test_grid_direct_brick_boundary(n):
     """Plain calls of at most 16384 segments take the direct path, larger
