@@ -46,7 +46,7 @@ constexpr int kCountBlock = 256;
 constexpr int kCountPerThread = 4;
 constexpr int64_t kSegsPerCountBlock = (int64_t)kCountBlock * kCountPerThread;
 constexpr int kListBlock = 256;
-constexpr int kListPerThread = 4;
+constexpr int kListPerThread = 8;
 constexpr int64_t kListTile = (int64_t)kListBlock * kListPerThread;
 
 struct ListWork {

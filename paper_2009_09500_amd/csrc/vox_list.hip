@@ -11,6 +11,8 @@
 //   4. voxels  every lane computes kListPerThread consecutive voxels of the
 //              flat output with the exact stepping of eq. (3), stages them
 //              in LDS and the block writes the tile with 16-byte stores.
+#include <type_traits>
+
 #include "vox_device.h"
 #include "vox_internal.h"
 
@@ -258,15 +260,20 @@ __global__ __launch_bounds__(kCountBlock) void k_list_tiles(const int64_t* __res
 // ------------------------------------------------------------ voxel tiles
 
 // One tile = kListTile consecutive output voxels [j0, j1).  Its segments
-// s0..s1 are staged in LDS as packed int16 end points with their offsets
-// relative to j0; lane t computes voxels j0 + t*P .. j0 + t*P + P - 1
-// (P = kListPerThread), stepping exactly from one voxel to the next and
-// moving to the following segment when the voxel index reaches its offset.
+// s0..s1 are staged in LDS, at most kWinSegs at a time, as packed end points
+// with their offsets relative to j0; lane t computes voxels j0 + t*P ..
+// j0 + t*P + P - 1 (P = kListPerThread), stepping exactly from one voxel to
+// the next and moving to the following segment when the voxel index reaches
+// its offset.  A tile with more segments than a window holds (segments
+// shorter than kListTile / kWinSegs voxels on average) is done in several
+// windows, each lane computing the voxels of its P that fall in the window;
+// LDS sized for the usual case keeps many blocks on a CU.
 template <typename T>
 struct PackedSeg {
     T p0[3];
     T p1[3];
 };
+constexpr int kWinSegs = 256;
 
 // T = int16_t: coordinates in int16 (differences below 2^16); T = int32_t:
 // every axis difference below 2^30 (checked by the count kernel).
@@ -276,19 +283,18 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     const int32_t* __restrict__ tile_seg, T* __restrict__ voxels,
     const int64_t* __restrict__ total_p, const int32_t* __restrict__ status) {
     using PSeg = PackedSeg<T>;
-    constexpr int kMaxSegs = (int)kListTile + 1;
-    constexpr int kSegWords = (int)(kMaxSegs * sizeof(PSeg) / 4);
+    constexpr int kSegWords = (int)(kWinSegs * sizeof(PSeg) / 4);
     constexpr int kVoxBytes = 3 * (int)sizeof(T);
     constexpr int kLaneWords = kListPerThread * kVoxBytes / 4;  // a lane's staged voxels
     constexpr int kStageWords = (int)kListTile * kVoxBytes / 4;
     // The staged segments and the output stage share LDS (the segments are
-    // dead once every lane has its voxels): 16 KiB a block for int16 lists
-    // (8 blocks a CU), 28 KiB for int32 lists.
+    // dead once every lane has its voxels): 13 KiB a block for int16 lists,
+    // 25 KiB for int32 lists.
     __shared__ __align__(16) uint32_t lds_raw[kSegWords > kStageWords ? kSegWords : kStageWords];
-    __shared__ int32_t srel[kMaxSegs + 1];
+    __shared__ int32_t srel[kWinSegs + 1];
     PSeg* sseg = reinterpret_cast<PSeg*>(lds_raw);
     uint32_t* stage = lds_raw;
-    static_assert((kMaxSegs * sizeof(PSeg)) % 4 == 0 && (kListPerThread * kVoxBytes) % 4 == 0, "packing");
+    static_assert((kWinSegs * sizeof(PSeg)) % 4 == 0 && (kListPerThread * kVoxBytes) % 4 == 0, "packing");
 
     if (*status != 0) return;
     const int64_t total = *total_p;
@@ -301,36 +307,50 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     int32_t s1 = tile + 1 < ntiles ? tile_seg[tile + 1] : (int32_t)(n - 1);
     const int nseg = s1 - s0 + 1;  // <= kListTile + 1
 
-    for (int s = threadIdx.x; s < nseg; s += kListBlock) {
-        Seg g = load_seg<kAligned8>(segs, (int64_t)s0 + s);
-        PSeg p;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            p.p0[a] = (T)g.p0[a];
-            p.p1[a] = (T)g.p1[a];
-        }
-        sseg[s] = p;
-    }
-    for (int s = threadIdx.x; s <= nseg; s += kListBlock) {
-        int64_t o = (int64_t)s0 + s <= n ? offsets[(int64_t)s0 + s] : total;
-        int64_t rel = o - j0;
-        // A tile's own segments start within [-(2^30 - 1), kListTile].
-        rel = rel < -(1ll << 30) ? -(1ll << 30) : (rel > (1ll << 30) ? (1ll << 30) : rel);
-        srel[s] = (int32_t)rel;
-    }
-    __syncthreads();
-
     const int first = threadIdx.x * kListPerThread;  // tile-relative voxel
     const int count = (int)(j1 - j0);
     T out[kListPerThread * 3];
-    if (first < count) {
-        // Segment of the first voxel: largest s with srel[s] <= first.
-        int lo = 0, hi = nseg - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (srel[mid] <= first) lo = mid; else hi = mid - 1;
+    // Window w: the tile's segments [w, w + m); srel[i] is the offset of
+    // segment w + i relative to j0 (srel[m]: of the segment after the window,
+    // or the total), so the window's voxels are [srel[0], srel[m]).  Almost
+    // every tile is one window (kOne: every voxel of the lane's P lies in it).
+    auto run_window = [&](int w, int m, auto one) {
+        constexpr bool kOne = decltype(one)::value;
+        for (int i = threadIdx.x; i < m; i += kListBlock) {
+            Seg g = load_seg<kAligned8>(segs, (int64_t)s0 + w + i);
+            PSeg p;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                p.p0[a] = (T)g.p0[a];
+                p.p1[a] = (T)g.p1[a];
+            }
+            sseg[i] = p;
         }
-        int s = lo;
+        for (int i = threadIdx.x; i <= m; i += kListBlock) {
+            const int64_t si = (int64_t)s0 + w + i;
+            int64_t o = si <= n ? offsets[si] : total;
+            int64_t rel = o - j0;
+            // A tile's own segments start within [-(2^30 - 1), kListTile].
+            rel = rel < -(1ll << 30) ? -(1ll << 30) : (rel > (1ll << 30) ? (1ll << 30) : rel);
+            srel[i] = (int32_t)rel;
+        }
+        __syncthreads();
+
+        // This lane's voxels inside the window: [lo, hi).
+        int lo = first, hi = first + kListPerThread < count ? first + kListPerThread : count;
+        if constexpr (!kOne) {
+            const int wlo = srel[0], whi = srel[m];
+            lo = first > wlo ? first : wlo;
+            hi = hi < whi ? hi : whi;
+        }
+        if (lo >= hi) return;
+        // Segment of voxel lo: largest s with srel[s] <= lo.
+        int a_ = 0, b_ = m - 1;
+        while (a_ < b_) {
+            int mid = (a_ + b_ + 1) >> 1;
+            if (srel[mid] <= lo) a_ = mid; else b_ = mid - 1;
+        }
+        int s = a_;
         int next = srel[s + 1];
         PSeg p = sseg[s];
         uint32_t neg[3], a[3];
@@ -344,7 +364,7 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
             a[ax] = (int32_t)d < 0 ? 0u - d : d;
             N = a[ax] > N ? a[ax] : N;
         }
-        uint32_t k = (uint32_t)(first - srel[s]);
+        uint32_t k = (uint32_t)(lo - srel[s]);
         AxisStep st[3];
         if (N == 0) {
 #pragma unroll
@@ -356,10 +376,12 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
 #pragma unroll
         for (int v = 0; v < kListPerThread; ++v) {
             const int j = first + v;
-            // (Never at v = 0: the search found the segment holding voxel
-            // `first`, and every segment has at least one voxel.)
-            if (v > 0 && j >= next && j < count) {
-                // First voxel of the following segment: k = 0.
+            if (j >= hi || (!kOne && j < lo)) continue;
+            // (Never at j = lo: the search found the segment holding voxel
+            // lo, and every segment has at least one voxel.)
+            if (j > lo && j >= next) {
+                // First voxel of the following segment (inside the window, as
+                // j < hi <= srel[m]): k = 0.
                 ++s;
                 next = srel[s + 1];
                 p = sseg[s];
@@ -385,6 +407,14 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
                 out[v * 3 + ax] = (T)((int32_t)p.p0[ax] + (neg[ax] ? -q : q));
                 axis_step(st[ax], two_n);
             }
+        }
+    };
+    if (nseg <= kWinSegs) {
+        run_window(0, nseg, std::integral_constant<bool, true>{});
+    } else {
+        for (int w = 0; w < nseg; w += kWinSegs) {
+            if (w > 0) __syncthreads();  // the previous window is read
+            run_window(w, nseg - w < kWinSegs ? nseg - w : kWinSegs, std::integral_constant<bool, false>{});
         }
     }
     __syncthreads();  // the staged segments are dead from here

@@ -71,6 +71,29 @@ def test_point_segments_only():
     assert_parity(np.concatenate([p, p], 1).astype(np.int32))
 
 
+def test_dense_tiles_mixed_lengths():
+    """Tiles holding more segments than one LDS window (256): runs of 1- to
+    3-voxel segments, so that window boundaries fall inside a lane's eight
+    voxels, between runs of long segments, so that tiles go from dense to
+    sparse and back."""
+    rng = np.random.default_rng(17)
+    parts = []
+    for r in range(12):
+        if r % 3 == 2:
+            parts.append(pins.random_segments(40, 100 + r, -3000, 3000))
+        else:
+            n = int(rng.integers(2000, 6000))
+            p0 = rng.integers(-500, 500, size=(n, 3))
+            p1 = p0 + rng.integers(-2, 3, size=(n, 3))
+            parts.append(np.concatenate([p0, p1], 1).astype(np.int32))
+    segs = np.concatenate(parts)
+    assert_parity(segs)
+    torch = pytest.importorskip("torch")
+    offs, vox = binding.segments_to_list(to_dev(segs), wide=True)
+    exp = oracle.voxel_list(segs)
+    assert np.array_equal(to_host(vox), exp.astype(np.int32))
+
+
 def test_empty():
     torch = pytest.importorskip("torch")
     segs = torch.zeros((0, 6), dtype=torch.int32, device=dev())
