@@ -177,10 +177,12 @@ size_t vox_grid_workspace_bytes(int64_t n, int32_t dim_x, int32_t dim_y, int32_t
  * two in-range integers).  A segment that fails sets VOX_ERR_OUT_OF_RANGE
  * and contributes no voxel; the others are still written.
  *
- * Calls with more than 16384 segments, 8-byte-aligned d_segs, the
- * Chebyshev N, dim_x a multiple of 32 and every side at most 16384 (and a
- * brick count within the library's limit) fill LDS bricks; the others take
- * the direct path (one device atomic per voxel).  The output is the same. */
+ * Calls with more than 16384 segments, 8-byte-aligned d_segs, dim_x a
+ * multiple of 32 and every side at most 16384 (and a brick count within the
+ * library's limit; with VOX_GRID_EUCLID also a volume diagonal
+ * sqrt((dim_x-1)^2 + (dim_y-1)^2 + (dim_z-1)^2) below 16385) fill LDS
+ * bricks; the others take the direct path (one device atomic per voxel).
+ * The output is the same. */
 vox_status vox_segments_to_grid(const vox_segment *d_segs, int64_t n,
                                 int32_t dim_x, int32_t dim_y, int32_t dim_z,
                                 uint32_t *d_grid, int32_t *d_counts, uint32_t flags,
@@ -277,11 +279,12 @@ size_t vox_workspace_bytes(int op, int64_t n_segments, int32_t n_scenes);
  * vox_segments_to_grid rules: a scene that breaks one, or scenes whose
  * segments exceed total_segments, stop the call with nothing written and
  * the status VOX_ERR_INVALID_ARGUMENT / VOX_ERR_BATCH_MISMATCH.  Scenes whose
- * segment array is 8-byte aligned, with the Chebyshev N, dim_x a multiple
- * of 32, every side at most 16384 and at most 16384 bricks take the LDS
- * brick kernels; the others (and every scene, when the piece records of the
- * call do not fit the workspace) take direct kernels with one device atomic
- * per voxel.  The output never depends on which.
+ * segment array is 8-byte aligned, dim_x a multiple of 32, every side at
+ * most 16384 and at most 16384 bricks (with VOX_GRID_EUCLID, a volume
+ * diagonal below 16385) take the LDS brick kernels; the others (and every
+ * scene, when the piece records of the call do not fit the workspace) take
+ * direct kernels with one device atomic per voxel.  The output never depends
+ * on which.
  *
  * Reads no device memory on the host, synchronises nothing and allocates
  * nothing, so it can be captured into a HIP graph once and replayed after

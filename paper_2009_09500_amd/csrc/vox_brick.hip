@@ -247,19 +247,18 @@ __device__ __forceinline__ void write_table(uint8_t* work, const BrickLaunch& L,
     *wv.pieces = 0;
 }
 
-// The plan: one block reads the caller's scenes (the device vox_scene array,
-// or the one scene of a plain call passed by value), checks each against the
-// argument rules, decides which scenes the brick kernels serve (8-byte-aligned
-// segment arrays, the Chebyshev N, volumes the bricks cover) and which the
+// The plan of a batch: one block reads the caller's scenes (the device
+// vox_scene array), checks each against the argument rules, decides which
+// scenes the brick kernels serve (8-byte-aligned segment arrays, volumes the
+// bricks cover; with the Euclidean N, a diagonal below 16385) and which the
 // direct kernels serve, numbers the histogram rows and bricks of all brick
 // scenes (block scans), and writes the table, the status word, the brick
 // queues and the flags.  A scene that breaks a rule, or scenes beyond the
 // launch bounds, stop the whole call (nothing is written).  When the
 // histograms and brick offsets do not fit the workspace, the direct kernels
 // serve every scene.
-__global__ __launch_bounds__(kPlanBlock) void k_brick_plan(const vox_scene* __restrict__ scenes, vox_scene one,
-                                                           uint32_t has_one, BrickLaunch L, uint8_t* __restrict__ work,
-                                                           uint64_t work_bytes) {
+__global__ __launch_bounds__(kPlanBlock) void k_brick_plan(const vox_scene* __restrict__ scenes, BrickLaunch L,
+                                                           uint8_t* __restrict__ work, uint64_t work_bytes) {
     __shared__ uint32_t scan32[kPlanBlock / kWave];
     __shared__ uint64_t scan64[kPlanBlock / kWave];
     __shared__ uint32_t bad_s, max_nb_s;
@@ -279,7 +278,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_brick_plan(const vox_scene* __re
         uint32_t rows = 0, nb = 0, isd = 0;
         uint64_t hist = 0, n = 0;
         if (i < L.n_scenes) {
-            const vox_scene in = has_one ? one : scenes[i];
+            const vox_scene in = scenes[i];
             if (!plan_scene(in, L.lg, L.segs_per_row, b)) atomicOr(&bad_s, 1u);
             isd = (b.flags & kSceneDirect) ? 1u : 0u;
             rows = b.rows;
@@ -313,26 +312,6 @@ __global__ __launch_bounds__(kPlanBlock) void k_brick_plan(const vox_scene* __re
     __syncthreads();
     if (threadIdx.x != 0) return;
     write_table(work, L, work_bytes, rows_c, bricks_c, direct_c, max_nb_s, hist_c, segs_c, dsegs_c, bad_s != 0);
-}
-
-// The plan of a plain call (its one scene passed by value): the table
-// k_brick_plan writes for a single scene, by one lane, with no block scans.
-__global__ __launch_bounds__(kWave) void k_brick_plan_one(vox_scene one, BrickLaunch L, uint8_t* __restrict__ work,
-                                                         uint64_t work_bytes) {
-    if (threadIdx.x != 0) return;
-    BrickScene b;
-    const bool valid = plan_scene(one, L.lg, L.segs_per_row, b);
-    const bool isd = (b.flags & kSceneDirect) != 0;
-    b.row_base = 0;
-    b.brick_base = 0;
-    b.hist_off = 0;
-    uint8_t* tb = work + kWorkTable;
-    BrickScene* out = reinterpret_cast<BrickScene*>(tb + kTableScenes);
-    out[0] = b;
-    if (isd) reinterpret_cast<uint32_t*>(out + 1)[0] = 0u;
-    const uint32_t nb = isd ? 0u : b.bg.nbricks;
-    const uint64_t n = b.n > 0 ? (uint64_t)b.n : 0u;
-    write_table(work, L, work_bytes, b.rows, nb, isd ? 1u : 0u, nb, (uint64_t)b.rows * nb, n, isd ? n : 0u, !valid);
 }
 
 // Scene of every histogram row and of every brick (tables of several
@@ -526,8 +505,8 @@ __device__ __forceinline__ uint32_t euclid_moves(const StagedSeg& g, uint32_t N,
     return moves;
 }
 
-// Per-wave LDS of the Euclidean counts: the wave's 64 segments' first chunk
-// numbers, lengths N and move counts.
+// Per-wave LDS of the Euclidean counts, one entry per lane: its segment's
+// first chunk number, length N and move count.
 struct CountScratch {
     uint32_t pre[kWave], n[kWave], cnt[kWave];
 };
@@ -693,9 +672,9 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_hist(uint8_t* __restrict__
 
 // A plain call's plan and histogram in one launch: every workgroup plans the
 // call's one scene (passed by value) itself, the first one also writes the
-// table and header words for the kernels that follow (k_brick_plan_one's
-// output), and the workgroups go on to their histogram rows when the brick
-// kernels may run.
+// table and header words for the kernels that follow (what k_brick_plan
+// writes for a single scene), and the workgroups go on to their histogram
+// rows when the brick kernels may run.
 __global__ __launch_bounds__(kHistBlock) void k_brick_plan_hist(vox_scene one, BrickLaunch L,
                                                                uint8_t* __restrict__ work, uint64_t work_bytes) {
     extern __shared__ __align__(16) uint8_t hist_lds[];
@@ -1740,11 +1719,12 @@ hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunc
         }();
         if (attr != hipSuccess) return attr;
     }
-    // A plain call (one scene by value, at most kMaxBricks bricks): the plan
-    // runs inside the histogram launch, five launches in all; a batch takes
-    // seven or more.
-    const bool plain = one != nullptr && L.n_scenes == 1 && L.bricks <= kMaxBricks;
-    if (plain) {
+    // A plain call (its one scene by value; the brick geometry keeps it to at
+    // most kMaxBricks bricks): the plan runs inside the histogram launch,
+    // five launches in all; a batch (a device scene array) takes seven or
+    // more.
+    if (one) {
+        if (L.n_scenes != 1 || L.bricks > kMaxBricks) return hipErrorInvalidValue;
         KernelTimer t("brick_plan_hist", stream);
         k_brick_plan_hist<<<L.rows, kHistBlock, kHistLds, stream>>>(*static_cast<const vox_scene*>(one), L, work,
                                                                     (uint64_t)work_bytes);
@@ -1752,13 +1732,8 @@ hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunc
     } else {
         {
             KernelTimer t("brick_plan", stream);
-            vox_scene os{};
-            if (one) os = *static_cast<const vox_scene*>(one);
-            if (one && L.n_scenes == 1)
-                k_brick_plan_one<<<1, kWave, 0, stream>>>(os, L, work, (uint64_t)work_bytes);
-            else
-                k_brick_plan<<<1, kPlanBlock, 0, stream>>>(static_cast<const vox_scene*>(d_scenes), os,
-                                                           one ? 1u : 0u, L, work, (uint64_t)work_bytes);
+            k_brick_plan<<<1, kPlanBlock, 0, stream>>>(static_cast<const vox_scene*>(d_scenes), L, work,
+                                                       (uint64_t)work_bytes);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (L.n_scenes > 1) {

@@ -199,9 +199,10 @@ size_t batch_fixed_bytes(const BrickLaunch& L);
 constexpr uint64_t kRecordBytes = 16;
 constexpr uint64_t kDefaultPiecesPerSegment = 16;
 
-// Launches the plan kernel and the brick pipeline over the scenes
-// d_scenes[n_scenes] (device vox_scene array), or over the single scene
-// *one (a host vox_scene) when d_scenes is null.
+// Launches the brick pipeline over the scenes d_scenes[n_scenes] (device
+// vox_scene array, planned by the plan kernel), or over the single scene
+// *one (a host vox_scene, planned inside the histogram launch) when
+// d_scenes is null.
 hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunch& L, int fill_wgs_per_cu,
                          void* d_work, size_t work_bytes, hipStream_t stream);
 // Launch bounds of a plain call that takes the brick path, and its
