@@ -349,27 +349,27 @@ constexpr int kStageBig = 8192;   // ... by the histogram when its counters leav
 constexpr uint32_t kBigStageBricks = 8192;  // bricks per scene up to which they do
 constexpr int kOrderBins = 64;
 
-// Staged segments ordered by their number of bricks, longest walks first, so
-// the lanes of a wave walk segments of (nearly) equal piece counts: they all
-// start together and finish together.  The count used is
-// 1 + sum_a |brick_a(P1) - brick_a(P0)| (exact unless two axes cross at the
-// same k), clamped to the last bucket.
+// Staged segments ordered by their estimated number of pieces (walk_estimate),
+// longest walks first, so the lanes of a wave walk segments of (nearly)
+// equal piece counts: they all start together and finish together.  Bucket
+// kOrderBins - est, the longest (est >= kOrderBins) in bucket 0.  The buckets
+// fall into the classes of walk_parts: 8 parts (bucket 0), 4 (buckets 1-32),
+// 2 (33-48) and 1 (49-63), so each class is a contiguous run of the order.
 template <int kN>
 struct Stage {
     StagedSeg seg[kN];
     uint16_t order[kN];
-    uint32_t bins[kOrderBins];  // bucket sizes, then bucket cursors
+    uint32_t bins[kOrderBins];  // bucket sizes, then bucket starts, then bucket ends
     uint32_t nvalid;
+    uint32_t claim;             // next group of the walk (walk_ordered)
 };
+static_assert(kOrderBins == 64 && kMaxWalkParts == 8, "walk classes: buckets 0, 1-32, 33-48, 49-63");
+constexpr int kBinEnd8 = 0, kBinEnd4 = 32, kBinEnd2 = 48;  // last bucket of each class
 
 __device__ __forceinline__ uint32_t order_bin(const StagedSeg& g, const BrickGeom& bg) {
-    uint32_t est = 1;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int32_t db = ((int32_t)g.p1[ax] >> bg.lg[ax]) - ((int32_t)g.p0[ax] >> bg.lg[ax]);
-        est += (uint32_t)(db < 0 ? -db : db);
-    }
-    return kOrderBins - 1 - (est < kOrderBins - 1 ? est : kOrderBins - 1);
+    const int32_t p0[3] = {g.p0[0], g.p0[1], g.p0[2]}, p1[3] = {g.p1[0], g.p1[1], g.p1[2]};
+    const uint32_t est = walk_estimate(p0, p1, bg.lg);
+    return (uint32_t)kOrderBins - (est < (uint32_t)kOrderBins ? est : (uint32_t)kOrderBins);
 }
 
 // Loads segments [base, base + cnt) into the stage (all threads of the
@@ -417,7 +417,10 @@ __device__ __forceinline__ void stage_segments(const int32_t* __restrict__ segs,
         const uint32_t c = st.bins[threadIdx.x];
         const uint32_t incl = wave_inclusive_sum(c);
         st.bins[threadIdx.x] = incl - c;
-        if (threadIdx.x == kWave - 1) st.nvalid = incl;
+        if (threadIdx.x == kWave - 1) {
+            st.nvalid = incl;
+            st.claim = 0;
+        }
     }
     lds_barrier();
     slot = 0;
@@ -435,16 +438,20 @@ static_assert(kStage / kHistBlock <= 32 && kStageBig / kHistBlock <= 32 && kStag
 struct WalkState {
     AxisCross c[3];
     uint32_t N, klo;  // length (Chebyshev or Euclidean), first k inside the current brick
+    uint32_t kend;    // last k of the walk's part
 };
 
 // floor(sqrt(s)) for s < 2^31: the double square root is correctly rounded,
 // so its integer part is exact in this range.
 __device__ __forceinline__ uint32_t isqrt31(uint32_t s) { return (uint32_t)__dsqrt_rn((double)s); }
 
-// Walk state at k = 0.  Every coordinate of eq. (3) is monotone in k for any
-// N >= max |d_a|, so the brick crossings follow the same rules under the
-// Euclidean N of eq. (1) (N = floor |P1 - P0| >= max |d_a|).
-__device__ __forceinline__ void walk_init(WalkState& w, const StagedSeg& g, const BrickGeom& bg, bool euclid) {
+// Walk state at the start of part `part` of `parts` of a walk (the whole
+// walk when parts = 1; false for an empty part).  Every coordinate of
+// eq. (3) is monotone in k for any N >= max |d_a|, so the brick crossings
+// follow the same rules under the Euclidean N of eq. (1)
+// (N = floor |P1 - P0| >= max |d_a|).
+__device__ __forceinline__ bool walk_init(WalkState& w, const StagedSeg& g, const BrickGeom& bg, bool euclid,
+                                          uint32_t part, uint32_t parts) {
     int32_t p0[3], p1[3];
     uint32_t a[3], neg[3], N = 0, ss = 0;
 #pragma unroll
@@ -458,10 +465,14 @@ __device__ __forceinline__ void walk_init(WalkState& w, const StagedSeg& g, cons
         ss += a[ax] * a[ax];
     }
     if (euclid) N = isqrt31(ss);
+    uint32_t k0 = 0, k1 = N;
+    if (parts > 1u && !part_window(p0, p1, a, neg, N, bg.lg, part, parts, k0, k1)) return false;
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) cross_init(w.c[ax], p0[ax], p1[ax], a[ax], neg[ax], N, bg.lg[ax]);
+    for (int ax = 0; ax < 3; ++ax) cross_init_at(w.c[ax], p0[ax], p1[ax], a[ax], neg[ax], N, bg.lg[ax], k0);
     w.N = N;
-    w.klo = 0;
+    w.klo = k0;
+    w.kend = k1;
+    return true;
 }
 
 // Steps k0 + 1 ... k0 + len (k0 + len <= N) of an in-volume segment under
@@ -576,34 +587,62 @@ __device__ __forceinline__ void euclid_counts(const Stage<kN>& st, int32_t* __re
     }
 }
 
-// Walks the ordered staged segments: each wave takes the next 64 in order
-// and steps all of them one brick at a time until the wave's last segment
-// ends.  emit(brick id, klo, khi, staged index, brick x, y, z, N) per piece,
-// [klo, khi] being the segment's k-window inside the brick.
+// Walks the ordered staged segments.  The order falls into four classes of
+// walk_parts (8, 4, 2 and 1 parts, longest walks first), and the walk into
+// groups of 64 part walks: 8 segments of the first class cut into 8 parts
+// each, 16 of the second cut into 4, and so on.  Waves claim groups in order
+// from an LDS counter, so the longest groups start first and a wave that
+// finishes early takes the next group (no wave waits for a fixed share).
+// Lanes of a group step their parts one brick at a time until the last ends.
+// emit(brick id, klo, khi, staged segment, brick x, y, z, N) per piece,
+// [klo, khi] being the segment's k-window inside the brick.  The segment is
+// read from LDS once per walk, so what the emitter derives from it alone is
+// computed once per walk, not per piece.
 template <int kN, typename Emit>
-__device__ __forceinline__ void walk_ordered(const Stage<kN>& st, const BrickGeom& bg, bool euclid, Emit emit) {
+__device__ __forceinline__ void walk_ordered(Stage<kN>& st, const BrickGeom& bg, bool euclid, Emit emit) {
     const uint32_t lane = __lane_id();
     const uint32_t nvalid = st.nvalid;
-    for (uint32_t base = threadIdx.x - lane; base < nvalid; base += kHistBlock) {
-        const uint32_t i = base + lane;
-        bool active = i < nvalid;
-        uint32_t j = 0;
+    // Ends of the classes in the order, and their first groups.
+    const uint32_t e8 = st.bins[kBinEnd8], e4 = st.bins[kBinEnd4], e2 = st.bins[kBinEnd2];
+    const uint32_t g4 = (e8 + 7u) >> 3;
+    const uint32_t g2 = g4 + ((e4 - e8 + 15u) >> 4);
+    const uint32_t g1 = g2 + ((e2 - e4 + 31u) >> 5);
+    const uint32_t gt = g1 + ((nvalid - e2 + 63u) >> 6);
+    for (;;) {
+        uint32_t grp = 0;
+        if (lane == 0) grp = atomicAdd(&st.claim, 1u);
+        grp = __builtin_amdgcn_readfirstlane(grp);
+        if (grp >= gt) break;
+        uint32_t lgp, start, end;
+        if (grp < g4) {
+            lgp = 3; start = grp << 3; end = e8;
+        } else if (grp < g2) {
+            lgp = 2; start = e8 + ((grp - g4) << 4); end = e4;
+        } else if (grp < g1) {
+            lgp = 1; start = e4 + ((grp - g2) << 5); end = e2;
+        } else {
+            lgp = 0; start = e2 + ((grp - g1) << 6); end = nvalid;
+        }
+        const uint32_t i = start + (lane >> lgp);
+        bool active = i < end;
+        StagedSeg g = {};
         WalkState w = {};
         if (active) {
-            j = st.order[i];
-            walk_init(w, st.seg[j], bg, euclid);
+            g = st.seg[st.order[i]];
+            active = walk_init(w, g, bg, euclid, lane & ((1u << lgp) - 1u), 1u << lgp);
         }
         while (__ballot(active)) {
             uint32_t km = w.c[0].kn < w.c[1].kn ? w.c[0].kn : w.c[1].kn;
             km = km < w.c[2].kn ? km : w.c[2].kn;
+            const bool more = km <= w.kend;
             // Brick ids and counts stay below 2^24: 24-bit multiplies.
             if (active)
                 emit(__umul24(__umul24((uint32_t)w.c[2].b, (uint32_t)bg.nb[1]) + (uint32_t)w.c[1].b,
                               (uint32_t)bg.nb[0]) +
                          (uint32_t)w.c[0].b,
-                     w.klo, km == kNever ? w.N : km - 1u, j, w.c[0].b, w.c[1].b, w.c[2].b, w.N);
+                     w.klo, more ? km - 1u : w.kend, g, w.c[0].b, w.c[1].b, w.c[2].b, w.N);
             // The rest with selects only (lanes step different segments).
-            const bool go = active && km != kNever;
+            const bool go = active && more;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) cross_advance(w.c[ax], go && w.c[ax].kn == km);
             w.klo = go ? km : w.klo;
@@ -627,7 +666,7 @@ __device__ __forceinline__ void hist_row(const BrickScene& sc, uint32_t g, Stage
         const uint32_t cnt = (uint32_t)(hi - base < kN ? hi - base : kN);
         stage_segments(sc.segs, base, cnt, bg, euclid, st, sc.counts, bad);
         walk_ordered(st, bg, euclid,
-                     [&](uint32_t b, uint32_t, uint32_t, uint32_t, int32_t, int32_t, int32_t, uint32_t) {
+                     [&](uint32_t b, uint32_t, uint32_t, const StagedSeg&, int32_t, int32_t, int32_t, uint32_t) {
                          atomicAdd(&lh[b], 1u);
                      });
         if (euclid && sc.counts) euclid_counts(st, sc.counts + base, cscratch);
@@ -914,16 +953,16 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restric
         const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
         stage_segments(sc.segs, base, cnt, bg, euclid, st, nullptr, bad);
         if (euclid) {
-            walk_ordered(st, bg, true, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j, int32_t bx,
+            walk_ordered(st, bg, true, [&](uint32_t b, uint32_t klo, uint32_t khi, const StagedSeg& g, int32_t bx,
                                            int32_t by, int32_t bz, uint32_t N) {
                 const uint32_t pos = atomicAdd(&cur[b], 1u);
-                recs[pos] = piece_record_euclid(st.seg[j], N, klo, khi, bx, by, bz, bg);
+                recs[pos] = piece_record_euclid(g, N, klo, khi, bx, by, bz, bg);
             });
         } else {
-            walk_ordered(st, bg, false, [&](uint32_t b, uint32_t klo, uint32_t khi, uint32_t j, int32_t bx,
+            walk_ordered(st, bg, false, [&](uint32_t b, uint32_t klo, uint32_t khi, const StagedSeg& g, int32_t bx,
                                             int32_t by, int32_t bz, uint32_t) {
                 const uint32_t pos = atomicAdd(&cur[b], 1u);
-                recs[pos] = piece_record(st.seg[j], klo, khi, bx, by, bz, bg);
+                recs[pos] = piece_record(g, klo, khi, bx, by, bz, bg);
             });
         }
         lds_barrier();

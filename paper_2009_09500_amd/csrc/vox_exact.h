@@ -70,9 +70,21 @@ struct AxisCross {
     uint32_t sl, Q, R, D;
 };
 
-__host__ __device__ __forceinline__ void cross_init(AxisCross& c, int32_t p0, int32_t p1, uint32_t a,
-                                                    uint32_t neg, uint32_t N, int lg) {
-    c.b = p0 >> lg;
+// Crossing state of one axis at step k0 of the walk: the brick holding the
+// axis coordinate at k0 and the next crossing after it.  The coordinate's
+// offset from p0 at k0 is eq. (3)'s quotient there, (2 k0 a + N - neg) div 2N
+// (k0 itself on an axis with a = N, 0 at k0 = 0); the next crossing is where
+// the offset reaches the brick's far face, m, measured from p0.
+__host__ __device__ __forceinline__ void cross_init_at(AxisCross& c, int32_t p0, int32_t p1, uint32_t a,
+                                                       uint32_t neg, uint32_t N, int lg, uint32_t k0) {
+    uint32_t off = 0;
+    if (a == N) {
+        off = k0;
+    } else if (a != 0 && k0 != 0) {
+        uint32_t r;
+        divmod_u64(2ull * k0 * a + N - neg, 2u * N, off, r);
+    }
+    c.b = (neg ? p0 - (int32_t)off : p0 + (int32_t)off) >> lg;
     c.bend = p1 >> lg;
     c.dir = neg ? -1 : 1;
     c.kn = kNever;
@@ -92,6 +104,11 @@ __host__ __device__ __forceinline__ void cross_init(AxisCross& c, int32_t p0, in
     c.kn = r ? q + 1u : q;
     c.sl = r ? c.D - r : 0u;
     divmod_u64(2ull * N * B, c.D, c.Q, c.R);
+}
+
+__host__ __device__ __forceinline__ void cross_init(AxisCross& c, int32_t p0, int32_t p1, uint32_t a,
+                                                    uint32_t neg, uint32_t N, int lg) {
+    cross_init_at(c, p0, p1, a, neg, N, lg, 0u);
 }
 
 // Advances an axis if `hit` (its crossing c.kn has just happened), written
@@ -133,24 +150,90 @@ __host__ __device__ __forceinline__ SegAxes seg_axes(const Seg& g) {
     return s;
 }
 
-// Walks the bricks of one in-volume segment in order, calling
-// emit(brick id, klo, khi) with the k-window [klo, khi] of the segment inside
-// each brick: a window ends where the next crossing begins.
+// Cutting a walk into parts.  A long segment crosses many bricks, and the
+// lanes of a wave that walk segments side by side wait for the longest, so
+// the kernels cut a walk of an estimated `est` pieces into walk_parts(est)
+// parts (power-of-two sizes, so that a wave takes segments of one part count
+// at a time) and walk the parts on separate lanes.  The estimate is
+// 1 + sum_a |brick_a(P1) - brick_a(P0)|, exact unless axes cross at the same
+// k.  The cuts lie at brick crossings of one axis, so the parts' pieces are
+// exactly the whole walk's: the same records, found in a shorter time.
+constexpr uint32_t kMaxWalkParts = 8;
+__host__ __device__ __forceinline__ uint32_t walk_estimate(const int32_t p0[3], const int32_t p1[3],
+                                                           const int32_t lg[3]) {
+    uint32_t est = 1;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int32_t db = (p1[ax] >> lg[ax]) - (p0[ax] >> lg[ax]);
+        est += (uint32_t)(db < 0 ? -db : db);
+    }
+    return est;
+}
+__host__ __device__ __forceinline__ uint32_t walk_parts(uint32_t est) {
+    return est >= 64u ? 8u : (est >= 32u ? 4u : (est >= 16u ? 2u : 1u));
+}
+
+// k-window [k0, k1] of part `part` of `parts`.  The cuts follow the axis that
+// spans the most bricks (the first such axis), nbs of them: part i holds its
+// bricks [i nbs / parts, (i + 1) nbs / parts) in walk order, from the step
+// that enters the first to the step before the one that leaves the last.
+// Crossing t of that axis is the step at which the offset from p0 reaches
+// m0 + t B (m0: the start brick's far face, B: the brick size).  Returns
+// false for a part with no brick (nbs < parts).
+__host__ __device__ __forceinline__ bool part_window(const int32_t p0[3], const int32_t p1[3], const uint32_t a[3],
+                                                     const uint32_t neg[3], uint32_t N, const int32_t lg[3],
+                                                     uint32_t part, uint32_t parts, uint32_t& k0, uint32_t& k1) {
+    int32_t q0 = p0[0], l = lg[0];
+    uint32_t nbs = 0, as = a[0], ns = neg[0];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int32_t db = (p1[ax] >> lg[ax]) - (p0[ax] >> lg[ax]);
+        const uint32_t n = (uint32_t)(db < 0 ? -db : db) + 1u;
+        const bool more = n > nbs;
+        nbs = more ? n : nbs;
+        q0 = more ? p0[ax] : q0;
+        l = more ? lg[ax] : l;
+        as = more ? a[ax] : as;
+        ns = more ? neg[ax] : ns;
+    }
+    const uint32_t j0 = part * nbs / parts, j1 = (part + 1u) * nbs / parts;
+    if (j0 == j1) return false;
+    const int32_t b0 = q0 >> l;
+    const uint32_t m0 = ns ? (uint32_t)(q0 - (b0 << l) + 1) : (uint32_t)(((b0 + 1) << l) - q0);
+    const uint32_t B = 1u << l;
+    k0 = j0 == 0u ? 0u : k_reach(m0 + (j0 - 1u) * B, as, N, ns);
+    k1 = j1 == nbs ? N : k_reach(m0 + (j1 - 1u) * B, as, N, ns) - 1u;
+    return true;
+}
+
+// Walks the bricks of part `part` of `parts` of one in-volume segment in
+// order (parts = 1: the whole walk), calling emit(brick id, klo, khi) with
+// the k-window [klo, khi] of the segment inside each brick: a window ends
+// where the next crossing begins, or at the part's end.
 template <typename Emit>
-__host__ __device__ __forceinline__ void walk_bricks(const SegAxes& s, const BrickGeom& bg, Emit emit) {
+__host__ __device__ __forceinline__ void walk_bricks_part(const SegAxes& s, const BrickGeom& bg, uint32_t part,
+                                                          uint32_t parts, Emit emit) {
+    uint32_t k0 = 0, k1 = s.N;
+    if (parts > 1u && !part_window(s.p0, s.p1, s.a, s.neg, s.N, bg.lg, part, parts, k0, k1)) return;
     AxisCross c[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) cross_init(c[ax], s.p0[ax], s.p1[ax], s.a[ax], s.neg[ax], s.N, bg.lg[ax]);
-    uint32_t klo = 0;
+    for (int ax = 0; ax < 3; ++ax) cross_init_at(c[ax], s.p0[ax], s.p1[ax], s.a[ax], s.neg[ax], s.N, bg.lg[ax], k0);
+    uint32_t klo = k0;
     while (true) {
         uint32_t km = c[0].kn < c[1].kn ? c[0].kn : c[1].kn;
         km = km < c[2].kn ? km : c[2].kn;
-        emit((uint32_t)((c[2].b * bg.nb[1] + c[1].b) * bg.nb[0] + c[0].b), klo, km == kNever ? s.N : km - 1u);
-        if (km == kNever) break;
+        const bool more = km <= k1;
+        emit((uint32_t)((c[2].b * bg.nb[1] + c[1].b) * bg.nb[0] + c[0].b), klo, more ? km - 1u : k1);
+        if (!more) break;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) cross_advance(c[ax], c[ax].kn == km);
         klo = km;
     }
+}
+
+template <typename Emit>
+__host__ __device__ __forceinline__ void walk_bricks(const SegAxes& s, const BrickGeom& bg, Emit emit) {
+    walk_bricks_part(s, bg, 0u, 1u, emit);
 }
 
 __host__ __device__ __forceinline__ bool in_volume(const Seg& g, const BrickGeom& bg) {

@@ -1,6 +1,6 @@
-"""The brick path's exact integer helpers (brick walk, k-window clipping),
-built for the host from the library's own header, against the oracle's voxel
-lists grouped by brick (CPU only)."""
+"""The brick path's exact integer helpers (brick walk, the walk cut into
+parts, k-window clipping), built for the host from the library's own header,
+against the oracle's voxel lists grouped by brick (CPU only)."""
 
 import os
 import shutil
@@ -29,12 +29,15 @@ def driver(tmp_path_factory):
     return out
 
 
-def run(driver, segs, dims, lg):
+def run(driver, segs, dims, lg, euclid=False):
     inp = "%d %d %d %d %d %d %d\n" % (tuple(dims) + tuple(lg) + (len(segs),))
     inp += "\n".join(" ".join(str(int(v)) for v in s) for s in segs) + "\n"
-    r = subprocess.run([driver], input=inp, capture_output=True, text=True, check=True)
+    r = subprocess.run([driver] + (["euclid"] if euclid else []), input=inp, capture_output=True, text=True,
+                       check=True)
     out = []
     for line in r.stdout.splitlines():
+        # The driver reports a walk whose parts or windows disagree.
+        assert "MISMATCH" not in line, line
         body = line.split(":", 1)[1].strip()
         if body == "out":
             out.append(None)
@@ -115,3 +118,45 @@ def test_out_of_volume_flagged(driver):
     segs = np.array([[0, 0, 0, 64, 0, 0], [-1, 0, 0, 3, 3, 3], [1, 1, 1, 2, 2, 2]], np.int32)
     got = run(driver, segs, (64, 64, 64), (5, 5, 5))
     assert got[0] is None and got[1] is None and got[2] is not None
+
+
+def expected_euclid(segs, dims, lg):
+    """Pieces under the Euclidean N from the oracle's samples k = 0..N (each
+    sample, duplicates included, is one step of the walk)."""
+    o = oracle.native()
+    nb = [(dims[a] + (1 << lg[a]) - 1) >> lg[a] for a in range(3)]
+    res = []
+    for s in segs:
+        n = o.length_euclid(s)
+        v = np.array([o.sample_euclid(s, k) for k in range(n + 1)], dtype=np.int64)
+        b = v >> np.array(lg)
+        bid = (b[:, 2] * nb[1] + b[:, 1]) * nb[0] + b[:, 0]
+        pieces, start = [], 0
+        for k in range(1, len(bid) + 1):
+            if k == len(bid) or bid[k] != bid[start]:
+                pieces.append((int(bid[start]), start, k - 1))
+                start = k
+        res.append(pieces)
+    return res
+
+
+@pytest.mark.parametrize("dims,lg", [((96, 40, 20), (5, 3, 2)), ((320, 200, 100), (6, 5, 4)),
+                                     ((64, 64, 64), (5, 3, 3))])
+def test_walk_euclid(driver, dims, lg):
+    """The walk (whole and cut into parts) under the Euclidean N."""
+    segs = inside(dims, 250, 7 * sum(dims) + sum(lg))
+    assert run(driver, segs, dims, lg, euclid=True) == expected_euclid(segs, dims, lg)
+
+
+def test_parts_long_walks(driver):
+    """Segments crossing many small bricks: every walk is cut into 8 parts,
+    some of them empty (fewer bricks along the cut axis than parts), and the
+    parts are checked against the whole walk for both lengths."""
+    dims, lg = (1024, 512, 256), (5, 4, 4)
+    segs = inside(dims, 800, 99)
+    segs[:40, 3:] = segs[:40, :3]                  # points
+    segs[40:80, 4:] = segs[40:80, 1:3]             # along x
+    segs[80:120, 3] = segs[80:120, 0] + 17 * ((segs[80:120, 0] < 512) * 2 - 1)  # dx = +-17
+    got = run(driver, segs, dims, lg)
+    assert got == expected(segs, dims, lg)
+    run(driver, segs, dims, lg, euclid=True)       # parts == whole, windows == box windows
