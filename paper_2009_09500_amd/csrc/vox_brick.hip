@@ -587,23 +587,30 @@ __device__ __forceinline__ void euclid_counts(const Stage<kN>& st, int32_t* __re
     }
 }
 
-// Walks the ordered staged segments.  The order falls into four classes of
-// walk_parts (8, 4, 2 and 1 parts, longest walks first), and the walk into
-// groups of 64 part walks: 8 segments of the first class cut into 8 parts
-// each, 16 of the second cut into 4, and so on.  Waves claim groups in order
-// from an LDS counter, so the longest groups start first and a wave that
-// finishes early takes the next group (no wave waits for a fixed share).
-// Lanes of a group step their parts one brick at a time until the last ends.
+// Walks the ordered staged segments.  With kSplit the order falls into four
+// classes of walk_parts (8, 4, 2 and 1 parts, longest walks first), and the
+// walk into groups of 64 part walks: 8 segments of the first class cut into
+// 8 parts each, 16 of the second cut into 4, and so on; without, into groups
+// of 64 whole walks.  Waves claim groups in order from an LDS counter, so the
+// longest groups start first and a wave that finishes early takes the next
+// group (no wave waits for a fixed share).  Lanes of a group step their
+// walks one brick at a time until the last ends.  The parts cost a division
+// or three each at their start: the scatter, whose steps are dear (a record
+// store each), gains from them, the histogram (an LDS increment a step) does
+// not.
 // emit(brick id, klo, khi, staged segment, brick x, y, z, N) per piece,
 // [klo, khi] being the segment's k-window inside the brick.  The segment is
 // read from LDS once per walk, so what the emitter derives from it alone is
 // computed once per walk, not per piece.
-template <int kN, typename Emit>
+template <bool kSplit, int kN, typename Emit>
 __device__ __forceinline__ void walk_ordered(Stage<kN>& st, const BrickGeom& bg, bool euclid, Emit emit) {
     const uint32_t lane = __lane_id();
     const uint32_t nvalid = st.nvalid;
-    // Ends of the classes in the order, and their first groups.
-    const uint32_t e8 = st.bins[kBinEnd8], e4 = st.bins[kBinEnd4], e2 = st.bins[kBinEnd2];
+    // Ends of the classes in the order, and their first groups (without
+    // kSplit every walk is in the last class).
+    const uint32_t e8 = kSplit ? st.bins[kBinEnd8] : 0u;
+    const uint32_t e4 = kSplit ? st.bins[kBinEnd4] : 0u;
+    const uint32_t e2 = kSplit ? st.bins[kBinEnd2] : 0u;
     const uint32_t g4 = (e8 + 7u) >> 3;
     const uint32_t g2 = g4 + ((e4 - e8 + 15u) >> 4);
     const uint32_t g1 = g2 + ((e2 - e4 + 31u) >> 5);
@@ -665,10 +672,10 @@ __device__ __forceinline__ void hist_row(const BrickScene& sc, uint32_t g, Stage
     for (int64_t base = lo; base < hi; base += kN) {
         const uint32_t cnt = (uint32_t)(hi - base < kN ? hi - base : kN);
         stage_segments(sc.segs, base, cnt, bg, euclid, st, sc.counts, bad);
-        walk_ordered(st, bg, euclid,
-                     [&](uint32_t b, uint32_t, uint32_t, const StagedSeg&, int32_t, int32_t, int32_t, uint32_t) {
-                         atomicAdd(&lh[b], 1u);
-                     });
+        walk_ordered<false>(st, bg, euclid,
+                            [&](uint32_t b, uint32_t, uint32_t, const StagedSeg&, int32_t, int32_t, int32_t, uint32_t) {
+                                atomicAdd(&lh[b], 1u);
+                            });
         if (euclid && sc.counts) euclid_counts(st, sc.counts + base, cscratch);
         lds_barrier();
     }
@@ -953,14 +960,14 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restric
         const uint32_t cnt = (uint32_t)(hi - base < kStage ? hi - base : kStage);
         stage_segments(sc.segs, base, cnt, bg, euclid, st, nullptr, bad);
         if (euclid) {
-            walk_ordered(st, bg, true, [&](uint32_t b, uint32_t klo, uint32_t khi, const StagedSeg& g, int32_t bx,
-                                           int32_t by, int32_t bz, uint32_t N) {
+            walk_ordered<true>(st, bg, true, [&](uint32_t b, uint32_t klo, uint32_t khi, const StagedSeg& g,
+                                                 int32_t bx, int32_t by, int32_t bz, uint32_t N) {
                 const uint32_t pos = atomicAdd(&cur[b], 1u);
                 recs[pos] = piece_record_euclid(g, N, klo, khi, bx, by, bz, bg);
             });
         } else {
-            walk_ordered(st, bg, false, [&](uint32_t b, uint32_t klo, uint32_t khi, const StagedSeg& g, int32_t bx,
-                                            int32_t by, int32_t bz, uint32_t) {
+            walk_ordered<true>(st, bg, false, [&](uint32_t b, uint32_t klo, uint32_t khi, const StagedSeg& g,
+                                                  int32_t bx, int32_t by, int32_t bz, uint32_t) {
                 const uint32_t pos = atomicAdd(&cur[b], 1u);
                 recs[pos] = piece_record(g, klo, khi, bx, by, bz, bg);
             });
