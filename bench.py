@@ -643,6 +643,9 @@ def cpu_baseline_other(workloads):
     return out
 
 
+ONLY_WORKLOADS = ("list", "list_euclid", "grid_euclid", "paper_shapes", "small", "batch", "serving")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -654,11 +657,21 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuning (profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated extra workloads to run alone, for profiler runs (list, list_euclid, "
+                         "grid_euclid, paper_shapes, small, batch, serving): no main workload, no CPU "
+                         "baseline; prints {\"only\": {name: result}}")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs on a single MI355X and has "
               "no multi-GPU path (sharding is described, not implemented); run with --gpus 1",
               file=sys.stderr)
+        sys.exit(2)
+
+    only = [x for x in args.only.split(",") if x]
+    unknown = [x for x in only if x not in ONLY_WORKLOADS]
+    if unknown:
+        print("unknown workload(s) for --only: %s" % ", ".join(unknown), file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -674,6 +687,20 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    if args.only:
+        runs = {
+            "list": lambda: bench_list(args, torch, binding, workloads, dev, stream),
+            "list_euclid": lambda: bench_list(args, torch, binding, workloads, dev, stream, euclid=True),
+            "grid_euclid": lambda: bench_grid_euclid(args, torch, binding, workloads, dev, stream),
+            "paper_shapes": lambda: bench_paper(args, torch, binding, workloads, dev, stream),
+            "small": lambda: bench_small(args, torch, binding, workloads, dev, stream),
+            "batch": lambda: bench_batch(args, torch, binding, workloads, dev, stream),
+            "serving": lambda: bench_serving(args, torch, binding, workloads, dev),
+        }
+        names = [x for x in args.only.split(",") if x]
+        print(json.dumps({"only": {x: runs[x]() for x in names}}))
+        return
 
     r = bench_grid(args, torch, binding, workloads, dev, stream)
     ms_step = r["ms_total"] / args.steps
