@@ -28,14 +28,19 @@
 //   colscan   per brick, exclusive prefix of the rows over workgroups, and
 //             the brick's piece total
 //   base      exclusive scan of the brick totals -> bin offsets; if the
-//             records do not fit the workspace, the direct kernels take over
+//             records do not fit the workspace, the direct kernels take over;
+//             the fill's work items: one per brick, several for a brick with
+//             more than a fair share of the records
+//   clear     zeroes the volumes of the cleared direct scenes and, in
+//             cleared brick scenes, the bricks cut into several items
 //   scatter   the same walk again, writing one 16-byte piece record (start
 //             point, direction, k-window in the brick) into the brick's bin
-//   fill      persistent workgroups take bricks from work-stealing queues,
-//             set the bits of every piece with LDS atomic OR and flush the
-//             brick to the volume
-//   direct    (batches) clear, then one device atomic per voxel, for the
-//             scenes the bricks do not serve
+//   fill      persistent workgroups take work items from work-stealing
+//             queues, set the bits of every piece with LDS atomic OR and
+//             flush the brick to the volume (an item that holds part of a
+//             brick with device atomic OR)
+//   direct    (batches) one device atomic per voxel, for the scenes the
+//             bricks do not serve
 #include "vox.h"
 #include "vox_device.h"
 #include "vox_direct.h"
@@ -103,8 +108,38 @@ static_assert(sizeof(Piece) == 16, "16-byte piece records");
 
 // Sections of the workspace: the header words, the table the plan kernel
 // writes at kWorkTable, then at the table's data_off the histograms, the
-// brick totals, the bin offsets and the piece records (the rest of the
-// workspace).
+// brick totals, the bin offsets, the fill's work items and the piece records
+// (the rest of the workspace).
+//
+// Work items of the fill.  A brick's records are the work of one workgroup,
+// and a brick can hold far more than a workgroup's fair share of a launch
+// (a small dense volume in a batch is a single brick of millions of
+// voxels), which would leave one workgroup running long after the others.
+// So a brick with more than T records, T = max(kSplitMinRecords,
+// ceil(total / kSplitShares)), becomes ceil(records / T) items, each with
+// an even part of its records, set in LDS by its own workgroup and ORed
+// into the volume with device atomics (the clear kernel zeroes such a
+// brick first in a cleared volume).  Since every cut brick holds more than
+// T records, the items beyond one per brick number at most
+// total / T <= kSplitShares, and so do the cut bricks.
+constexpr uint32_t kSplitShares = 1024;
+constexpr uint32_t kSplitMinRecords = 4096;
+constexpr uint32_t kMaxExtraItems = kSplitShares;
+
+__host__ __device__ inline uint64_t split_threshold(uint64_t total) {
+    const uint64_t t = total / kSplitShares + (total % kSplitShares != 0u ? 1u : 0u);
+    return t > kSplitMinRecords ? t : kSplitMinRecords;
+}
+__host__ __device__ inline uint32_t brick_items(uint32_t records, uint64_t T) {
+    if (records <= T) return 1u;               // every brick when T >= 2^32
+    return (records - 1u) / (uint32_t)T + 1u;  // ceil(records / T), T < records < 2^32
+}
+
+// Bytes from the table's data_off to the piece records.
+__host__ __device__ inline uint64_t brick_data_bytes(uint64_t hist_words, uint64_t bricks) {
+    return up256(hist_words * 4u) + up256(bricks * 4u) + 2u * up256((bricks + 1u) * 4u) +
+           up256((bricks + kMaxExtraItems) * 4u) + up256((uint64_t)kMaxExtraItems * 4u);
+}
 struct WorkView {
     int32_t* status;
     uint32_t* counter;   // [kXcds] brick queues of the fill, one per XCD
@@ -114,6 +149,11 @@ struct WorkView {
     uint32_t* hist;
     uint32_t* totals;
     uint32_t* bin_base;
+    uint32_t* n_items;     // fill work items (header word)
+    uint32_t* n_split;     // bricks cut into several items (header word)
+    uint32_t* item_base;   // [bricks + 1] first work item of each brick
+    uint32_t* item_brick;  // [bricks + kMaxExtraItems] brick of each work item
+    uint32_t* split;       // [kMaxExtraItems] the bricks cut into several items
     Piece* recs;
     uint64_t rec_off;    // byte offset of the records
 };
@@ -127,6 +167,8 @@ __host__ __device__ inline WorkView work_view(uint8_t* work, uint64_t data_off, 
     v.ok = w + kWOk;
     v.direct_all = w + kWDirectAll;
     v.pieces = reinterpret_cast<uint64_t*>(w + kWPieces);
+    v.n_items = w + kWItems;
+    v.n_split = w + kWSplit;
     uint64_t off = data_off;
     v.hist = reinterpret_cast<uint32_t*>(work + off);
     off += up256(hist_words * 4u);
@@ -134,6 +176,12 @@ __host__ __device__ inline WorkView work_view(uint8_t* work, uint64_t data_off, 
     off += up256((uint64_t)bricks * 4u);
     v.bin_base = reinterpret_cast<uint32_t*>(work + off);
     off += up256(((uint64_t)bricks + 1u) * 4u);
+    v.item_base = reinterpret_cast<uint32_t*>(work + off);
+    off += up256(((uint64_t)bricks + 1u) * 4u);
+    v.item_brick = reinterpret_cast<uint32_t*>(work + off);
+    off += up256(((uint64_t)bricks + kMaxExtraItems) * 4u);
+    v.split = reinterpret_cast<uint32_t*>(work + off);
+    off += up256((uint64_t)kMaxExtraItems * 4u);
     v.recs = reinterpret_cast<Piece*>(work + off);
     v.rec_off = off;
     return v;
@@ -166,15 +214,17 @@ __device__ __forceinline__ WorkView work_of(uint8_t* work, const TableView& tv) 
     return work_view(work, tv.h.data_off, tv.h.hist_words, tv.h.bricks);
 }
 
-// Brick queues of the fill.  The 8 XCDs of the chip each have their own L2;
-// workgroup w runs on XCD w % 8.  Groups of 8 consecutive bricks (along x, the
-// fastest brick axis) are dealt to the XCDs in turn, so neighbouring bricks,
-// whose 32-byte row pieces share memory lines, are flushed through the same
-// L2 at about the same time and reach HBM as whole lines.  A workgroup takes
-// from its own XCD's queue first and then from the others.
+// Work queues of the fill (over its work items: one per brick, more for a
+// brick cut into several).  The 8 XCDs of the chip each have their own L2;
+// workgroup w runs on XCD w % 8.  Groups of 8 consecutive items (bricks
+// along x, the fastest brick axis) are dealt to the XCDs in turn, so
+// neighbouring bricks, whose 32-byte row pieces share memory lines, are
+// flushed through the same L2 at about the same time and reach HBM as whole
+// lines.  A workgroup takes from its own XCD's queue first and then from
+// the others.
 constexpr int kXcds = 8;
 
-// Brick of the c-th claim on queue x.
+// Item of the c-th claim on queue x.
 __device__ __forceinline__ uint32_t queue_brick(uint32_t x, uint32_t c) {
     return (c >> 3) * (8u * kXcds) + x * 8u + (c & 7u);
 }
@@ -201,6 +251,33 @@ __device__ __forceinline__ uint32_t claim_brick(uint32_t* queues, uint32_t xcd, 
         }
         if (!open) return NB;
     }
+}
+
+// The next work item of a workgroup (claimed by one thread): its brick (NB
+// when none is left), its part [lo, hi) of the brick's records and whether
+// the brick is cut into several items.
+struct ItemClaim {
+    uint32_t brick, lo, hi, split;
+};
+__device__ __forceinline__ ItemClaim claim_item(const WorkView& wv, uint32_t xcd, uint32_t n_items, uint32_t n_split,
+                                                uint32_t NB) {
+    ItemClaim c = {NB, 0u, 0u, 0u};
+    const uint32_t i = claim_brick(wv.counter, xcd, n_items);
+    if (i >= n_items) return c;
+    if (n_split == 0u) {  // the items are the bricks
+        c.brick = i;
+        c.lo = wv.bin_base[i];
+        c.hi = wv.bin_base[i + 1];
+        return c;
+    }
+    const uint32_t b = wv.item_brick[i];
+    const uint32_t i0 = wv.item_base[b], k = wv.item_base[b + 1] - i0, j = i - i0;
+    const uint32_t lo = wv.bin_base[b], cnt = wv.bin_base[b + 1] - lo;
+    c.brick = b;
+    c.lo = lo + (uint32_t)((uint64_t)cnt * j / k);
+    c.hi = lo + (uint32_t)((uint64_t)cnt * (j + 1u) / k);
+    c.split = k > 1u ? 1u : 0u;
+    return c;
 }
 
 // Histogram row of workgroup w out of G.  Each XCD takes a contiguous block
@@ -758,29 +835,135 @@ __global__ __launch_bounds__(kHistBlock) void k_brick_plan_hist(vox_scene one, B
 
 constexpr int kBaseBlock = 1024;
 
-// bin_base[b] = sum of totals before global brick b, bin_base[NB] = total,
-// by one block of kBlock threads: each thread sums a run of consecutive
-// totals, one block scan of the run sums (64-bit; lds: kBlock / 64 entries),
-// then each thread writes its run's offsets.  The direct kernels take over
-// when the records do not fit the workspace (or reach 2^32 - 1).
+// The brick totals pass through LDS in chunks of kBaseChunk bricks: loaded
+// coalesced (all of a thread's loads issued before any is used), read in
+// runs of consecutive bricks per thread for the scans, and the results (bin
+// offsets, item offsets, the brick of each item) staged in LDS and written
+// back coalesced: from one workgroup, stores of the threads' runs would each
+// touch a memory line of their own.  Entry i of a stage sits at i + i / 32,
+// so that the lanes' runs (16 entries apart) fall in different banks.
+constexpr uint32_t kBaseChunk = 16384;
+constexpr uint32_t kBaseStage = (kBaseChunk + 1024u) + (kBaseChunk + 1024u) / 32;  // a chunk's items at most
+__device__ __forceinline__ uint32_t stage_slot(uint32_t i) { return i + (i >> 5); }
+
 template <int kBlock>
-__device__ __forceinline__ void scan_totals(const WorkView& wv, uint32_t NB, uint64_t work_bytes, uint64_t* lds) {
-    const uint32_t per = (NB + kBlock - 1) / kBlock;
-    const uint32_t lo = threadIdx.x * per < NB ? threadIdx.x * per : NB;
-    const uint32_t hi = lo + per < NB ? lo + per : NB;
+__device__ __forceinline__ void stage_in(const uint32_t* __restrict__ src, uint32_t m, uint32_t* st) {
+    constexpr int kPer = (int)(kBaseChunk / kBlock);
+    uint32_t v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t i = threadIdx.x + (uint32_t)k * kBlock;
+        v[k] = i < m ? src[i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) st[stage_slot(threadIdx.x + (uint32_t)k * kBlock)] = v[k];
+    __syncthreads();
+}
+
+template <int kBlock>
+__device__ __forceinline__ void stage_out(const uint32_t* st, uint32_t m, uint32_t* __restrict__ dst) {
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) dst[i] = st[stage_slot(i)];
+}
+
+// Exclusive scan, from `base`, of f(entry) over the m entries of a stage
+// (runs of kBaseChunk / kBlock consecutive entries per thread, one block
+// scan of the run sums; lds: kBlock / 64 entries) into the stage `out`;
+// returns the sum.
+template <int kBlock, typename F>
+__device__ __forceinline__ uint64_t scan_stage(const uint32_t* st, uint32_t m, uint64_t base, uint32_t* out,
+                                               uint64_t* lds, F f, uint32_t* max_s = nullptr) {
+    constexpr uint32_t kRun = kBaseChunk / kBlock;
+    const uint32_t r0 = threadIdx.x * kRun;
     uint64_t run = 0;
-    for (uint32_t i = lo; i < hi; ++i) run += wv.totals[i];
-    uint64_t total;
-    uint64_t off = block_exclusive_sum<kBlock>(run, lds, total);
-    for (uint32_t i = lo; i < hi; ++i) {
-        wv.bin_base[i] = (uint32_t)off;
-        off += wv.totals[i];
+    uint32_t mx = 0;
+    for (uint32_t k = 0; k < kRun && r0 + k < m; ++k) {
+        const uint32_t c = st[stage_slot(r0 + k)];
+        run += f(c);
+        mx = c > mx ? c : mx;
+    }
+    if (max_s) {
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)mx, d, kWave);
+            mx = o > mx ? o : mx;
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_s, mx);  // (read after the scan's barriers)
+    }
+    uint64_t sum;
+    uint64_t off = base + block_exclusive_sum<kBlock>(run, lds, sum);
+    for (uint32_t k = 0; k < kRun && r0 + k < m; ++k) {
+        out[stage_slot(r0 + k)] = (uint32_t)off;
+        off += f(st[stage_slot(r0 + k)]);
+    }
+    __syncthreads();
+    return sum;
+}
+
+// bin_base[b] = sum of totals before global brick b, bin_base[NB] = total,
+// by one block of kBlock threads, a chunk at a time.  The direct kernels
+// take over when the records do not fit the workspace (or reach 2^32 - 1).
+template <int kBlock>
+__device__ __forceinline__ uint64_t scan_totals(const WorkView& wv, uint32_t NB, uint64_t work_bytes, uint64_t* lds,
+                                                uint32_t* st, uint32_t* ob, uint32_t* max_s) {
+    uint64_t total = 0;
+    if (threadIdx.x == 0) *max_s = 0u;  // (ordered before the atomics by stage_in's barrier)
+    for (uint32_t c0 = 0; c0 < NB; c0 += kBaseChunk) {
+        const uint32_t m = NB - c0 < kBaseChunk ? NB - c0 : kBaseChunk;
+        stage_in<kBlock>(wv.totals + c0, m, st);
+        total += scan_stage<kBlock>(st, m, total, ob, lds, [](uint32_t c) { return (uint64_t)c; }, max_s);
+        stage_out<kBlock>(ob, m, wv.bin_base + c0);
+        __syncthreads();  // both stages are rewritten by the next chunk (st read by make_items)
     }
     if (threadIdx.x == 0) {
         wv.bin_base[NB] = (uint32_t)total;
         *wv.pieces = total;
         const uint64_t cap = work_bytes > wv.rec_off ? (work_bytes - wv.rec_off) / sizeof(Piece) : 0u;
         if (total > cap || total >= 0xFFFFFFFFull) *wv.direct_all = 1u;
+    }
+    return total;
+}
+
+// The fill's work items (see kSplitShares) when some brick is cut, the same
+// way: item_base[b] = items before brick b; the list of cut bricks; the
+// brick of each item, staged in LDS (the totals' stage, free by then) and
+// written back coalesced; the counts in the header.  With a single chunk the
+// stage still holds the totals from scan_totals.  When no brick is cut the
+// items are the bricks (n_split = 0 tells the fill and the clear kernel so,
+// and the item arrays are not written).
+template <int kBlock>
+__device__ __forceinline__ void make_items(const WorkView& wv, uint32_t NB, uint64_t total, uint64_t* lds,
+                                           uint32_t* st, uint32_t* ob, uint32_t* n_split_s) {
+    const uint64_t T = split_threshold(total);
+    if (threadIdx.x == 0) *n_split_s = 0u;  // (ordered before the atomics below by the scan's barriers)
+    uint64_t items = 0;
+    for (uint32_t c0 = 0; c0 < NB; c0 += kBaseChunk) {
+        const uint32_t m = NB - c0 < kBaseChunk ? NB - c0 : kBaseChunk;
+        if (NB > kBaseChunk) stage_in<kBlock>(wv.totals + c0, m, st);
+        const uint64_t sum = scan_stage<kBlock>(st, m, items, ob, lds, [T](uint32_t c) {
+            return (uint64_t)brick_items(c, T);
+        });
+        stage_out<kBlock>(ob, m, wv.item_base + c0);
+        // A brick's items are the difference of its item offset and the
+        // next one.  The chunk's cut bricks, then the brick of each of the
+        // chunk's items (at most kBaseChunk + 1023 of them) through the
+        // totals' stage, free by now, and out coalesced.
+        const uint32_t end = (uint32_t)(items + sum);
+        __syncthreads();  // every thread's scan reads of st are done
+        for (uint32_t i = threadIdx.x; i < m; i += kBlock) {
+            const uint32_t o = ob[stage_slot(i)];
+            const uint32_t n = (i + 1u < m ? ob[stage_slot(i + 1u)] : end) - o;
+            if (n > 1u) wv.split[atomicAdd(n_split_s, 1u)] = c0 + i;
+            for (uint32_t j = 0; j < n; ++j) st[stage_slot(o - (uint32_t)items + j)] = c0 + i;
+        }
+        __syncthreads();
+        stage_out<kBlock>(st, (uint32_t)sum, wv.item_brick + items);
+        items += sum;
+        __syncthreads();  // both stages are rewritten by the next chunk
+    }
+    if (threadIdx.x == 0) {
+        wv.item_base[NB] = (uint32_t)items;
+        *wv.n_items = (uint32_t)items;
+        *wv.n_split = *n_split_s;
     }
 }
 
@@ -848,10 +1031,18 @@ __global__ __launch_bounds__(256) void k_brick_colscan(uint8_t* __restrict__ wor
 // every scene instead of the scatter and the fill.
 __global__ __launch_bounds__(kBaseBlock) void k_brick_base(uint8_t* __restrict__ work, uint64_t work_bytes) {
     __shared__ uint64_t lds[kBaseBlock / kWave];
+    __shared__ uint32_t st[kBaseStage], ob[kBaseStage];
+    __shared__ uint32_t n_split_s, max_s;
     const TableView tv = table_view(work + kWorkTable);
     const WorkView wv = work_of(work, tv);
     if (*wv.ok == 0) return;
-    scan_totals<kBaseBlock>(wv, tv.h.bricks, work_bytes, lds);
+    const uint64_t total = scan_totals<kBaseBlock>(wv, tv.h.bricks, work_bytes, lds, st, ob, &max_s);
+    if ((uint64_t)max_s > split_threshold(total)) {
+        make_items<kBaseBlock>(wv, tv.h.bricks, total, lds, st, ob, &n_split_s);
+    } else if (threadIdx.x == 0) {
+        *wv.n_items = tv.h.bricks;
+        *wv.n_split = 0u;
+    }
 }
 
 // The record of the piece of staged segment g with k-window [klo, khi] in
@@ -1403,14 +1594,13 @@ void k_brick_fill(uint8_t* __restrict__ work) {
     __shared__ __align__(16) uint32_t brick[Shape::kWords];
     __shared__ uint16_t ent[kWaves][kEntCap];  // per-wave chunk tables
     __shared__ uint32_t cursor_s[kQuarters];  // per-SIMD record cursors of the brick
-    __shared__ uint32_t next_s[3];
+    __shared__ uint32_t next_s[4];
 
     const TableView tv = table_view(work + kWorkTable);
     const WorkView wv = work_of(work, tv);
     if (*wv.ok == 0 || *wv.direct_all != 0) return;
     const uint32_t NB = tv.h.bricks;  // global bricks of all scenes
-    uint32_t* __restrict__ work_counter = wv.counter;
-    const uint32_t* __restrict__ bin_base = wv.bin_base;
+    const uint32_t n_items = *wv.n_items, n_split = *wv.n_split;
     const uint32_t lane = __lane_id();
     const uint32_t wave = threadIdx.x / kWave;
     uint16_t* my_ent = ent[wave];
@@ -1420,14 +1610,16 @@ void k_brick_fill(uint8_t* __restrict__ work) {
     // without a claim (first_group); the cursors start after them.
     constexpr uint32_t kSkip = (uint32_t)(kWaves / kQuarters) * (uint32_t)kGroup;
     const uint32_t qu = wave % kQuarters, slot = wave / kQuarters;
-    // The next brick and its bin range are claimed by thread 0 at the start
-    // of the current one, so their memory latency overlaps this brick's work.
+    // The next work item (its brick and record range) is claimed by thread 0
+    // at the start of the current one, so its memory latency overlaps this
+    // item's work.
     if (threadIdx.x == 0) {
-        const uint32_t nb = claim_brick(work_counter, blockIdx.x % kXcds, NB);
-        next_s[0] = nb;
-        next_s[1] = nb < NB ? bin_base[nb] : 0u;
-        next_s[2] = nb < NB ? bin_base[nb + 1] : 0u;
-        set_quarters(cursor_s, next_s[1], next_s[2], kSkip);
+        const ItemClaim c = claim_item(wv, blockIdx.x % kXcds, n_items, n_split, NB);
+        next_s[0] = c.brick;
+        next_s[1] = c.lo;
+        next_s[2] = c.hi;
+        next_s[3] = c.split;
+        set_quarters(cursor_s, c.lo, c.hi, kSkip);
     }
     {
         u32x4* b4 = reinterpret_cast<u32x4*>(brick);
@@ -1435,20 +1627,14 @@ void k_brick_fill(uint8_t* __restrict__ work) {
     }
     lds_barrier();
     uint32_t b = next_s[0];
-    uint32_t p_lo = next_s[1], p_hi = next_s[2];
+    uint32_t p_lo = next_s[1], p_hi = next_s[2], split = next_s[3];
     uint32_t gbase = 0, q_hi = 0;
     u32x4 rn0 = {0u, 0u, 0u, 0u}, rn1 = {0u, 0u, 0u, 0u};
     if (b < NB) first_group(recv, p_lo, p_hi, qu, slot, lane, gbase, q_hi, rn0, rn1);
 
     while (b < NB) {
-        uint32_t nb = 0, nlo = 0, nhi = 0;
-        if (threadIdx.x == 0) {
-            nb = claim_brick(work_counter, blockIdx.x % kXcds, NB);
-            if (nb < NB) {
-                nlo = bin_base[nb];
-                nhi = bin_base[nb + 1];
-            }
-        }
+        ItemClaim nc = {NB, 0u, 0u, 0u};
+        if (threadIdx.x == 0) nc = claim_item(wv, blockIdx.x % kXcds, n_items, n_split, NB);
         // The brick's scene and its place in that scene's volume.
         const uint32_t gb = __builtin_amdgcn_readfirstlane(b);
         const BrickScene& sc = tv.scenes[tv.brick_scene ? tv.brick_scene[gb] : 0u];
@@ -1480,14 +1666,15 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         else
             fill_records<false, LGX, LGY, LGZ, kEntCap>(brick, my_ent, recv, cursor_s, qu, q_hi, gbase, rn0, rn1,
                                                         lane);
-        // Hand over the next brick (read by all after the barrier).
+        // Hand over the next item (read by all after the barrier).
         if (threadIdx.x == 0) {
-            next_s[0] = nb;
-            next_s[1] = nlo;
-            next_s[2] = nhi;
+            next_s[0] = nc.brick;
+            next_s[1] = nc.lo;
+            next_s[2] = nc.hi;
+            next_s[3] = nc.split;
         }
-        lds_barrier();  // every wave done with this brick
-        const uint32_t b_next = next_s[0], lo_next = next_s[1], hi_next = next_s[2];
+        lds_barrier();  // every wave done with this item
+        const uint32_t b_next = next_s[0], lo_next = next_s[1], hi_next = next_s[2], split_next = next_s[3];
         // The next brick's first group is loaded before the flush's stores:
         // a wait for a load also waits for every store issued before it, so
         // loaded after the flush its records would arrive only once the
@@ -1495,14 +1682,32 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         if (b_next < NB) first_group(recv, lo_next, hi_next, qu, slot, lane, gbase, q_hi, rn0, rn1);
 
         // Flush: brick rows -> volume words, zeroing the brick on the way.
-        // The owner writes every word of its brick, so a clearing call needs
-        // no other pass.  A brick with no pieces in a scene that ORs into its
-        // volume changes nothing: no flush (its LDS copy is still zero).
+        // The owner of a whole brick writes every word of it, so a clearing
+        // call needs no other pass.  A brick with no pieces in a scene that
+        // ORs into its volume changes nothing: no flush (its LDS copy is
+        // still zero).  An item holding part of a cut brick ORs its nonzero
+        // words into the volume with device atomics (the other items of the
+        // brick do the same; the clear kernel zeroed the brick first in a
+        // cleared volume).
         const int rows = (clear || p_lo != p_hi) ? ext[1] * ext[2] : 0;
         // Whole 16-byte units when the volume's rows hold whole brick rows.
         const bool vec = Shape::kBXw % 4 == 0 && (bg.dim[0] & ((1 << LGX) - 1)) == 0;
         const bool full_y = ext[1] == (1 << LGY);  // rows per slab a power of two
-        if (vec && full_y) {
+        if (split) {
+            const int xws = ext[0] >> 5;  // whole words: dim_x and the brick origin are multiples of 32
+            const int total = rows * xws;
+            for (int t = threadIdx.x; t < total; t += kBlock) {
+                const int xw = t % xws, r = t / xws;
+                const int y = r % ext[1], z = r / ext[1];
+                uint32_t* src = &brick[(((uint32_t)z << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + xw];
+                const uint32_t v = *src;
+                *src = 0u;  // zero for the next item
+                if (v != 0u)
+                    __hip_atomic_fetch_or(grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words +
+                                              (org[0] >> 5) + xw,
+                                          v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else if (vec && full_y) {
             // 16-byte units, kUpr per row, rows full width and full slabs:
             // a thread's units share their row in the slab and their part of
             // the row, and step by a fixed number of slabs (kBlock units are
@@ -1565,10 +1770,11 @@ void k_brick_fill(uint8_t* __restrict__ work) {
             }
         }
         // Every word that can hold a bit (inside the volume) was read and
-        // zeroed above; the others were never set.  Next brick:
+        // zeroed above; the others were never set.  Next item:
         b = b_next;
         p_lo = lo_next;
         p_hi = hi_next;
+        split = split_next;
         if (threadIdx.x == 0) set_quarters(cursor_s, p_lo, p_hi, kSkip);
         lds_barrier();
     }
@@ -1590,14 +1796,47 @@ __device__ __forceinline__ bool direct_scenes(const uint8_t* work, const TableVi
     return count > 0;
 }
 
-// Zeroes the volumes of the cleared direct scenes.
-__global__ __launch_bounds__(kDirectBlock) void k_batch_direct_clear(uint8_t* __restrict__ work) {
+// Before the fill: zeroes, in cleared brick scenes, the bricks cut into
+// several work items (their items OR into the volume), and the volumes of
+// the cleared direct scenes.
+__global__ __launch_bounds__(kDirectBlock) void k_brick_clear(uint8_t* __restrict__ work) {
     const TableView tv = table_view(work + kWorkTable);
+    const int64_t t0 = (int64_t)blockIdx.x * kDirectBlock + threadIdx.x;
+    const int64_t ts = (int64_t)gridDim.x * kDirectBlock;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(work);
+    if (w[kWOk] != 0u && w[kWDirectAll] == 0u) {
+        const WorkView wv = work_of(work, tv);
+        const uint32_t ns = *wv.n_split;
+        for (uint32_t j = blockIdx.x; j < ns; j += gridDim.x) {  // a workgroup a brick
+            const uint32_t gb = wv.split[j];
+            const BrickScene& sc = tv.scenes[tv.brick_scene ? tv.brick_scene[gb] : 0u];
+            if (!(sc.flags & kSceneClear)) continue;
+            const BrickGeom& bg = sc.bg;
+            const uint32_t lb = gb - sc.brick_base;
+            const int32_t org[3] = {(int32_t)(lb % (uint32_t)bg.nb[0]) << bg.lg[0],
+                                    (int32_t)((lb / (uint32_t)bg.nb[0]) % (uint32_t)bg.nb[1]) << bg.lg[1],
+                                    (int32_t)(lb / ((uint32_t)bg.nb[0] * (uint32_t)bg.nb[1])) << bg.lg[2]};
+            int32_t ext[3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int32_t e = bg.dim[ax] - org[ax];
+                ext[ax] = e < (1 << bg.lg[ax]) ? e : (1 << bg.lg[ax]);
+            }
+            // A brick has at most 2^20 bits: 32-bit index arithmetic.
+            const uint32_t xws = (uint32_t)ext[0] >> 5, ey = (uint32_t)ext[1];
+            const uint32_t words = xws * ey * (uint32_t)ext[2];
+            const int64_t row_words = (int64_t)bg.dim[0] >> 5;
+            for (uint32_t t = threadIdx.x; t < words; t += kDirectBlock) {
+                const uint32_t xw = t % xws, r = t / xws;
+                const uint32_t y = r % ey, z = r / ey;
+                sc.grid[((int64_t)(org[2] + (int32_t)z) * bg.dim[1] + (org[1] + (int32_t)y)) * row_words +
+                        (org[0] >> 5) + xw] = 0u;
+            }
+        }
+    }
     uint32_t nd;
     bool all;
     if (!direct_scenes(work, tv, nd, all)) return;
-    const int64_t t0 = (int64_t)blockIdx.x * kDirectBlock + threadIdx.x;
-    const int64_t ts = (int64_t)gridDim.x * kDirectBlock;
     for (uint32_t j = 0; j < nd; ++j) {
         const BrickScene& sc = tv.scenes[all ? j : tv.direct[j]];
         if (!(sc.flags & kSceneClear)) continue;
@@ -1690,10 +1929,9 @@ BrickLaunch batch_launch(uint32_t n_scenes, uint64_t total_segments, const int l
 }
 
 // Table, histograms (each scene's rows times at most kMaxBricks bricks),
-// brick totals and offsets.
+// brick totals, offsets and work items.
 size_t batch_fixed_bytes(const BrickLaunch& L) {
-    return (size_t)(kWorkTable + L.table_bytes + up256((uint64_t)L.rows * kMaxBricks * 4u) +
-                    up256((uint64_t)L.bricks * 4u) + up256(((uint64_t)L.bricks + 1u) * 4u));
+    return (size_t)(kWorkTable + L.table_bytes + brick_data_bytes((uint64_t)L.rows * kMaxBricks, L.bricks));
 }
 
 BrickLaunch plain_launch(int64_t n, const BrickGeom& bg) {
@@ -1712,8 +1950,7 @@ BrickLaunch plain_launch(int64_t n, const BrickGeom& bg) {
 
 size_t brick_workspace_bytes(int64_t n, const BrickGeom& bg) {
     const BrickLaunch L = plain_launch(n, bg);
-    return (size_t)(kWorkTable + L.table_bytes + up256((uint64_t)L.rows * bg.nbricks * 4u) +
-                    up256((uint64_t)L.bricks * 4u) + up256(((uint64_t)L.bricks + 1u) * 4u) +
+    return (size_t)(kWorkTable + L.table_bytes + brick_data_bytes((uint64_t)L.rows * bg.nbricks, L.bricks) +
                     max_pieces(n, bg) * sizeof(Piece));
 }
 
@@ -1727,8 +1964,8 @@ static int device_cus() {
 
 // Persistent fill workgroups: wgs_per_cu per compute unit (0: for 64 KiB
 // bricks two, unless the launch has fewer bricks than two per CU, then one
-// of 1024 threads), and no more than the launch has bricks (a workgroup
-// without a brick would only take a CU slot).
+// of 1024 threads), and no more than the launch can have work items (a
+// workgroup without one would only take a CU slot).
 template <int LGX, int LGY, int LGZ>
 static hipError_t launch_fill(uint8_t* work, int wgs_per_cu, uint32_t max_bricks, hipStream_t stream) {
     const int cus = device_cus();
@@ -1736,7 +1973,7 @@ static hipError_t launch_fill(uint8_t* work, int wgs_per_cu, uint32_t max_bricks
     if constexpr (LGX + LGY + LGZ < 20)
         per = wgs_per_cu == 1 || wgs_per_cu == 2 ? wgs_per_cu : (max_bricks < 2u * (uint32_t)cus ? 1 : 2);
     int wgs = cus * per;
-    if ((uint32_t)wgs > max_bricks) wgs = (int)max_bricks;
+    if ((uint64_t)wgs > (uint64_t)max_bricks + kMaxExtraItems) wgs = (int)(max_bricks + kMaxExtraItems);
     if constexpr (LGX + LGY + LGZ < 20) {
         if (per == 2) {
             k_brick_fill<LGX, LGY, LGZ, 2><<<wgs, FillCfg<LGX, LGY, LGZ, 2>::kBlock, 0, stream>>>(work);
@@ -1807,6 +2044,11 @@ hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunc
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
+        KernelTimer t("brick_clear", stream);
+        k_brick_clear<<<2048, kDirectBlock, 0, stream>>>(work);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
         KernelTimer t("brick_scatter", stream);
         const size_t scatter_lds = (size_t)(L.n_scenes > 1 ? kMaxBricks : L.bricks) * sizeof(uint32_t);
         k_brick_scatter<<<L.rows, kHistBlock, scatter_lds, stream>>>(work);
@@ -1823,11 +2065,6 @@ hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunc
     }
     if (e != hipSuccess) return e;
     if (L.direct_kernels) {
-        {
-            KernelTimer t("batch_direct_clear", stream);
-            k_batch_direct_clear<<<2048, kDirectBlock, 0, stream>>>(work);
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
         KernelTimer t("batch_direct", stream);
         k_batch_direct<<<4096, kDirectBlock, 0, stream>>>(work);
         if ((e = hipGetLastError()) != hipSuccess) return e;

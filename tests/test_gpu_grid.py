@@ -267,3 +267,48 @@ def test_direct_brick_boundary(n):
     rng = np.random.default_rng(n)
     base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
     assert_grid(segs, dims, base=base)
+
+
+def dense_spot(dims, spot, n_spot, n_rest, seed):
+    """n_spot short segments (up to 6 voxels) inside the box [0, spot) and
+    n_rest random ones in the whole volume."""
+    rng = np.random.default_rng(seed)
+    p0 = np.stack([rng.integers(0, s, n_spot) for s in spot], 1)
+    p1 = np.clip(p0 + rng.integers(-6, 7, (n_spot, 3)), 0, np.array(spot) - 1)
+    return np.concatenate([np.concatenate([p0, p1], 1).astype(np.int32), random_in(dims, n_rest, seed + 1)])
+
+
+@pytest.mark.parametrize("euclid", [False, True])
+def test_dense_brick_cut_into_items(euclid):
+    """A brick holding far more than a workgroup's share of the records
+    (100 000 short segments in one 256x64x32 brick of a 512x256x128 volume)
+    is cut into several work items of the fill, each ORing its part into the
+    volume with device atomics, after the clear kernel zeroed the brick in a
+    cleared volume: the oracle's volume, cleared and ORed into a volume,
+    through the compact workspace and the worst-case one."""
+    torch = pytest.importorskip("torch")
+    dims = (512, 256, 128)
+    segs = dense_spot(dims, (256, 64, 32), 100_000, 20_000, 77)
+    n = len(segs)
+    flags = binding.VOX_GRID_EUCLID if euclid else 0
+    grid_fn = oracle.grid_euclid if euclid else oracle.grid
+    rng = np.random.default_rng(78)
+    base = rng.integers(0, 2**32, size=binding.grid_words(dims), dtype=np.uint32)
+    base &= rng.integers(0, 2**32, size=base.size, dtype=np.uint32)
+    for work_bytes in (binding.vox_workspace_bytes(binding.VOX_OP_GRID, n, 1),
+                       binding.vox_grid_workspace_bytes(n, dims)):
+        work = binding.workspace(work_bytes, dev())
+        for clear in (True, False):
+            g = to_dev(base.view(np.int32))
+            binding.vox_segments_to_grid(to_dev(segs), dims, g, None,
+                                         flags | (binding.VOX_GRID_CLEAR if clear else 0), work)
+            assert binding.vox_read_status(work) == binding.VOX_OK
+            # Header words 12 and 13 of the workspace (internal layout): the
+            # fill's work items and the bricks cut into several.
+            hdr = work[:64].cpu().view(torch.int32).numpy()
+            assert hdr[13] >= 1 and hdr[12] > hdr[13]
+            got = grid_host(g)
+            exp = grid_fn(segs, dims, base=None if clear else base)
+            if not np.array_equal(got, exp):
+                bad = np.flatnonzero(got != exp)
+                raise AssertionError("%d words differ, first %s" % (bad.size, bad[:5].tolist()))
