@@ -31,10 +31,11 @@
 //             records do not fit the workspace, the direct kernels take over;
 //             the fill's work items: one per brick, several for a brick with
 //             more than a fair share of the records
-//   clear     zeroes the volumes of the cleared direct scenes and, in
-//             cleared brick scenes, the bricks cut into several items
-//   scatter   the same walk again, writing one 16-byte piece record (start
-//             point, direction, k-window in the brick) into the brick's bin
+//   clear     (batches) zeroes the volumes of the cleared direct scenes
+//   scatter   zeroes the bricks cut into several items in cleared volumes,
+//             then the same walk again, writing one 16-byte piece record
+//             (start point, direction, k-window in the brick) into the
+//             brick's bin
 //   fill      persistent workgroups take work items from work-stealing
 //             queues, set the bits of every piece with LDS atomic OR and
 //             flush the brick to the volume (an item that holds part of a
@@ -118,8 +119,8 @@ static_assert(sizeof(Piece) == 16, "16-byte piece records");
 // So a brick with more than T records, T = max(kSplitMinRecords,
 // ceil(total / kSplitShares)), becomes ceil(records / T) items, each with
 // an even part of its records, set in LDS by its own workgroup and ORed
-// into the volume with device atomics (the clear kernel zeroes such a
-// brick first in a cleared volume).  Since every cut brick holds more than
+// into the volume with device atomics (the scatter zeroes such a brick
+// first in a cleared volume).  Since every cut brick holds more than
 // T records, the items beyond one per brick number at most
 // total / T <= kSplitShares, and so do the cut bricks.
 constexpr uint32_t kSplitShares = 1024;
@@ -928,8 +929,8 @@ __device__ __forceinline__ uint64_t scan_totals(const WorkView& wv, uint32_t NB,
 // brick of each item, staged in LDS (the totals' stage, free by then) and
 // written back coalesced; the counts in the header.  With a single chunk the
 // stage still holds the totals from scan_totals.  When no brick is cut the
-// items are the bricks (n_split = 0 tells the fill and the clear kernel so,
-// and the item arrays are not written).
+// items are the bricks (n_split = 0 tells the fill and the scatter so, and
+// the item arrays are not written).
 template <int kBlock>
 __device__ __forceinline__ void make_items(const WorkView& wv, uint32_t NB, uint64_t total, uint64_t* lds,
                                            uint32_t* st, uint32_t* ob, uint32_t* n_split_s) {
@@ -1128,13 +1129,47 @@ __device__ __forceinline__ Piece piece_record_euclid(const StagedSeg& g, uint32_
     return pc;
 }
 
+// In cleared brick scenes, zeroes the bricks cut into several work items
+// (their items OR into the volume), one workgroup a brick, before the fill.
+__device__ __forceinline__ void zero_cut_bricks(const TableView& tv, const WorkView& wv) {
+    const uint32_t ns = *wv.n_split;
+    for (uint32_t j = blockIdx.x; j < ns; j += gridDim.x) {
+        const uint32_t gb = wv.split[j];
+        const BrickScene& sc = tv.scenes[tv.brick_scene ? tv.brick_scene[gb] : 0u];
+        if (!(sc.flags & kSceneClear)) continue;
+        const BrickGeom& bg = sc.bg;
+        const uint32_t lb = gb - sc.brick_base;
+        const int32_t org[3] = {(int32_t)(lb % (uint32_t)bg.nb[0]) << bg.lg[0],
+                                (int32_t)((lb / (uint32_t)bg.nb[0]) % (uint32_t)bg.nb[1]) << bg.lg[1],
+                                (int32_t)(lb / ((uint32_t)bg.nb[0] * (uint32_t)bg.nb[1])) << bg.lg[2]};
+        int32_t ext[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int32_t e = bg.dim[ax] - org[ax];
+            ext[ax] = e < (1 << bg.lg[ax]) ? e : (1 << bg.lg[ax]);
+        }
+        // A brick has at most 2^20 bits: 32-bit index arithmetic.
+        const uint32_t xws = (uint32_t)ext[0] >> 5, ey = (uint32_t)ext[1];
+        const uint32_t words = xws * ey * (uint32_t)ext[2];
+        const int64_t row_words = (int64_t)bg.dim[0] >> 5;
+        for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) {
+            const uint32_t xw = t % xws, r = t / xws;
+            const uint32_t y = r % ey, z = r / ey;
+            sc.grid[((int64_t)(org[2] + (int32_t)z) * bg.dim[1] + (org[1] + (int32_t)y)) * row_words +
+                    (org[0] >> 5) + xw] = 0u;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kHistBlock) void k_brick_scatter(uint8_t* __restrict__ work) {
     extern __shared__ uint32_t cur[];
     __shared__ Stage<kStage> st;
     const TableView tv = table_view(work + kWorkTable);
     const WorkView wv = work_of(work, tv);
     const uint32_t r = xcd_row(blockIdx.x, gridDim.x);
-    if (*wv.ok == 0 || *wv.direct_all != 0 || r >= tv.h.rows) return;
+    if (*wv.ok == 0 || *wv.direct_all != 0) return;
+    zero_cut_bricks(tv, wv);
+    if (r >= tv.h.rows) return;
     const BrickScene sc = tv.scenes[tv.row_scene ? tv.row_scene[r] : 0u];
     const BrickGeom& bg = sc.bg;
     const uint32_t NB = bg.nbricks;
@@ -1687,8 +1722,8 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         // ORs into its volume changes nothing: no flush (its LDS copy is
         // still zero).  An item holding part of a cut brick ORs its nonzero
         // words into the volume with device atomics (the other items of the
-        // brick do the same; the clear kernel zeroed the brick first in a
-        // cleared volume).
+        // brick do the same; the scatter zeroed the brick first in a cleared
+        // volume).
         const int rows = (clear || p_lo != p_hi) ? ext[1] * ext[2] : 0;
         // Whole 16-byte units when the volume's rows hold whole brick rows.
         const bool vec = Shape::kBXw % 4 == 0 && (bg.dim[0] & ((1 << LGX) - 1)) == 0;
@@ -1796,44 +1831,12 @@ __device__ __forceinline__ bool direct_scenes(const uint8_t* work, const TableVi
     return count > 0;
 }
 
-// Before the fill: zeroes, in cleared brick scenes, the bricks cut into
-// several work items (their items OR into the volume), and the volumes of
-// the cleared direct scenes.
-__global__ __launch_bounds__(kDirectBlock) void k_brick_clear(uint8_t* __restrict__ work) {
+// Zeroes the volumes of the cleared direct scenes (before the fill; the
+// direct kernel sets their bits after it).
+__global__ __launch_bounds__(kDirectBlock) void k_batch_direct_clear(uint8_t* __restrict__ work) {
     const TableView tv = table_view(work + kWorkTable);
     const int64_t t0 = (int64_t)blockIdx.x * kDirectBlock + threadIdx.x;
     const int64_t ts = (int64_t)gridDim.x * kDirectBlock;
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(work);
-    if (w[kWOk] != 0u && w[kWDirectAll] == 0u) {
-        const WorkView wv = work_of(work, tv);
-        const uint32_t ns = *wv.n_split;
-        for (uint32_t j = blockIdx.x; j < ns; j += gridDim.x) {  // a workgroup a brick
-            const uint32_t gb = wv.split[j];
-            const BrickScene& sc = tv.scenes[tv.brick_scene ? tv.brick_scene[gb] : 0u];
-            if (!(sc.flags & kSceneClear)) continue;
-            const BrickGeom& bg = sc.bg;
-            const uint32_t lb = gb - sc.brick_base;
-            const int32_t org[3] = {(int32_t)(lb % (uint32_t)bg.nb[0]) << bg.lg[0],
-                                    (int32_t)((lb / (uint32_t)bg.nb[0]) % (uint32_t)bg.nb[1]) << bg.lg[1],
-                                    (int32_t)(lb / ((uint32_t)bg.nb[0] * (uint32_t)bg.nb[1])) << bg.lg[2]};
-            int32_t ext[3];
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                const int32_t e = bg.dim[ax] - org[ax];
-                ext[ax] = e < (1 << bg.lg[ax]) ? e : (1 << bg.lg[ax]);
-            }
-            // A brick has at most 2^20 bits: 32-bit index arithmetic.
-            const uint32_t xws = (uint32_t)ext[0] >> 5, ey = (uint32_t)ext[1];
-            const uint32_t words = xws * ey * (uint32_t)ext[2];
-            const int64_t row_words = (int64_t)bg.dim[0] >> 5;
-            for (uint32_t t = threadIdx.x; t < words; t += kDirectBlock) {
-                const uint32_t xw = t % xws, r = t / xws;
-                const uint32_t y = r % ey, z = r / ey;
-                sc.grid[((int64_t)(org[2] + (int32_t)z) * bg.dim[1] + (org[1] + (int32_t)y)) * row_words +
-                        (org[0] >> 5) + xw] = 0u;
-            }
-        }
-    }
     uint32_t nd;
     bool all;
     if (!direct_scenes(work, tv, nd, all)) return;
@@ -2043,9 +2046,9 @@ hipError_t launch_bricks(const void* d_scenes, const void* one, const BrickLaunc
         k_brick_base<<<1, kBaseBlock, 0, stream>>>(work, (uint64_t)work_bytes);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    {
-        KernelTimer t("brick_clear", stream);
-        k_brick_clear<<<2048, kDirectBlock, 0, stream>>>(work);
+    if (L.direct_kernels) {
+        KernelTimer t("batch_direct_clear", stream);
+        k_batch_direct_clear<<<2048, kDirectBlock, 0, stream>>>(work);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     {
