@@ -112,38 +112,15 @@ static_assert(sizeof(Piece) == 16, "16-byte piece records");
 // brick totals, the bin offsets, the fill's work items and the piece records
 // (the rest of the workspace).
 //
-// Work items of the fill.  A brick's records are the work of one workgroup,
-// and a brick can hold far more than a workgroup's fair share of a launch
-// (a small dense volume in a batch is a single brick of millions of
-// voxels), which would leave one workgroup running long after the others.
-// So a brick with more than T records, T = max(kSplitMinRecords,
-// ceil(total / kSplitShares)), becomes ceil(records / T) items, each with
-// an even part of its records, set in LDS by its own workgroup and ORed
-// into the volume with device atomics (the scatter zeroes such a brick
-// first in a cleared volume).  Since every cut brick holds more than
-// T records, the items beyond one per brick number at most
-// total / T <= kSplitShares, and so do the cut bricks.
-constexpr uint32_t kSplitShares = 1024;
-constexpr uint32_t kSplitMinRecords = 4096;
-constexpr uint32_t kMaxExtraItems = kSplitShares;
-
-__host__ __device__ inline uint64_t split_threshold(uint64_t total) {
-    const uint64_t t = total / kSplitShares + (total % kSplitShares != 0u ? 1u : 0u);
-    return t > kSplitMinRecords ? t : kSplitMinRecords;
-}
-__host__ __device__ inline uint32_t brick_items(uint32_t records, uint64_t T) {
-    if (records <= T) return 1u;               // every brick when T >= 2^32
-    return (records - 1u) / (uint32_t)T + 1u;  // ceil(records / T), T < records < 2^32
-}
-
 // Bytes from the table's data_off to the piece records.
 __host__ __device__ inline uint64_t brick_data_bytes(uint64_t hist_words, uint64_t bricks) {
     return up256(hist_words * 4u) + up256(bricks * 4u) + 2u * up256((bricks + 1u) * 4u) +
            up256((bricks + kMaxExtraItems) * 4u) + up256((uint64_t)kMaxExtraItems * 4u);
 }
+
 struct WorkView {
     int32_t* status;
-    uint32_t* counter;   // [kXcds] brick queues of the fill, one per XCD
+    uint32_t* counter;   // [kXcds] work queues of the fill, one per XCD
     uint32_t* ok;
     uint32_t* direct_all;
     uint64_t* pieces;
@@ -273,10 +250,9 @@ __device__ __forceinline__ ItemClaim claim_item(const WorkView& wv, uint32_t xcd
     }
     const uint32_t b = wv.item_brick[i];
     const uint32_t i0 = wv.item_base[b], k = wv.item_base[b + 1] - i0, j = i - i0;
-    const uint32_t lo = wv.bin_base[b], cnt = wv.bin_base[b + 1] - lo;
+    const uint32_t lo = wv.bin_base[b];
     c.brick = b;
-    c.lo = lo + (uint32_t)((uint64_t)cnt * j / k);
-    c.hi = lo + (uint32_t)((uint64_t)cnt * (j + 1u) / k);
+    item_range(lo, wv.bin_base[b + 1] - lo, j, k, c.lo, c.hi);
     c.split = k > 1u ? 1u : 0u;
     return c;
 }

@@ -304,6 +304,37 @@ __host__ __device__ inline bool brick_geometry(int32_t dx, int32_t dy, int32_t d
 }
 
 
+// Work items of the fill.  A brick's records are the work of one workgroup,
+// and a brick can hold far more than a workgroup's fair share of a launch
+// (a small dense volume in a batch is a single brick of millions of
+// voxels), which would leave one workgroup running long after the others.
+// So a brick with more than T records, T = max(kSplitMinRecords,
+// ceil(total / kSplitShares)), becomes ceil(records / T) items, each with
+// an even part of its records, set in LDS by its own workgroup and ORed
+// into the volume with device atomics (the scatter zeroes such a brick
+// first in a cleared volume).  Since every cut brick holds more than
+// T records, the items beyond one per brick number at most
+// total / T <= kSplitShares, and so do the cut bricks.
+constexpr uint32_t kSplitShares = 1024;
+constexpr uint32_t kSplitMinRecords = 4096;
+constexpr uint32_t kMaxExtraItems = kSplitShares;
+
+__host__ __device__ inline uint64_t split_threshold(uint64_t total) {
+    const uint64_t t = total / kSplitShares + (total % kSplitShares != 0u ? 1u : 0u);
+    return t > kSplitMinRecords ? t : kSplitMinRecords;
+}
+__host__ __device__ inline uint32_t brick_items(uint32_t records, uint64_t T) {
+    if (records <= T) return 1u;               // every brick when T >= 2^32
+    return (records - 1u) / (uint32_t)T + 1u;  // ceil(records / T), T < records < 2^32
+}
+// Records [lo, hi) of item j of the k items of a brick whose records are
+// [first, first + count).
+__host__ __device__ inline void item_range(uint32_t first, uint32_t count, uint32_t j, uint32_t k, uint32_t& lo,
+                                           uint32_t& hi) {
+    lo = first + (uint32_t)((uint64_t)count * j / k);
+    hi = first + (uint32_t)((uint64_t)count * (j + 1u) / k);
+}
+
 // The argument rules of a bit-volume scene (those of vox_segments_to_grid):
 // n in [0, 2^31 - 2], segs non-null when n > 0 and 4-byte aligned, each side
 // in [1, 2^20] with at most 2^38 voxels, grid non-null and 16-byte aligned,

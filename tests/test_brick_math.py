@@ -160,3 +160,21 @@ def test_parts_long_walks(driver):
     got = run(driver, segs, dims, lg)
     assert got == expected(segs, dims, lg)
     run(driver, segs, dims, lg, euclid=True)       # parts == whole, windows == box windows
+
+
+def test_work_items():
+    """The fill's work items (a brick of more than T records cut into parts):
+    bounded extra items and cut bricks, exact tiling of each brick's records
+    (tests/cpp/items_check.cpp, the library's own header built for the host)."""
+    import tempfile
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "items_check")
+        subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17",
+                               "-I", os.path.join(ROOT, "include"),
+                               "-I", os.path.join(ROOT, "paper_2009_09500_amd", "csrc"),
+                               "-o", exe, os.path.join(ROOT, "tests", "cpp", "items_check.cpp")])
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
