@@ -275,3 +275,51 @@ def test_graph_capture_and_replay():
         torch.cuda.synchronize()
         assert binding.vox_read_status(work) == binding.VOX_OK
         b.check()
+
+
+def test_dense_scenes_cut_into_items():
+    """Single-brick scenes far denser than the rest of the batch (60 000 and
+    80 000 segments in 64^3, each one brick; the threshold is about 4 096
+    records) are cut into several work items of the fill: one ORed into a
+    volume, one with the Euclidean N, one cleared, beside ordinary scenes;
+    every volume and count equals the oracle's, also on a second launch of
+    the same batch and in a HIP-graph replay."""
+    import torch
+    rng = np.random.default_rng(41)
+    base = rng.integers(0, 2**32, size=binding.grid_words((64, 64, 64)), dtype=np.uint32)
+    base &= rng.integers(0, 2**32, size=base.size, dtype=np.uint32)
+    specs = [
+        (random_in((64, 64, 64), 60000, 42), (64, 64, 64), 0, base, True),
+        (random_in((64, 64, 64), 30000, 43), (64, 64, 64), binding.VOX_GRID_CLEAR | binding.VOX_GRID_EUCLID,
+         None, True),
+        (random_in((64, 64, 64), 80000, 44), (64, 64, 64), binding.VOX_GRID_CLEAR, None, False),
+        (random_in((256, 128, 128), 20000, 45), (256, 128, 128), binding.VOX_GRID_CLEAR, None, True),
+        (random_in((96, 40, 20), 500, 46), (96, 40, 20), binding.VOX_GRID_CLEAR, None, False),
+    ]
+    b = Batch(specs)
+    status, work = run_batch(b)
+    assert status == binding.VOX_OK
+    # Header words 12 and 13 of the workspace (internal layout): the fill's
+    # work items and the bricks cut into several.
+    hdr = work[:64].cpu().view(torch.int32).numpy()
+    assert hdr[13] >= 3 and hdr[12] > hdr[13]
+    b.check()
+    b.reset()
+    status, _ = run_batch(b, work=work)
+    assert status == binding.VOX_OK
+    b.check()
+    # Graph capture and replays of the same launch.
+    stream = torch.cuda.Stream(device=dev())
+    d_scenes = b.d_scenes()
+    total = b.total()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        binding.vox_batch_scenes(d_scenes, len(specs), total, work, stream=stream)
+    for _ in range(3):
+        b.reset()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert binding.vox_read_status(work) == binding.VOX_OK
+        b.check()
