@@ -323,3 +323,29 @@ def test_dense_scenes_cut_into_items():
         torch.cuda.synchronize()
         assert binding.vox_read_status(work) == binding.VOX_OK
         b.check()
+
+
+def test_more_bricks_than_one_base_chunk():
+    """A batch of 17 408 bricks (34 volumes of 1024x1024x256 in 128x64x64
+    bricks), more than the 16 384 the base kernel stages at a time, so the
+    brick totals, bin offsets and work items are made in two chunks; one
+    volume holds a dense brick that is cut into several items.  Every volume
+    against the oracle."""
+    rng = np.random.default_rng(51)
+    dims = (1024, 1024, 256)
+    specs = []
+    for i in range(34):
+        segs = random_in(dims, 2000, 500 + i)
+        if i == 20:
+            p0 = np.stack([rng.integers(0, 128, 30000), rng.integers(0, 64, 30000),
+                           rng.integers(0, 64, 30000)], 1)
+            p1 = np.clip(p0 + rng.integers(-4, 5, (30000, 3)), 0, [127, 63, 63])
+            segs = np.concatenate([segs, np.concatenate([p0, p1], 1).astype(np.int32)])
+        specs.append((segs, dims, binding.VOX_GRID_CLEAR, None, i % 5 == 0))
+    b = Batch(specs)
+    status, work = run_batch(b, tuning=binding.make_tuning(brick_lg=(7, 6, 6)))
+    assert status == binding.VOX_OK
+    import torch
+    hdr = work[:64].cpu().view(torch.int32).numpy()
+    assert hdr[13] >= 1 and hdr[12] > 17408          # cut bricks; items beyond one a brick
+    b.check()
