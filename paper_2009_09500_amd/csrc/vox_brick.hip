@@ -20,7 +20,7 @@
 // Pipeline (one stream, no host synchronisation, no allocation):
 //   plan      checks every scene, decides brick or direct kernels per scene,
 //             numbers rows and bricks (block scans), writes the table, the
-//             status word and the brick queues
+//             status word and the fill's work queues
 //   expand    scene of each histogram row and brick (several scenes only)
 //   hist      per segment: count N+1, range check, walk its bricks and count
 //             pieces per brick in an LDS histogram; one histogram row per
@@ -270,7 +270,7 @@ __device__ __forceinline__ uint32_t xcd_row(uint32_t w, uint32_t G) {
 
 constexpr int kPlanBlock = 1024;
 
-// The table header, status word, flags and brick queues of a launch whose
+// The table header, status word, flags and work queues of a launch whose
 // scenes have been numbered (one lane).
 __device__ __forceinline__ void write_table(uint8_t* work, const BrickLaunch& L, uint64_t work_bytes, uint32_t rows_c,
                                             uint32_t bricks_c, uint32_t direct_c, uint32_t max_nb, uint64_t hist_c,
@@ -1576,15 +1576,16 @@ __device__ __forceinline__ void fill_records(uint32_t* brick, uint16_t* my_ent, 
 }
 
 
-// Persistent fill.  Workgroups take bricks from the brick queues (work
-// stealing: bricks differ a lot in work).  Inside a brick the waves work
-// independently, with no workgroup barrier until the brick is done: a wave
-// takes the next 128 piece records of its SIMD's quarter of the brick (two
-// per lane), turns them into digests, cuts the pieces into chunks of at most
-// kChunk voxels, lists the chunks in its own LDS table (full chunks first)
-// and runs them in rounds of 64, one chunk per lane, reading each chunk's
-// digest from the owning lane with ds_bpermute.  The next 128 records are
-// loaded while the current ones run.
+// Persistent fill.  Workgroups take work items (a brick, or part of a cut
+// brick) from the work queues (work stealing: bricks differ a lot in work).
+// Inside an item the waves work independently, with no workgroup barrier
+// until the item is done: a wave takes the next 128 piece records of its
+// SIMD's quarter of the item's records (two per lane), turns them into
+// digests, cuts the pieces into chunks of at most kChunk voxels, lists the
+// chunks in its own LDS table (full chunks first) and runs them in rounds of
+// 64, one chunk per lane, reading each chunk's digest from the owning lane
+// with ds_bpermute.  The next 128 records are loaded while the current ones
+// run.
 template <int LGX, int LGY, int LGZ, int kWgs>
 __global__ __launch_bounds__((FillCfg<LGX, LGY, LGZ, kWgs>::kBlock), kWgs)
 void k_brick_fill(uint8_t* __restrict__ work) {
@@ -1686,7 +1687,7 @@ void k_brick_fill(uint8_t* __restrict__ work) {
         }
         lds_barrier();  // every wave done with this item
         const uint32_t b_next = next_s[0], lo_next = next_s[1], hi_next = next_s[2], split_next = next_s[3];
-        // The next brick's first group is loaded before the flush's stores:
+        // The next item's first group is loaded before the flush's stores:
         // a wait for a load also waits for every store issued before it, so
         // loaded after the flush its records would arrive only once the
         // whole brick had been written.
@@ -1736,7 +1737,7 @@ void k_brick_fill(uint8_t* __restrict__ work) {
             const int64_t dst_step = (int64_t)kSlabsPerStep * bg.dim[1] * row_words / 4;  // in 16-byte units
             for (int t = threadIdx.x; t < units; t += kBlock) {
                 const u32x4 v = *src;
-                *src = (u32x4){0u, 0u, 0u, 0u};  // zero for the next brick
+                *src = (u32x4){0u, 0u, 0u, 0u};  // zero for the next item
                 if (clear) {
                     *dst = v;
                 } else {
@@ -1755,7 +1756,7 @@ void k_brick_fill(uint8_t* __restrict__ work) {
                 u32x4* src = reinterpret_cast<u32x4*>(
                     &brick[(((uint32_t)z << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + 4u * part]);
                 const u32x4 v = *src;
-                *src = (u32x4){0u, 0u, 0u, 0u};  // zero for the next brick
+                *src = (u32x4){0u, 0u, 0u, 0u};  // zero for the next item
                 global_u32x4* dst = (global_u32x4*)(
                     grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words + (org[0] >> 5) +
                     4 * part);
@@ -1773,7 +1774,7 @@ void k_brick_fill(uint8_t* __restrict__ work) {
                 const int y = r % ext[1], z = r / ext[1];
                 uint32_t* src = &brick[(((uint32_t)z << LGY) | (uint32_t)y) * (uint32_t)Shape::kBXw + xw];
                 const uint32_t v = *src;
-                *src = 0u;  // zero for the next brick
+                *src = 0u;  // zero for the next item
                 global_u32* dst = (global_u32*)grid + ((int64_t)(org[2] + z) * bg.dim[1] + (org[1] + y)) * row_words +
                                 (org[0] >> 5) + xw;
                 if (clear) *dst = v;

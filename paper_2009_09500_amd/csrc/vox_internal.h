@@ -158,7 +158,7 @@ static_assert(sizeof(BrickTable) <= kTableScenes, "table header fits its slot");
 constexpr int kWStatus = 0;    // status bits (kStatus*)
 constexpr int kWOk = 2;        // 1 when the brick kernels may run
 constexpr int kWDirectAll = 3; // 1: the direct kernels serve every scene (records do not fit)
-constexpr int kWQueues = 4;    // 8 brick queues of the fill
+constexpr int kWQueues = 4;    // 8 work queues of the fill
 constexpr int kWItems = 12;    // the fill's work items (k_brick_base)
 constexpr int kWSplit = 13;    // bricks cut into several work items (k_brick_base)
 constexpr int kWPieces = 16;   // uint64: piece records the call needed (information)
