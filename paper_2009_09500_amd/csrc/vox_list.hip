@@ -260,30 +260,43 @@ __global__ __launch_bounds__(kCountBlock) void k_list_tiles(const int64_t* __res
 // ------------------------------------------------------------ voxel tiles
 
 // One tile = kListTile consecutive output voxels [j0, j1).  Its segments
-// s0..s1 are staged in LDS, at most kWinSegs at a time, as packed end points
-// with their offsets relative to j0; lane t computes voxels j0 + t*P ..
-// j0 + t*P + P - 1 (P = kListPerThread), stepping exactly from one voxel to
-// the next and moving to the following segment when the voxel index reaches
-// its offset.  A tile with more segments than a window holds (segments
-// shorter than kListTile / kWinSegs voxels on average) is done in several
-// windows, each lane computing the voxels of its P that fall in the window;
-// LDS sized for the usual case keeps many blocks on a CU.
-template <typename T>
-struct PackedSeg {
-    T p0[3];
-    T p1[3];
+// s0..s1 are staged in LDS, at most kWinSegs at a time, each as its
+// stepping state at k = 0 (SegStart) with its offset relative to j0; lane t
+// computes voxels j0 + t*P .. j0 + t*P + P - 1 (P = kListPerThread),
+// stepping exactly from one voxel to the next and loading the following
+// segment's state when the voxel index reaches its offset.  A tile with
+// more segments than a window holds (segments shorter than kListTile /
+// kWinSegs voxels on average) is done in several windows, each lane
+// computing the voxels of its P that fall in the window; LDS sized for the
+// usual case keeps many blocks on a CU.
+//
+// The stepping of eq. (3) per axis, for direction sign m (0 or all ones)
+// and r = (2 k a + N - neg) mod 2N: the coordinate is kept as c' = c ^ m,
+// which grows by one on every carry whichever the sign (for m = all ones,
+// c' = -c - 1), and the remainder as f = r - 2N (mod 2^32), so that
+// f + 2a carries out of 32 bits exactly when r + 2a >= 2N: one add with
+// carry, one add of the carry to c', one conditional subtract of 2N.
+struct SegStart {
+    uint32_t c[3];     // p0 ^ m per axis
+    uint32_t f[3];     // r(0) - 2N = N - neg - 2N (0 for a point)
+    uint32_t ta[3];    // 2 |d_a|
+    uint32_t two_n;    // 2N
+    uint32_t neg;      // sign bits of d, axis a at bit a
+    uint32_t pad;
 };
 constexpr int kWinSegs = 256;
 
 // T = int16_t: coordinates in int16 (differences below 2^16); T = int32_t:
-// every axis difference below 2^30 (checked by the count kernel).
+// every axis difference below 2^30 (checked by the count kernel).  The int16
+// kernel is held to 64 VGPRs (eight waves a SIMD, which its 13 KiB of LDS
+// allows); the int32 kernel's 25 KiB of LDS allows six blocks a CU anyway.
 template <bool kAligned8, typename T>
-__global__ __launch_bounds__(kListBlock) void k_list_voxels(
+__global__ __launch_bounds__(kListBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 2 ? 8 : 1)))
+void k_list_voxels(
     const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
     const int32_t* __restrict__ tile_seg, T* __restrict__ voxels,
     const int64_t* __restrict__ total_p, const int32_t* __restrict__ status) {
-    using PSeg = PackedSeg<T>;
-    constexpr int kSegWords = (int)(kWinSegs * sizeof(PSeg) / 4);
+    constexpr int kSegWords = (int)(kWinSegs * sizeof(SegStart) / 4);
     constexpr int kVoxBytes = 3 * (int)sizeof(T);
     constexpr int kLaneWords = kListPerThread * kVoxBytes / 4;  // a lane's staged voxels
     constexpr int kStageWords = (int)kListTile * kVoxBytes / 4;
@@ -292,9 +305,9 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     // 25 KiB for int32 lists.
     __shared__ __align__(16) uint32_t lds_raw[kSegWords > kStageWords ? kSegWords : kStageWords];
     __shared__ int32_t srel[kWinSegs + 1];
-    PSeg* sseg = reinterpret_cast<PSeg*>(lds_raw);
+    SegStart* sseg = reinterpret_cast<SegStart*>(lds_raw);
     uint32_t* stage = lds_raw;
-    static_assert((kWinSegs * sizeof(PSeg)) % 4 == 0 && (kListPerThread * kVoxBytes) % 4 == 0, "packing");
+    static_assert(sizeof(SegStart) % 16 == 0 && (kListPerThread * kVoxBytes) % 4 == 0, "packing");
 
     if (*status != 0) return;
     const int64_t total = *total_p;
@@ -314,17 +327,32 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
     // segment w + i relative to j0 (srel[m]: of the segment after the window,
     // or the total), so the window's voxels are [srel[0], srel[m]).  Almost
     // every tile is one window (kOne: every voxel of the lane's P lies in it).
-    auto run_window = [&](int w, int m, auto one) {
+    auto run_window = [&](int w, int m, auto one, auto full) {
         constexpr bool kOne = decltype(one)::value;
+        constexpr bool kFull = decltype(full)::value;  // a tile of kListTile voxels, one window
         for (int i = threadIdx.x; i < m; i += kListBlock) {
-            Seg g = load_seg<kAligned8>(segs, (int64_t)s0 + w + i);
-            PSeg p;
+            const Seg g = load_seg<kAligned8>(segs, (int64_t)s0 + w + i);
+            SegStart st;
+            uint32_t N = 0, neg[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                p.p0[a] = (T)g.p0[a];
-                p.p1[a] = (T)g.p1[a];
+            for (int ax = 0; ax < 3; ++ax) {
+                // (int32 end points: the difference is formed without
+                // overflow and is below 2^30 in magnitude.)
+                const uint32_t d = (uint32_t)g.p1[ax] - (uint32_t)g.p0[ax];
+                neg[ax] = (int32_t)d < 0 ? 1u : 0u;
+                const uint32_t a = (int32_t)d < 0 ? 0u - d : d;
+                st.ta[ax] = 2u * a;
+                N = a > N ? a : N;
             }
-            sseg[i] = p;
+            st.two_n = 2u * N;
+            st.neg = neg[0] | (neg[1] << 1) | (neg[2] << 2);
+            st.pad = 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                st.c[ax] = (uint32_t)g.p0[ax] ^ (0u - neg[ax]);
+                st.f[ax] = N ? (N - neg[ax]) - 2u * N : 0u;
+            }
+            sseg[i] = st;
         }
         for (int i = threadIdx.x; i <= m; i += kListBlock) {
             const int64_t si = (int64_t)s0 + w + i;
@@ -337,7 +365,7 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
         __syncthreads();
 
         // This lane's voxels inside the window: [lo, hi).
-        int lo = first, hi = first + kListPerThread < count ? first + kListPerThread : count;
+        int lo = first, hi = kFull ? first + kListPerThread : (first + kListPerThread < count ? first + kListPerThread : count);
         if constexpr (!kOne) {
             const int wlo = srel[0], whi = srel[m];
             lo = first > wlo ? first : wlo;
@@ -352,27 +380,27 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
         }
         int s = a_;
         int next = srel[s + 1];
-        PSeg p = sseg[s];
-        uint32_t neg[3], a[3];
-        uint32_t N = 0;
+        SegStart st = sseg[s];
+        uint32_t mk[3];
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            // (int32 end points: the difference is formed without overflow
-            // and is below 2^30 in magnitude.)
-            const uint32_t d = (uint32_t)p.p1[ax] - (uint32_t)p.p0[ax];
-            neg[ax] = (int32_t)d < 0;
-            a[ax] = (int32_t)d < 0 ? 0u - d : d;
-            N = a[ax] > N ? a[ax] : N;
-        }
-        uint32_t k = (uint32_t)(lo - srel[s]);
-        AxisStep st[3];
-        if (N == 0) {
+        for (int ax = 0; ax < 3; ++ax) mk[ax] = 0u - ((st.neg >> ax) & 1u);
+        const uint32_t k = (uint32_t)(lo - srel[s]);
+        if (k != 0u) {
+            // Voxel k of the segment (k <= N, so N >= 1): c' = c'(0) + q.
+            uint32_t a[3], neg[3];
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) st[ax] = AxisStep{0u, 0u, 0u};
-        } else {
-            axis_init3(a, neg, N, k, st);
+            for (int ax = 0; ax < 3; ++ax) {
+                a[ax] = st.ta[ax] >> 1;
+                neg[ax] = (st.neg >> ax) & 1u;
+            }
+            AxisStep as[3];
+            axis_init3(a, neg, st.two_n >> 1, k, as);
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                st.c[ax] += as[ax].q;
+                st.f[ax] = as[ax].r - st.two_n;
+            }
         }
-        uint32_t two_n = 2u * N;
 #pragma unroll
         for (int v = 0; v < kListPerThread; ++v) {
             const int j = first + v;
@@ -381,40 +409,32 @@ __global__ __launch_bounds__(kListBlock) void k_list_voxels(
             // lo, and every segment has at least one voxel.)
             if (j > lo && j >= next) {
                 // First voxel of the following segment (inside the window, as
-                // j < hi <= srel[m]): k = 0.
+                // j < hi <= srel[m]): its state at k = 0.
                 ++s;
                 next = srel[s + 1];
-                p = sseg[s];
-                N = 0;
+                st = sseg[s];
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const uint32_t d = (uint32_t)p.p1[ax] - (uint32_t)p.p0[ax];
-                    neg[ax] = (int32_t)d < 0;
-                    a[ax] = (int32_t)d < 0 ? 0u - d : d;
-                    N = a[ax] > N ? a[ax] : N;
-                }
-                two_n = 2u * N;
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    st[ax].q = 0u;
-                    st[ax].r = N - (N ? neg[ax] : 0u);
-                    st[ax].two_a = 2u * a[ax];
-                }
+                for (int ax = 0; ax < 3; ++ax) mk[ax] = 0u - ((st.neg >> ax) & 1u);
             }
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                int32_t q = (int32_t)st[ax].q;
-                out[v * 3 + ax] = (T)((int32_t)p.p0[ax] + (neg[ax] ? -q : q));
-                axis_step(st[ax], two_n);
+                out[v * 3 + ax] = (T)(int32_t)(st.c[ax] ^ mk[ax]);
+                const uint32_t t = st.f[ax] + st.ta[ax];
+                const bool carry = t < st.ta[ax];
+                st.f[ax] = carry ? t - st.two_n : t;
+                st.c[ax] += carry ? 1u : 0u;
             }
         }
     };
-    if (nseg <= kWinSegs) {
-        run_window(0, nseg, std::integral_constant<bool, true>{});
+    if (nseg <= kWinSegs && count == (int)kListTile) {
+        run_window(0, nseg, std::integral_constant<bool, true>{}, std::integral_constant<bool, true>{});
+    } else if (nseg <= kWinSegs) {
+        run_window(0, nseg, std::integral_constant<bool, true>{}, std::integral_constant<bool, false>{});
     } else {
         for (int w = 0; w < nseg; w += kWinSegs) {
             if (w > 0) __syncthreads();  // the previous window is read
-            run_window(w, nseg - w < kWinSegs ? nseg - w : kWinSegs, std::integral_constant<bool, false>{});
+            run_window(w, nseg - w < kWinSegs ? nseg - w : kWinSegs, std::integral_constant<bool, false>{},
+                       std::integral_constant<bool, false>{});
         }
     }
     __syncthreads();  // the staged segments are dead from here
