@@ -20,34 +20,77 @@ namespace vox {
 
 // ------------------------------------------------------------------ count
 
-// Voxels of an int16-range segment under the Euclidean N of eq. (1)
-// (consecutive duplicates removed): 1 + the steps k - 1 -> k, k = 1..N,
-// that carry on some axis (r_a += 2a; a carry when r_a reaches 2N, which is
-// exactly when that axis moves, since a <= N).  One thread walks the
-// segment; a wave's segments have similar lengths in the workloads here.
-__device__ __forceinline__ uint32_t euclid_count(const Seg& g) {
-    const uint32_t N = euclid_length(g);
-    const uint32_t two_n = 2u * N;
-    uint32_t two_a[3], r[3];
+// Voxels of each segment under the Euclidean N of eq. (1) (consecutive
+// duplicates removed): 1 + the steps k - 1 -> k, k = 1..N, that carry on
+// some axis (a carry of r_a + 2a past 2N is exactly a move of that axis,
+// since a <= N); 1 for a segment outside int16, which writes nothing.
+// kLanes lanes share a segment, lane l walking samples [l S, (l + 1) S),
+// S = ceil((N + 1) / kLanes), from one division at its first sample, and the
+// lanes' counts are summed; the host takes more lanes a segment when there
+// are fewer segments, so that a few long segments still spread over the
+// chip.  Per axis the walk keeps f = r - 2N, whose add of 2a carries out of
+// 32 bits exactly when r + 2a >= 2N.
+template <bool kAligned8, int kLanes>
+__global__ __launch_bounds__(kCountBlock) void k_euclid_counts(const int32_t* __restrict__ segs, int64_t n,
+                                                              uint32_t* __restrict__ counts) {
+    static_assert(kLanes >= 1 && kLanes <= kWave && (kWave % kLanes) == 0, "lanes a segment");
+    const uint32_t sub = threadIdx.x % kLanes;
+    const int64_t groups = (int64_t)gridDim.x * (kCountBlock / kLanes);
+    // (Every lane of a group takes the same segments, so a group's lanes are
+    // active together at the sum below.)
+    for (int64_t i = ((int64_t)blockIdx.x * kCountBlock + threadIdx.x) / kLanes; i < n; i += groups) {
+        const Seg g = load_seg<kAligned8>(segs, i);
+        uint32_t c = 0;
+        if (!in_int16(g)) {
+            c = sub == 0 ? 1u : 0u;
+        } else {
+            const uint32_t N = euclid_length(g);
+            const uint32_t S = (N + (uint32_t)kLanes) / (uint32_t)kLanes;
+            const uint32_t k0 = sub * S;
+            const uint32_t k1 = k0 + S < N + 1u ? k0 + S : N + 1u;
+            if (N == 0u) {
+                c = sub == 0 ? 1u : 0u;
+            } else if (k0 < k1) {
+                const uint32_t two_n = 2u * N;
+                uint32_t ta[3], f[3];
+                bool moved = k0 == 0u;
+                const float rcpd = rcp_down(two_n);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int32_t d = g.p1[ax] - g.p0[ax];
-        two_a[ax] = 2u * (uint32_t)(d < 0 ? -d : d);
-        r[ax] = N - (d < 0 ? 1u : 0u);
-    }
-    uint32_t c = 1;
-    for (uint32_t k = 1; k <= N; ++k) {
-        bool moved = false;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int32_t d = g.p1[ax] - g.p0[ax];
+                    const uint32_t neg = d < 0 ? 1u : 0u;
+                    ta[ax] = 2u * (uint32_t)(d < 0 ? -d : d);
+                    uint32_t r;
+                    if (kLanes == 1 || k0 == 0u) {
+                        r = N - neg;
+                    } else if (N <= 32767u) {
+                        // 2 k0 a + N < 2^31, 2N < 2^16, quotient <= a < 2^15.
+                        uint32_t q;
+                        divmod_down(2u * k0 * (ta[ax] >> 1) + N - neg, two_n, rcpd, q, r);
+                    } else {
+                        r = (uint32_t)(((uint64_t)k0 * ta[ax] + N - neg) % two_n);
+                    }
+                    moved |= r < ta[ax];
+                    f[ax] = r - two_n;
+                }
+                c = moved ? 1u : 0u;
+                for (uint32_t k = k0 + 1u; k < k1; ++k) {
+                    bool mv = false;
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const uint32_t t = r[ax] + two_a[ax];
-            const bool carry = t >= two_n;
-            r[ax] = carry ? t - two_n : t;
-            moved |= carry;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const uint32_t t = f[ax] + ta[ax];
+                        const bool carry = t < ta[ax];
+                        f[ax] = carry ? t - two_n : t;
+                        mv |= carry;
+                    }
+                    c += mv ? 1u : 0u;
+                }
+            }
         }
-        c += moved ? 1u : 0u;
+#pragma unroll
+        for (int o = kLanes / 2; o >= 1; o >>= 1) c += __shfl_xor(c, o, kLanes);
+        if (sub == 0) counts[i] = c;
     }
-    return c;
 }
 
 // Voxel counts per segment (N + 1, or with the Euclidean N of eq. (1) the
@@ -71,8 +114,7 @@ __global__ __launch_bounds__(kCountBlock) void k_list_count(const int32_t* __res
             const bool inr = kKind == kListI32 ? span_below_2p30(g) : in_int16(g);
             int64_t c;
             if constexpr (kKind == kListEuclid) {
-                // (An out-of-range segment writes nothing: no walk of it.)
-                c = inr ? (int64_t)euclid_count(g) : 1;
+                c = counts[i];  // from k_euclid_counts
             } else {
                 c = seg_length(g) + 1;
             }
@@ -185,7 +227,7 @@ __global__ __launch_bounds__(kCountBlock) void k_list_one_block(
             const bool inr = kKind == kListI32 ? span_below_2p30(g) : in_int16(g);
             int64_t v;
             if constexpr (kKind == kListEuclid) {
-                v = inr ? (int64_t)euclid_count(g) : 1;
+                v = counts[i];  // from k_euclid_counts
             } else {
                 v = seg_length(g) + 1;
             }
@@ -468,12 +510,83 @@ void k_list_voxels(
     for (int64_t c = tail0 / 2 + threadIdx.x; c < bytes / 2; c += kListBlock) dst16[c] = src16[c];
 }
 
+// The samples k, k + kSampleLanes, ... of one segment under the Euclidean N
+// as taken by one of its lanes, stepped as the tile kernel steps (per axis:
+// c' = coordinate ^ sign mask grows by dq + carry, f = r - 2N carries out of
+// 32 bits exactly when r + dr >= 2N).  A sample k >= 1 starts a new voxel
+// when some axis moved from k - 1 to k, that is when r_a(k) < 2a_a for some
+// a, i.e. f_a < 2a_a - 2N as signed values (|2N| < 2^31).
+struct ListSamples {
+    uint32_t c[3], f[3], h[3], dq[3], dr[3], mk[3];
+    uint32_t N, two_n;
+
+    // Sample k of segment g (length n); returns whether it starts a voxel.
+    __device__ __forceinline__ bool start(const Seg& g, uint32_t n, uint32_t k) {
+        N = n;
+        two_n = 2u * n;
+        uint32_t two_a[3], num0[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int32_t d = g.p1[ax] - g.p0[ax];
+            mk[ax] = d < 0 ? ~0u : 0u;
+            two_a[ax] = 2u * (uint32_t)(d < 0 ? -d : d);
+            num0[ax] = n - (d < 0 ? 1u : 0u);
+            h[ax] = two_a[ax] - two_n;
+        }
+        uint32_t q[3], r[3];
+        if (n == 0) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) q[ax] = r[ax] = dq[ax] = dr[ax] = 0;
+        } else if (n <= 32767u) {
+            const float rcpd = rcp_down(two_n);
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                divmod_down(__umul24(k, two_a[ax]) + num0[ax], two_n, rcpd, q[ax], r[ax]);
+                divmod_down(kSampleLanes * two_a[ax], two_n, rcpd, dq[ax], dr[ax]);
+            }
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const uint64_t num = (uint64_t)k * two_a[ax] + num0[ax];
+                q[ax] = (uint32_t)(num / two_n);
+                r[ax] = (uint32_t)(num - (uint64_t)q[ax] * two_n);
+                const uint32_t s = kSampleLanes * two_a[ax];
+                dq[ax] = s / two_n;
+                dr[ax] = s - dq[ax] * two_n;
+            }
+        }
+        bool moved = k == 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            c[ax] = ((uint32_t)g.p0[ax] ^ mk[ax]) + q[ax];
+            f[ax] = r[ax] - two_n;
+            moved |= (int32_t)f[ax] < (int32_t)h[ax];
+        }
+        return moved;
+    }
+
+    // Moves on by kSampleLanes samples; returns whether the sample starts a voxel.
+    __device__ __forceinline__ bool next() {
+        bool moved = false;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const uint32_t t = f[ax] + dr[ax];
+            const bool carry = t < dr[ax];
+            f[ax] = carry ? t - two_n : t;
+            c[ax] += dq[ax] + (carry ? 1u : 0u);
+            moved |= (int32_t)f[ax] < (int32_t)h[ax];
+        }
+        return moved;
+    }
+
+    __device__ __forceinline__ int32_t coord(int ax) const { return (int32_t)(c[ax] ^ mk[ax]); }
+};
+
 // Lists with the Euclidean N of eq. (1).  A wave takes four segments, 16
 // lanes each; a segment's lanes take its samples k = 0..N 16 at a time,
 // each stepping its own samples and deciding alone whether its sample starts
-// a new voxel (SampleAt); a
-// ballot of those decisions places the kept voxels, and consecutive lanes
-// write consecutive voxels.
+// a new voxel (ListSamples); a ballot of those decisions places the kept
+// voxels, and consecutive lanes write consecutive voxels.
 template <bool kAligned8>
 __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
     const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
@@ -491,9 +604,8 @@ __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
         const bool valid = i < n;
         Seg g = {};
         if (valid) g = load_seg<kAligned8>(segs, i);
-        SampleAt s;
-        s.init(g, euclid_length(g));
-        bool moved = s.start(sub);
+        ListSamples s;
+        bool moved = s.start(g, euclid_length(g), sub);
         int16_t* out = voxels + 3 * (valid ? offsets[i] : 0);
         for (uint32_t c0 = 0; __ballot(valid && c0 <= s.N) != 0; c0 += kSampleLanes) {
             if (c0 != 0) moved = s.next();
@@ -504,7 +616,7 @@ __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 int16_t* o = out + 3 * before;
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) o[ax] = (int16_t)s.coord(g, ax);
+                for (int ax = 0; ax < 3; ++ax) o[ax] = (int16_t)s.coord(ax);
             }
             out += 3 * __popcll(m);
         }
@@ -545,8 +657,34 @@ ListWork list_workspace(void* d_work, int64_t n, int64_t capacity) {
     return w;
 }
 
+template <int kLanes>
+static void euclid_counts(const int32_t* segs, int64_t n, bool aligned8, uint32_t* counts, hipStream_t stream) {
+    int64_t blocks = (n * kLanes + kCountBlock - 1) / kCountBlock;
+    if (blocks > 16384) blocks = 16384;
+    if (aligned8)
+        k_euclid_counts<true, kLanes><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, counts);
+    else
+        k_euclid_counts<false, kLanes><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, counts);
+}
+
+// Euclidean counts into w.counts (n >= 1): one lane a segment from 65 536
+// segments on (a thread per segment already fills the chip), more lanes a
+// segment below that.
+static void launch_euclid_counts(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
+                                 hipStream_t stream) {
+    if (n >= 65536)
+        euclid_counts<1>(segs, n, aligned8, w.counts, stream);
+    else if (n >= 16384)
+        euclid_counts<4>(segs, n, aligned8, w.counts, stream);
+    else if (n >= 4096)
+        euclid_counts<16>(segs, n, aligned8, w.counts, stream);
+    else
+        euclid_counts<64>(segs, n, aligned8, w.counts, stream);
+}
+
 template <int kKind>
 static void list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w, hipStream_t stream) {
+    if (kKind == kListEuclid && n > 0) launch_euclid_counts(segs, n, aligned8, w, stream);
     // n == 0: one block that writes a zero sum and no flag.
     dim3 grid(n == 0 ? 1u : (unsigned)w.nb);
     if (aligned8)
@@ -580,6 +718,7 @@ static void list_one_block(const int32_t* segs, int64_t n, bool aligned8, const 
     // (The Euclidean lists are written per segment: no output tiles.)
     const int64_t tiles = want_voxels && kKind != kListEuclid ? (capacity + kListTile - 1) / kListTile : 0;
     const int64_t tile_limit = tiles <= kOneBlockMaxTiles ? tiles : 0;
+    if (kKind == kListEuclid && n > 0) launch_euclid_counts(segs, n, aligned8, w, stream);
     if (aligned8)
         k_list_one_block<true, kKind><<<1, kCountBlock, 0, stream>>>(segs, n, w.counts, offsets, w.tile_seg,
                                                                       tile_limit, w.total, w.status, capacity,
