@@ -67,6 +67,22 @@ def test_list_extreme_int16():
     assert_list(segs)
 
 
+@pytest.mark.parametrize("n", [1000, 4096, 16383, 65536])
+def test_list_count_lane_splits(n):
+    """Each way the count kernel splits a segment's samples over lanes (64,
+    16, 4 and 1 lanes a segment, chosen by the number of segments): points,
+    short and long segments, and the longest int16 diagonal (N > 32767)."""
+    rng = np.random.default_rng(70 + n % 97)
+    p0 = rng.integers(-300, 300, (n, 3))
+    length = rng.integers(0, 40, n)
+    length[::97] = rng.integers(1000, 3000, length[::97].size)
+    d = rng.normal(size=(n, 3))
+    d /= np.abs(d).max(axis=1, keepdims=True)
+    segs = np.concatenate([p0, p0 + np.rint(length[:, None] * d).astype(np.int64)], 1).astype(np.int32)
+    segs[1] = [-32768, -32768, -32768, 32767, 32767, 32767]
+    assert_list(segs)
+
+
 def test_list_fixed_length_scaled():
     assert_list(workloads.fixed_length(n=30_000)["segs"])
 
