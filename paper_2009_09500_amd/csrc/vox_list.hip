@@ -510,12 +510,13 @@ void k_list_voxels(
     for (int64_t c = tail0 / 2 + threadIdx.x; c < bytes / 2; c += kListBlock) dst16[c] = src16[c];
 }
 
-// The samples k, k + kSampleLanes, ... of one segment under the Euclidean N
-// as taken by one of its lanes, stepped as the tile kernel steps (per axis:
+// The samples k, k + L, k + 2L, ... of one segment under the Euclidean N as
+// taken by one of its L = kLanes lanes, stepped as the tile kernel steps (per axis:
 // c' = coordinate ^ sign mask grows by dq + carry, f = r - 2N carries out of
 // 32 bits exactly when r + dr >= 2N).  A sample k >= 1 starts a new voxel
 // when some axis moved from k - 1 to k, that is when r_a(k) < 2a_a for some
 // a, i.e. f_a < 2a_a - 2N as signed values (|2N| < 2^31).
+template <int kLanes>
 struct ListSamples {
     uint32_t c[3], f[3], h[3], dq[3], dr[3], mk[3];
     uint32_t N, two_n;
@@ -542,7 +543,7 @@ struct ListSamples {
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 divmod_down(__umul24(k, two_a[ax]) + num0[ax], two_n, rcpd, q[ax], r[ax]);
-                divmod_down(kSampleLanes * two_a[ax], two_n, rcpd, dq[ax], dr[ax]);
+                divmod_down(kLanes * two_a[ax], two_n, rcpd, dq[ax], dr[ax]);
             }
         } else {
 #pragma unroll
@@ -550,7 +551,7 @@ struct ListSamples {
                 const uint64_t num = (uint64_t)k * two_a[ax] + num0[ax];
                 q[ax] = (uint32_t)(num / two_n);
                 r[ax] = (uint32_t)(num - (uint64_t)q[ax] * two_n);
-                const uint32_t s = kSampleLanes * two_a[ax];
+                const uint32_t s = kLanes * two_a[ax];
                 dq[ax] = s / two_n;
                 dr[ax] = s - dq[ax] * two_n;
             }
@@ -565,7 +566,7 @@ struct ListSamples {
         return moved;
     }
 
-    // Moves on by kSampleLanes samples; returns whether the sample starts a voxel.
+    // Moves on by kLanes samples; returns whether the sample starts a voxel.
     __device__ __forceinline__ bool next() {
         bool moved = false;
 #pragma unroll
@@ -582,21 +583,22 @@ struct ListSamples {
     __device__ __forceinline__ int32_t coord(int ax) const { return (int32_t)(c[ax] ^ mk[ax]); }
 };
 
-// Lists with the Euclidean N of eq. (1).  A wave takes four segments, 16
-// lanes each; a segment's lanes take its samples k = 0..N 16 at a time,
-// each stepping its own samples and deciding alone whether its sample starts
-// a new voxel (ListSamples); a ballot of those decisions places the kept
-// voxels, and consecutive lanes write consecutive voxels.
-template <bool kAligned8>
+// Lists with the Euclidean N of eq. (1).  A wave takes 64 / kLanes segments,
+// kLanes lanes each; a segment's lanes take its samples k = 0..N kLanes at a
+// time, each stepping its own samples and deciding alone whether its sample
+// starts a new voxel (ListSamples); a ballot of those decisions places the
+// kept voxels, and consecutive lanes write consecutive voxels.
+template <bool kAligned8, int kLanes>
 __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
     const int32_t* __restrict__ segs, int64_t n, const int64_t* __restrict__ offsets,
     int16_t* __restrict__ voxels, const int32_t* __restrict__ status) {
     if (*status != 0) return;
-    constexpr int kSlots = kWave / kSampleLanes;
+    static_assert(kLanes >= 2 && kLanes <= kWave && (kWave % kLanes) == 0, "lanes a segment");
+    constexpr int kSlots = kWave / kLanes;
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t sub = lane % kSampleLanes;
-    const uint32_t slot = lane / kSampleLanes;
-    const uint64_t slot_bits = ((1ull << kSampleLanes) - 1) << (kSampleLanes * slot);
+    const uint32_t sub = lane % kLanes;
+    const uint32_t slot = lane / kLanes;
+    const uint64_t slot_bits = (kLanes == kWave ? ~0ull : ((1ull << kLanes) - 1)) << (kLanes * slot);
     const int64_t step = (int64_t)gridDim.x * (kCountBlock / kWave) * kSlots;
     for (int64_t i0 = ((int64_t)blockIdx.x * (kCountBlock / kWave) + threadIdx.x / kWave) * kSlots; i0 < n;
          i0 += step) {
@@ -604,10 +606,10 @@ __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
         const bool valid = i < n;
         Seg g = {};
         if (valid) g = load_seg<kAligned8>(segs, i);
-        ListSamples s;
+        ListSamples<kLanes> s;
         bool moved = s.start(g, euclid_length(g), sub);
         int16_t* out = voxels + 3 * (valid ? offsets[i] : 0);
-        for (uint32_t c0 = 0; __ballot(valid && c0 <= s.N) != 0; c0 += kSampleLanes) {
+        for (uint32_t c0 = 0; __ballot(valid && c0 <= s.N) != 0; c0 += kLanes) {
             if (c0 != 0) moved = s.next();
             const bool keep = moved && valid && c0 + sub <= s.N;
             const uint64_t m = __ballot(keep) & slot_bits;
@@ -799,19 +801,43 @@ hipError_t launch_list_voxels32(const int32_t* segs, int64_t n, bool aligned8, c
     return hipGetLastError();
 }
 
+template <int kLanes>
+static void list_voxels_euclid(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
+                               const ListWork& w, int16_t* voxels, hipStream_t stream) {
+    constexpr int kSegsPerBlock = kCountBlock / kLanes;
+    int64_t blocks = (n + kSegsPerBlock - 1) / kSegsPerBlock;
+    if (blocks > 16384) blocks = 16384;
+    if (aligned8)
+        k_list_voxels_euclid<true, kLanes><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, offsets,
+                                                                                               voxels, w.status);
+    else
+        k_list_voxels_euclid<false, kLanes><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, offsets,
+                                                                                                voxels, w.status);
+}
+
+// Lanes a segment for the Euclidean list kernel: about one pass of the
+// lanes per segment (at least 8 lanes, a pass covering up to 8 voxels a
+// lane), and at least 65 536 lanes in all so that a few long segments still
+// spread over the chip.  The voxels per segment are taken from the caller's
+// capacity (the workspace's tile count), so an oversized buffer only costs
+// speed.
+static int euclid_list_lanes(int64_t n, int64_t capacity) {
+    const int64_t avg = capacity / n;
+    int lanes = 8;
+    while (lanes < kWave && ((int64_t)lanes * 8 < avg || n * lanes < 65536)) lanes *= 2;
+    return lanes;
+}
+
 hipError_t launch_list_voxels_euclid(const int32_t* segs, int64_t n, bool aligned8, const int64_t* offsets,
                                      const ListWork& w, int16_t* voxels, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    constexpr int kSegsPerBlock = kCountBlock / kSampleLanes;
-    int64_t blocks = (n + kSegsPerBlock - 1) / kSegsPerBlock;
-    if (blocks > 16384) blocks = 16384;
     KernelTimer timer("list_voxels_euclid", stream);
-    if (aligned8)
-        k_list_voxels_euclid<true><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, offsets, voxels,
-                                                                                       w.status);
-    else
-        k_list_voxels_euclid<false><<<dim3((unsigned)blocks), kCountBlock, 0, stream>>>(segs, n, offsets, voxels,
-                                                                                        w.status);
+    switch (euclid_list_lanes(n, w.ntiles * kListTile)) {
+        case 8: list_voxels_euclid<8>(segs, n, aligned8, offsets, w, voxels, stream); break;
+        case 16: list_voxels_euclid<16>(segs, n, aligned8, offsets, w, voxels, stream); break;
+        case 32: list_voxels_euclid<32>(segs, n, aligned8, offsets, w, voxels, stream); break;
+        default: list_voxels_euclid<64>(segs, n, aligned8, offsets, w, voxels, stream); break;
+    }
     return hipGetLastError();
 }
 
