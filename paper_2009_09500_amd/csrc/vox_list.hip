@@ -671,14 +671,19 @@ static void euclid_counts(const int32_t* segs, int64_t n, bool aligned8, uint32_
 
 // Euclidean counts into w.counts (n >= 1): one lane a segment from 65 536
 // segments on (a thread per segment already fills the chip), more lanes a
-// segment below that.
+// segment below that, and more again while a lane would walk more than
+// about 256 samples (voxels a segment taken from the caller's capacity, the
+// workspace's tile count; none when only the total is asked for).
 static void launch_euclid_counts(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w,
                                  hipStream_t stream) {
-    if (n >= 65536)
+    int lanes = n >= 65536 ? 1 : (n >= 16384 ? 4 : (n >= 4096 ? 16 : 64));
+    const int64_t avg = w.ntiles * kListTile / n;
+    while (lanes < kWave && (int64_t)lanes * 256 < avg) lanes *= 4;
+    if (lanes == 1)
         euclid_counts<1>(segs, n, aligned8, w.counts, stream);
-    else if (n >= 16384)
+    else if (lanes == 4)
         euclid_counts<4>(segs, n, aligned8, w.counts, stream);
-    else if (n >= 4096)
+    else if (lanes == 16)
         euclid_counts<16>(segs, n, aligned8, w.counts, stream);
     else
         euclid_counts<64>(segs, n, aligned8, w.counts, stream);
