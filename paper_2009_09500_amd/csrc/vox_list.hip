@@ -862,14 +862,14 @@ static void list_voxels_euclid(const int32_t* segs, int64_t n, bool aligned8, co
 }
 
 // Lanes a segment for the Euclidean list kernel: about one pass of the
-// lanes per segment (at least 8 lanes, a pass covering up to 8 voxels a
+// lanes per segment (at least 4 lanes, a pass covering up to 8 voxels a
 // lane), and at least 65 536 lanes in all so that a few long segments still
 // spread over the chip.  The voxels per segment are taken from the caller's
 // capacity (the workspace's tile count), so an oversized buffer only costs
 // speed.
 static int euclid_list_lanes(int64_t n, int64_t capacity) {
     const int64_t avg = capacity / n;
-    int lanes = 8;
+    int lanes = 4;
     while (lanes < kWave && ((int64_t)lanes * 8 < avg || n * lanes < 65536)) lanes *= 2;
     return lanes;
 }
@@ -879,6 +879,7 @@ hipError_t launch_list_voxels_euclid(const int32_t* segs, int64_t n, bool aligne
     if (n == 0) return hipSuccess;
     KernelTimer timer("list_voxels_euclid", stream);
     switch (euclid_list_lanes(n, w.ntiles * kListTile)) {
+        case 4: list_voxels_euclid<4>(segs, n, aligned8, offsets, w, voxels, stream); break;
         case 8: list_voxels_euclid<8>(segs, n, aligned8, offsets, w, voxels, stream); break;
         case 16: list_voxels_euclid<16>(segs, n, aligned8, offsets, w, voxels, stream); break;
         case 32: list_voxels_euclid<32>(segs, n, aligned8, offsets, w, voxels, stream); break;
