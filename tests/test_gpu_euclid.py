@@ -83,6 +83,17 @@ def test_list_count_lane_splits(n):
     assert_list(segs)
 
 
+@pytest.mark.parametrize("n,top", [(70_000, 6), (70_000, 20), (70_000, 50)])
+def test_list_short_segments(n, top):
+    """Short segments (lengths 0..top-1): the list kernel's 4 and 8 lanes a
+    segment, chosen from the voxels a segment."""
+    rng = np.random.default_rng(90 + top)
+    p0 = rng.integers(-1000, 1000, (n, 3))
+    d = rng.integers(-top + 1, top, (n, 3))
+    segs = np.concatenate([p0, p0 + d], 1).astype(np.int32)
+    assert_list(segs)
+
+
 def test_list_fixed_length_scaled():
     assert_list(workloads.fixed_length(n=30_000)["segs"])
 
