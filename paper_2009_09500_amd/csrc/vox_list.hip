@@ -20,6 +20,24 @@ namespace vox {
 
 // ------------------------------------------------------------------ count
 
+// The Euclidean length N = floor(|P1 - P0|) of eq. (1) for int16 lists:
+// |d|^2 < 3 * 2^32 is rounded to float and its square root, within about
+// 2^-23 relative, is within one of N; the integer corrections make it exact.
+// (A float root here instead of the double one of the grid kernels: the
+// Euclidean list kernels measured 3-10 % faster.)
+__device__ __forceinline__ uint32_t list_euclid_length(const Seg& s) {
+    uint64_t ss = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t d = (int64_t)s.p1[a] - (int64_t)s.p0[a];
+        ss += (uint64_t)(d * d);
+    }
+    uint64_t r = (uint64_t)__builtin_sqrtf((float)ss);
+    while (r * r > ss) --r;
+    while ((r + 1) * (r + 1) <= ss) ++r;
+    return (uint32_t)r;
+}
+
 // Voxels of each segment under the Euclidean N of eq. (1) (consecutive
 // duplicates removed): 1 + the steps k - 1 -> k, k = 1..N, that carry on
 // some axis (a carry of r_a + 2a past 2N is exactly a move of that axis,
@@ -44,7 +62,7 @@ __global__ __launch_bounds__(kCountBlock) void k_euclid_counts(const int32_t* __
         if (!in_int16(g)) {
             c = sub == 0 ? 1u : 0u;
         } else {
-            const uint32_t N = euclid_length(g);
+            const uint32_t N = list_euclid_length(g);
             const uint32_t S = (N + (uint32_t)kLanes) / (uint32_t)kLanes;
             const uint32_t k0 = sub * S;
             const uint32_t k1 = k0 + S < N + 1u ? k0 + S : N + 1u;
@@ -641,7 +659,7 @@ __global__ __launch_bounds__(kCountBlock) void k_list_voxels_euclid(
         Seg g = {};
         if (valid) g = load_seg<kAligned8>(segs, i);
         ListSamples<kLanes> s;
-        bool moved = s.start(g, euclid_length(g), sub);
+        bool moved = s.start(g, list_euclid_length(g), sub);
         int16_t* out = voxels + 3 * (valid ? offsets[i] : 0);
         for (uint32_t c0 = 0; __ballot(valid && c0 <= s.N) != 0; c0 += kLanes) {
             if (c0 != 0) moved = s.next();
