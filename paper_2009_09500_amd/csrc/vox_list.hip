@@ -763,9 +763,15 @@ static void launch_euclid_counts(const int32_t* segs, int64_t n, bool aligned8, 
 
 template <int kKind>
 static void list_count(const int32_t* segs, int64_t n, bool aligned8, const ListWork& w, hipStream_t stream) {
-    // One lane a segment: the count kernel walks the segments itself (one
-    // launch fewer: 1 M segments of 9-14 samples 0.018 -> 0.014 ms).
-    const int walk = kKind == kListEuclid && n > 0 && euclid_count_lanes(n, w) == 1 ? 1 : 0;
+    // One lane a segment and short segments (at most 32 voxels on average by
+    // the capacity, or none given): the count kernel walks the segments
+    // itself, one launch fewer (1 M segments of 9-14 samples 0.018 -> 0.014
+    // ms).  Longer ones keep k_euclid_counts, a thread per segment rather
+    // than per four (1 M segments of 64-110 samples: 0.041 against 0.044 ms).
+    const int walk = kKind == kListEuclid && n > 0 && euclid_count_lanes(n, w) == 1 &&
+                             w.ntiles * kListTile / n <= 32
+                         ? 1
+                         : 0;
     if (kKind == kListEuclid && n > 0 && !walk) launch_euclid_counts(segs, n, aligned8, w, stream);
     // n == 0: one block that writes a zero sum and no flag.
     dim3 grid(n == 0 ? 1u : (unsigned)w.nb);
